@@ -1,0 +1,439 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks one oracle function against something other than itself:
+numeric quadrature of the integral the closed form solves, printed values,
+closed-form special cases, or invariants (reciprocity, linearity,
+convergence).  A plausible slip in the oracle (sign, index, dropped term,
+transposed operand) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gauss4():
+    a = np.loadtxt(os.path.join(GOLD, "gauss4_eq18.txt"))
+    return a[:, 0] + 1j * a[:, 1], a[:, 2] + 1j * a[:, 3]
+
+
+def setup(orc, **kw):
+    base = dict(n_elements=1, fc=7.6e6, pitch=0.3e-3, width=0.27e-3, height=5e-3,
+                elev_focus=18e-3, bandwidth=0.77, c=1540.0, alpha_db=0.0, fs=30.4e6, nu=1)
+    base.update(kw)
+    return orc.Setup(**base)
+
+
+def trapz(y, x):
+    return np.sum((y[1:] + y[:-1]) * np.diff(x)) / 2
+
+
+# ----------------------------------------------------------------- Eq. 18
+def test_gaussian_coefficients_sum_is_real(orc):
+    """Conjugate pairs make the Gaussian sum real (Eq. 18); its value at
+    y' = 0 is sum A_g = 0.95 (close to the rectangle's 1)."""
+    A, B = gauss4()
+    assert abs(A.sum().imag) < 1e-15
+    assert abs(A.sum().real - 0.95) < 1e-12
+    u = np.linspace(-2, 2, 401)
+    fit = (A[None, :] * np.exp(-B[None, :] * u[:, None] ** 2)).sum(1)
+    assert np.abs(fit.imag).max() < 1e-12
+
+
+def test_delta_at_focus_is_k_independent(orc):
+    """Eq. (14) at r = R_f, y = 0: alpha_g = B_g/h^2, so Eq. (15) gives
+    delta = h sum A_g sqrt(pi/B_g), the same at every frequency."""
+    A, B = gauss4()
+    su = setup(orc)
+    expected = su.height * np.sum(A * np.sqrt(np.pi / B))
+    for f in [1e6, 5e6, 7.6e6, 14e6]:
+        k = 2 * np.pi * f / su.c
+        d = orc.delta(su, 0.0, su.elev_focus, k)
+        assert abs(d - expected) < 1e-12 * abs(expected)
+
+
+@pytest.mark.parametrize("f,y,r", [(7.6e6, 0.0, 5e-3), (7.6e6, 0.0, 40e-3), (3e6, 1e-3, 25e-3),
+                                   (12e6, -0.6e-3, 12e-3), (5e6, 2e-3, 60e-3)])
+def test_delta_equals_gaussian_integral_quadrature(orc, f, y, r):
+    """Closed form Eq. (15) == quadrature over R of Eq. (13)'s left-hand
+    side with the Gaussian sum of Eq. (12) in place of the rectangle."""
+    A, B = gauss4()
+    su = setup(orc)
+    k = 2 * np.pi * f / su.c
+    h, Rf = su.height, su.elev_focus
+    yp = np.linspace(-4 * h, 4 * h, 800_001)
+    rect = (A[None, :] * np.exp(-B[None, :] * (yp[:, None] / h) ** 2)).sum(1)
+    integrand = rect * np.exp(-1j * k * yp ** 2 / (2 * Rf)) * np.exp(1j * k * (y - yp) ** 2 / (2 * r))
+    quad = trapz(integrand, yp)
+    d = orc.delta(su, y, r, k)
+    assert abs(d - quad) < 1e-7 * abs(quad)
+
+
+def test_delta_approximates_rectangle_integral(orc):
+    """Loose sanity: the 4-Gaussian delta is an approximation of the exact
+    rectangle integral (Eq. 11); the paper calls the differences small."""
+    su = setup(orc)
+    k = 2 * np.pi * 7.6e6 / su.c
+    h, Rf = su.height, su.elev_focus
+    for r in [10e-3, 18e-3, 30e-3]:
+        yp = np.linspace(-h / 2, h / 2, 200_001)
+        exact = trapz(np.exp(-1j * k * yp ** 2 / (2 * Rf)) * np.exp(1j * k * yp ** 2 / (2 * r)), yp)
+        d = orc.delta(su, 0.0, r, k)
+        assert abs(d - exact) < 0.2 * abs(exact)
+
+
+# ----------------------------------------------------------------- Eq. 10, 39
+@pytest.mark.parametrize("theta_deg", [0.0, 5.0, 20.0, 45.0, 70.0, -30.0])
+def test_directivity_is_the_aperture_integral(orc, theta_deg):
+    """Rigid baffle D = sinc(kb sin(theta)) must equal (1/2b) times the
+    integral of Eq. (10), computed by quadrature; soft and finite-impedance
+    baffles multiply it by the obliquity factors of Eq. (39)."""
+    f, b = 7.6e6, 0.135e-3
+    k = 2 * np.pi * f / 1540.0
+    th = math.radians(theta_deg)
+    xp = np.linspace(-b, b, 20_001)
+    integ = trapz(np.exp(-1j * k * xp * math.sin(th)), xp) / (2 * b)
+    assert abs(integ.imag) < 1e-12
+    rigid = orc.directivity(setup(orc, baffle=1), math.sin(th), math.cos(th), k, b)
+    soft = orc.directivity(setup(orc, baffle=0), math.sin(th), math.cos(th), k, b)
+    zeta = orc.directivity(setup(orc, baffle=2, zeta=1.75), math.sin(th), math.cos(th), k, b)
+    assert abs(rigid - integ.real) < 1e-8
+    assert abs(soft - integ.real * math.cos(th)) < 1e-8
+    assert abs(zeta - integ.real * math.cos(th) / (math.cos(th) + 1.75)) < 1e-8
+
+
+# ----------------------------------------------------------------- Eqs. 25-27, 47-49
+@pytest.mark.parametrize("n_cycles", [1.0, 2.5])
+def test_pulse_spectrum_is_fourier_transform_of_windowed_sine(orc, n_cycles):
+    """Eq. (25) is (2/T) times the Fourier integral of sin(wc t) over the
+    window [-T/2, T/2], T = n_lambda / fc, with the e^{+i w t} kernel that
+    the time convention of Eq. (1) implies."""
+    su = setup(orc, n_cycles=n_cycles)
+    wc = 2 * np.pi * su.fc
+    T = n_cycles / su.fc
+    t = np.linspace(-T / 2, T / 2, 200_001)
+    for w in np.linspace(0.1, 2.5, 9) * wc:
+        ft = trapz(np.sin(wc * t) * np.exp(1j * w * t), t) * 2 / T
+        sp = orc.pulse_spectrum(su, w)
+        assert abs(sp - ft) < 1e-8
+
+
+def test_transducer_spectrum_bandwidth_and_floor(orc):
+    """Eq. (47): S_T = 1/2 at wc +- wb/2; Eq. (49): S_T(0) = S_T(2 wc) = 2^-126;
+    S_T(wc) = 1; and Eq. (27) equals Eq. (26) with sigma from Eq. (48)."""
+    for bw in [0.5, 0.65, 0.77, 1.2]:
+        su = setup(orc, bandwidth=bw)
+        wc = 2 * np.pi * su.fc
+        wb = bw * wc
+        assert abs(orc.transducer_spectrum(su, wc + wb / 2) - 0.5) < 1e-13
+        assert abs(orc.transducer_spectrum(su, wc - wb / 2) - 0.5) < 1e-13
+        assert abs(orc.transducer_spectrum(su, 0.0) / 2.0 ** -126 - 1) < 1e-10
+        assert abs(orc.transducer_spectrum(su, 2 * wc) / 2.0 ** -126 - 1) < 1e-10
+        assert orc.transducer_spectrum(su, wc) == 1.0
+        # Eq. (26) with p from Eq. (27) and sigma from Eq. (48)
+        p = math.log(126) / math.log(2 * wc / wb)
+        sigma = wb / (2 * wc) / math.log(2) ** (1 / p)
+        for w in np.linspace(0.05, 1.95, 17) * wc:
+            eq26 = math.exp(-(abs(w - wc) / (sigma * wc)) ** p)
+            assert abs(orc.transducer_spectrum(su, w) - eq26) < 1e-12 * max(eq26, 1e-300) + 1e-300
+
+
+# ----------------------------------------------------------------- Eq. 21, 24
+def test_nu_matches_paper_examples(orc):
+    rows = np.loadtxt(os.path.join(GOLD, "nu_examples.txt"))
+    for fc, pitch, kerf, bw, nu in rows:
+        assert orc.nu_eq21(pitch - kerf, fc, bw, 1540.0) == int(nu)
+
+
+@pytest.mark.parametrize("N,nu", [(32, 2), (7, 3), (128, 1)])
+def test_linear_centroids(orc, N, nu):
+    """Eq. (24): centroids are symmetric about 0, each element's
+    sub-elements average to its centre pitch*(e - (N+1)/2), and the
+    sub-element spacing inside an element is 2b/nu."""
+    su = setup(orc, n_elements=N, nu=nu)
+    g = orc.subelements(su)
+    xc = g["xc"].reshape(N, nu)
+    assert abs(xc.sum()) < 1e-15 * N
+    centres = su.pitch * (np.arange(1, N + 1) - (N + 1) / 2)
+    assert np.allclose(xc.mean(1), centres, atol=1e-15)
+    if nu > 1:
+        assert np.allclose(np.diff(xc, axis=1), su.width / nu, atol=1e-15)
+    assert np.all(g["zc"] == 0) and np.all(g["nz"] == 1) and np.all(g["tx"] == 1)
+
+
+def test_convex_centroids(orc):
+    """Convex reading: element centres lie on the circle of radius R about
+    (0, -R), neighbouring centres are one pitch apart (chord), normals point
+    away from the centre of curvature, sub-elements lie on the face."""
+    su = setup(orc, n_elements=16, nu=2, radius=60e-3, pitch=0.5e-3, width=0.45e-3)
+    g = orc.subelements(su)
+    R = su.radius
+    xc, zc = g["xc"].reshape(16, 2), g["zc"].reshape(16, 2)
+    cx, cz = xc.mean(1), zc.mean(1)
+    assert np.allclose(np.hypot(cx, cz + R), R, atol=1e-15)
+    assert np.allclose(np.hypot(np.diff(cx), np.diff(cz)), su.pitch, atol=1e-15)
+    nx, nz = g["nx"].reshape(16, 2)[:, 0], g["nz"].reshape(16, 2)[:, 0]
+    assert np.allclose(nx * cx + nz * (cz + R), R, atol=1e-15)
+    # sub-elements on the face: displacement from the centre is along the tangent
+    d = np.stack([xc[:, 1] - xc[:, 0], zc[:, 1] - zc[:, 0]], -1)
+    assert np.allclose(d[:, 0] * nx + d[:, 1] * nz, 0, atol=1e-15)
+    assert np.allclose(np.hypot(d[:, 0], d[:, 1]), su.width / 2, atol=1e-15)
+
+
+# ----------------------------------------------------------------- Eqs. 1, 17-20, 29-34, 40
+def test_single_element_directivity(orc):
+    """One element, one sub-element, y = 0, points on a circle of radius r:
+    delta depends only on r, so G(theta)/G(0) is the directivity, which
+    must equal the aperture integral of Eq. (10) times cos(theta) (soft)."""
+    su = setup(orc)
+    r = 20e-3
+    w = 2 * np.pi * 7.6e6
+    k = w / su.c
+    b = su.width / 2
+    g0 = orc.green(su, 0, 0.0, 0.0, r, w)
+    xp = np.linspace(-b, b, 20_001)
+    for th in np.radians([3, 10, 25, 40, 60]):
+        g = orc.green(su, 0, r * math.sin(th), 0.0, r * math.cos(th), w)
+        integ = trapz(np.exp(-1j * k * xp * math.sin(th)), xp).real / (2 * b)
+        assert abs(g / g0 - integ * math.cos(th)) < 1e-8
+
+
+def test_on_axis_echo_closed_form(orc):
+    """One element (nu = 1), scatterer on axis at z0 = R_f, no attenuation:
+    X_j = S_P S_T R exp(2 i k z0) (h sum A sqrt(pi/B))^2 / z0^2 (Eqs. 17-20,
+    31-34 at theta = 0, r = R_f)."""
+    A, B = gauss4()
+    su = setup(orc)
+    z0 = su.elev_focus
+    d0 = su.height * np.sum(A * np.sqrt(np.pi / B))
+    delays, apod = np.zeros((1, 1)), np.ones((1, 1))
+    nfft = 2048
+    bins = np.arange(100, 700, 37)
+    X = orc.spectrum(su, nfft, delays, apod, [0.0], [0.0], [z0], [1.7], bins)[0, 0]
+    for j, xj in zip(bins, X):
+        w = 2 * np.pi * j * su.fs / nfft
+        k = w / su.c
+        P = orc.pulse_spectrum(su, w) * orc.transducer_spectrum(su, w)
+        expected = P * 1.7 * np.exp(2j * k * z0) * d0 ** 2 / z0 ** 2
+        assert abs(xj - expected) < 1e-10 * abs(expected) + 1e-300
+
+
+def test_on_axis_echo_arrives_at_two_way_time(orc):
+    """The RF envelope of an on-axis point echo peaks at t = 2 z0 / c."""
+    from scipy.signal import hilbert
+    su = setup(orc)
+    z0 = su.elev_focus
+    g = orc.grid(su, np.zeros((1, 1)), [0.0], [0.0], [z0])
+    rf = orc.rf(su, g, np.zeros((1, 1)), np.ones((1, 1)), [0.0], [0.0], [z0], [1.0])[0, 0]
+    env = np.abs(hilbert(rf))
+    assert abs(np.argmax(env) - 2 * z0 / su.c * su.fs) <= 1.0
+
+
+def test_attenuation_two_way_loss(orc):
+    """Eq. (40): with alpha dB/cm/MHz, the two-way echo of an on-axis
+    scatterer at z0 loses alpha * f[MHz] * 2 z0[cm] dB (to the 8.69 ~
+    20/ln 10 rounding the paper uses)."""
+    z0 = 30e-3
+    for alpha in [0.3, 0.5, 1.0]:
+        su0, su1 = setup(orc), setup(orc, alpha_db=alpha)
+        bins = np.array([200, 400, 600])
+        X0 = orc.spectrum(su0, 2048, np.zeros((1, 1)), np.ones((1, 1)), [0.0], [0.0], [z0], [1.0], bins)
+        X1 = orc.spectrum(su1, 2048, np.zeros((1, 1)), np.ones((1, 1)), [0.0], [0.0], [z0], [1.0], bins)
+        for j, a, b in zip(bins, X0[0, 0], X1[0, 0]):
+            f_mhz = j * su0.fs / 2048 / 1e6
+            loss_db = -20 * math.log10(abs(b / a))
+            assert abs(loss_db - alpha * f_mhz * 2 * z0 * 100) < 1e-3 * loss_db
+            assert abs(np.angle(b / a)) < 1e-12   # attenuation is amplitude-only
+
+
+def _tiny_phantom(n, seed=3, y=False):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-3e-3, 3e-3, n)
+    z = rng.uniform(6e-3, 20e-3, n)
+    yy = rng.uniform(-1e-3, 1e-3, n) if y else np.zeros(n)
+    R = rng.standard_normal(n)
+    return x, yy, z, R
+
+
+def test_reciprocity_full_synthetic_aperture(orc):
+    """Transmit on element i, receive on j == transmit on j, receive on i
+    (acoustic reciprocity used in Eq. 30)."""
+    N = 6
+    su = setup(orc, n_elements=N, nu=2, alpha_db=0.5)
+    x, y, z, R = _tiny_phantom(7, y=True)
+    delays, apod = np.zeros((N, N)), np.eye(N)
+    bins = np.array([150, 333, 511])
+    X = orc.spectrum(su, 1024, delays, apod, x, y, z, R, bins)   # [t, e, b]
+    for b in range(bins.size):
+        M = X[:, :, b]
+        assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+
+
+def test_linearity_in_reflectivity(orc):
+    su = setup(orc, n_elements=4, nu=2)
+    x, y, z, R1 = _tiny_phantom(9)
+    R2 = np.random.default_rng(5).standard_normal(9)
+    delays = np.array([[0.0, 1e-7, 2e-7, 3e-7]])
+    apod = np.array([[1.0, 0.5, 0.7, 1.2]])
+    g = orc.grid(su, delays, x, y, z)
+    f = lambda R: orc.rf(su, g, delays, apod, x, y, z, R)
+    a, b = 0.7, -1.9
+    lhs = f(a * R1 + b * R2)
+    rhs = a * f(R1) + b * f(R2)
+    assert np.abs(lhs - rhs).max() < 1e-11 * np.abs(lhs).max()
+
+
+def test_transmit_sum_matches_single_element_superposition(orc):
+    """Eq. (22)/(29): a transmit of several elements is the sum of the
+    single-element transmits with their delays and weights (linearity of
+    the transmit field), checked on the received spectra."""
+    N = 4
+    su = setup(orc, n_elements=N, nu=2)
+    x, y, z, R = _tiny_phantom(5)
+    dl = np.array([[0.0, 2e-8, 5e-8, 1e-7]])
+    ap = np.array([[1.0, 0.3, -0.8, 0.6]])
+    bins = np.array([200, 300])
+    full = orc.spectrum(su, 1024, dl, ap, x, y, z, R, bins)[0]
+    parts = sum(orc.spectrum(su, 1024, dl, np.eye(N)[i:i + 1] * ap, x, y, z, R, bins)[0]
+                for i in range(N))
+    assert np.abs(full - parts).max() < 1e-12 * np.abs(full).max()
+    # a delay tau multiplies single-element spectra by exp(i w tau) (Eq. 20)
+    one = orc.spectrum(su, 1024, np.zeros((1, N)), np.eye(N)[2:3], x, y, z, R, bins)[0]
+    dly = orc.spectrum(su, 1024, np.full((1, N), 7e-8), np.eye(N)[2:3], x, y, z, R, bins)[0]
+    w = 2 * np.pi * bins * su.fs / 1024
+    assert np.allclose(dly, one * np.exp(1j * w * 7e-8)[None, :], rtol=1e-12, atol=0)
+
+
+def test_subelement_convergence(orc):
+    """Splitting the element into nu sub-elements (Eqs. 21-24): the one-way
+    field divided by nu converges as nu grows (second order, as a midpoint
+    rule), and its limit agrees loosely with the Rayleigh-Sommerfeld
+    integral of Eq. (5) with the focusing velocity of Eq. (4)."""
+    b, h, Rf = 0.5e-3, 5e-3, 18e-3          # a wide element: 1 mm
+    w = 2 * np.pi * 7.6e6
+    k = w / 1540.0
+    pts = [(0.0, 0.0, 6e-3), (0.7e-3, 0.0, 8e-3), (0.0, 0.0, 12e-3), (1e-3, 0.0, 20e-3)]
+    vals = []
+    nus = [1, 2, 4, 8, 16, 32, 64]
+    for nu in nus:
+        su = setup(orc, width=2 * b, nu=nu, baffle=1)
+        X, Y, Z = zip(*pts)
+        F = orc.field(su, np.zeros(1), np.ones(1), [w], X, Y, Z)[:, 0]
+        vals.append(F / nu)
+    vals = np.array(vals)
+    diffs = np.abs(np.diff(vals, axis=0))          # [len(nus)-1, pts]
+    assert np.all(diffs[1:] < diffs[:-1])         # monotone
+    assert np.all(diffs[-1] < 0.35 * diffs[-2])   # ~ 1/4 per doubling
+    limit = vals[-1]
+    # Rayleigh-Sommerfeld (rigid baffle) with the elevation-focusing velocity,
+    # normalised like the model: (1/2b) int int v(y') e^{ikr'}/r' dx' dy'.
+    xp = np.linspace(-b, b, 801)
+    yp = np.linspace(-h / 2, h / 2, 2001)
+    XX, YY = np.meshgrid(xp, yp, indexing="ij")
+    for (px, py, pz), lim in zip(pts, limit):
+        rp = np.sqrt((px - XX) ** 2 + (py - YY) ** 2 + pz ** 2)
+        integ = np.exp(-1j * k * YY ** 2 / (2 * Rf)) * np.exp(1j * k * rp) / rp
+        rs = trapz(np.array([trapz(row, yp) for row in integ]), xp) / (2 * b)
+        assert abs(lim - rs) < 0.2 * abs(rs)
+
+
+# ----------------------------------------------------------------- inverse DFT
+def test_inverse_dft_conventions(orc):
+    """One bin X_j = 1 gives rf[q] = cos(2 pi j q / nfft) (Eq. 1 with the
+    e^{-i w t} kernel); X_j = i gives +sin.  The residual spectrum is the
+    exact adjoint of the inverse DFT."""
+    nfft, n_t = 96, 80
+    q = np.arange(n_t)
+    for j in [1, 5, 47]:
+        rf = orc.rf_from_spectrum(np.array([[1.0 + 0j]]), [j], nfft, n_t)[0]
+        assert np.allclose(rf, np.cos(2 * np.pi * j * q / nfft), atol=1e-13)
+        rf = orc.rf_from_spectrum(np.array([[1j]]), [j], nfft, n_t)[0]
+        assert np.allclose(rf, np.sin(2 * np.pi * j * q / nfft), atol=1e-13)
+    rng = np.random.default_rng(0)
+    bins = np.array([3, 4, 9, 20, 33])
+    X = rng.standard_normal((3, 5)) + 1j * rng.standard_normal((3, 5))
+    rho = rng.standard_normal((3, n_t))
+    lhs = np.sum(orc.rf_from_spectrum(X, bins, nfft, n_t) * rho)
+    rhs = np.real(np.sum(X * orc.residual_spectrum(rho, bins, nfft)))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# ----------------------------------------------------------------- grid reading
+def test_grid_rule_properties(orc):
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200")
+    p = w["probe"]
+    su = orc.Setup(**{k: p[k] for k in ["n_elements", "fc", "pitch", "width", "height",
+                                         "elev_focus", "bandwidth", "radius", "baffle", "zeta"]},
+                   c=1540.0, fs=4 * p["fc"])
+    ph = w["phantoms"][0]
+    g = orc.grid(su, w["delays"], ph["x"], ph["y"], ph["z"])
+    n = g["nfft"]
+    assert n % 2 == 0
+    m = n
+    for f in (2, 3, 5):
+        while m % f == 0:
+            m //= f
+    assert m == 1
+    # evaluated band: every bin outside has |S_P S_T| < eps * max
+    def weight(j):
+        wj = 2 * np.pi * j * su.fs / n
+        return abs(orc.pulse_spectrum(su, wj)) * orc.transducer_spectrum(su, wj)
+    cand = [j for j in range(1, n // 2) if j * su.fs / n < 2 * su.fc]
+    wts = np.array([weight(j) for j in cand])
+    lo, hi = g["j_lo"], g["j_lo"] + g["n_bins"] - 1
+    outside = [wt for j, wt in zip(cand, wts) if j < lo or j > hi]
+    assert max(outside) < 1e-7 * wts.max()
+    assert weight(lo) >= 1e-7 * wts.max() and weight(hi) >= 1e-7 * wts.max()
+
+
+def test_band_threshold_is_negligible(orc):
+    """Dropping bins below eps = 1e-7 of the spectral peak changes RF by
+    far less than the 1e-4 parity budget."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.1)
+    p = w["probe"]
+    su = orc.Setup(**{k: p[k] for k in ["n_elements", "fc", "pitch", "width", "height",
+                                         "elev_focus", "bandwidth"]}, c=1540.0, fs=4 * p["fc"])
+    ph = w["phantoms"][0]
+    g1 = orc.grid(su, w["delays"], ph["x"], ph["y"], ph["z"], eps=1e-7)
+    g0 = orc.grid(su, w["delays"], ph["x"], ph["y"], ph["z"], eps=0.0)
+    args = (w["delays"], w["apod"], ph["x"], ph["y"], ph["z"], ph["R"])
+    a, b = orc.rf(su, g1, *args), orc.rf(su, g0, *args)
+    assert g0["n_bins"] > g1["n_bins"]
+    assert np.linalg.norm(a - b) < 1e-6 * np.linalg.norm(b)
+
+
+# ----------------------------------------------------------------- RMS field
+def test_pfield_riemann_sum(orc):
+    """Eqs. (41)-(42): for one element on axis at z0 = R_f (alpha = 0),
+    |P|^2 = |S_P|^2 S_T |delta_0 / z0|^2, so P_RMS^2 approaches the
+    integral of |S_P|^2 S_T over [0, 2 wc] times |delta_0/z0|^2."""
+    from scipy.integrate import quad
+    A, B = gauss4()
+    su = setup(orc)
+    z0 = su.elev_focus
+    d0 = su.height * np.sum(A * np.sqrt(np.pi / B))
+    wc = 2 * np.pi * su.fc
+    integ, _ = quad(lambda w: abs(orc.pulse_spectrum(su, w)) ** 2 * orc.transducer_spectrum(su, w),
+                    0, 2 * wc, limit=400)
+    expected = math.sqrt(integ) * abs(d0) / z0
+    for nf in [64, 256]:
+        prms = orc.pfield(su, np.zeros(1), np.ones(1), nf, [0.0], [0.0], [z0])[0]
+        assert abs(prms - expected) < 2e-3 * expected
+
+
+def test_pfield_frequency_step_rule(orc):
+    """Section VII: dw = 2 pi / max(r/c + delay) over the region and the
+    elements; N_f = ceil(2 wc / dw)."""
+    su = setup(orc, n_elements=3, nu=1)
+    X, Y, Z = [0.0, 2e-3], [0.0, 0.0], [10e-3, 30e-3]
+    dl = np.array([0.0, 1e-7, 3e-7])
+    nf = orc.pfield_nf(su, dl, X, Y, Z)
+    # brute force over points and elements
+    xe = su.pitch * (np.arange(1, 4) - 2.0)
+    tmax = max(math.hypot(x - xe[e], z) / su.c + dl[e] for x, z in zip(X, Z) for e in range(3))
+    assert nf == math.ceil(2 * 2 * np.pi * su.fc / (2 * np.pi / tmax))
