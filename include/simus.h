@@ -1,0 +1,205 @@
+/*
+ * simus.h -- C ABI of libsimus, an MI355X (gfx950) implementation of the
+ * SIMUS radio-frequency synthesis of D. Garcia, "SIMUS: an open-source
+ * simulator for medical ultrasound imaging. Part I: theory & examples".
+ *
+ * The library computes, for every transmit t, receive element e and
+ * frequency bin j, the received element spectrum
+ *
+ *   X[t][e][j] = S_P(w_j) S_T(w_j) sum_s R_s a[s][t](w_j) B[e][s](w_j)
+ *
+ * with a = sum over all nu*N sub-elements n of W_{t,e(n)} exp(i w tau_{t,e(n)})
+ * G_{n,s} (Eq. 29), B = sum of G over the nu sub-elements of element e
+ * (Eqs. 32-33), the sub-element Green's term
+ *
+ *   G_{n,s}(w) = exp(i (k + i k_a) r) / r * D(theta, k) * delta(y, r, k)
+ *
+ * (Eqs. 17-20 with the sinc directivity of Eq. 10 and the baffle factors of
+ * Eq. 39, the four-Gaussian elevation term of Eqs. 12-18 and the
+ * attenuation of Eq. 40), the pulse spectrum of Eq. 25 and the transducer
+ * spectrum of Eq. 27 (Eqs. 28 and 34), and then the RF signals by the
+ * inverse transform of Eq. 1:
+ *
+ *   rf[t][e][q] = Re sum_j X[t][e][j] exp(-2 pi i j q / nfft).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - SI units (m, s, Hz); attenuation in dB/cm/MHz.
+ * - Scatterers are structure-of-arrays float32: x, y, z, refl.  y may be
+ *   NULL, meaning y = 0 for every scatterer (the azimuth plane).
+ * - Pointers documented "device" must point to memory of the current HIP
+ *   device; "host" pointers are read before the call returns.
+ * - The caller owns all buffers.  The library owns a workspace cached per
+ *   (device, stream), released by simus_release_workspace().
+ * - All device work is enqueued on `hip_stream` (a hipStream_t; NULL = the
+ *   null stream).  No entry point synchronises the stream; outputs are
+ *   ready when the stream's work completes.  Calls that share a stream are
+ *   ordered; calls on different streams use different workspaces.
+ * - Return value: SIMUS_OK (0) or a negative error code.  Arguments are
+ *   validated on the host before any HIP call, so invalid arguments never
+ *   reach the GPU.  simus_last_error() gives a message (thread-local).
+ * - Probe: linear when radius == 0, Eq. (24) sub-element centroids; convex
+ *   when radius > 0 (apex at the origin, centre of curvature at (0, -R),
+ *   flat elements of chord pitch, split along their face).  A sub-element
+ *   does not radiate behind its face (G = 0 where the local depth <= 0).
+ */
+#ifndef SIMUS_H
+#define SIMUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIMUS_VERSION 100
+
+#define SIMUS_OK 0
+#define SIMUS_EINVAL (-1)   /* invalid argument (NULL pointer, bad size, bad parameter) */
+#define SIMUS_EDOMAIN (-2)  /* scatterer outside the model's domain (host checks) */
+#define SIMUS_ENOMEM (-3)   /* device or pinned host allocation failed */
+#define SIMUS_EHIP (-4)     /* a HIP runtime call failed */
+
+typedef enum {
+    SIMUS_BAFFLE_SOFT = 0,   /* D = sinc(k b sin t) cos t   (Eq. 39, default) */
+    SIMUS_BAFFLE_RIGID = 1,  /* D = sinc(k b sin t)                           */
+    SIMUS_BAFFLE_ZETA = 2    /* D = sinc(k b sin t) cos t / (cos t + zeta)    */
+} simus_baffle;
+
+/* Transducer array (Fig. 2; Sections II-III, VI). */
+typedef struct {
+    int32_t n_elements;   /* N >= 1 */
+    int32_t baffle;       /* simus_baffle */
+    double fc;            /* centre frequency [Hz] > 0 */
+    double pitch;         /* element pitch [m] > 0 */
+    double width;         /* element width 2b [m], 0 < width <= pitch */
+    double height;        /* element height h [m] > 0 */
+    double elev_focus;    /* elevation focus R_f [m] > 0, may be +INFINITY */
+    double bandwidth;     /* pulse-echo fractional -6 dB bandwidth, 0 < bw < 2 */
+    double radius;        /* 0: linear array; > 0: convex radius [m] */
+    double zeta;          /* baffle impedance ratio (SIMUS_BAFFLE_ZETA), >= 0 */
+} simus_probe;
+
+/* Medium (Section VI-B). */
+typedef struct {
+    double c;             /* speed of sound [m/s] > 0 */
+    double alpha_db;      /* amplitude attenuation [dB/cm/MHz] >= 0 (Eq. 40) */
+} simus_medium;
+
+/* Sampling and model options. */
+typedef struct {
+    double fs;            /* RF sampling frequency [Hz], fs > 2 fc */
+    double n_cycles;      /* pulse length n_lambda in wavelengths (Eq. 25) > 0 */
+    double spectral_eps;  /* evaluated band: contiguous bins spanning every bin with
+                             |S_P S_T| >= eps * max (eps in [0, 1)); 1e-7 typical */
+    int32_t nu;           /* sub-elements per element; 0 = Eq. (21) with the
+                             shortest wavelength at the upper -6 dB edge */
+    int32_t nfft;         /* transform length (even).  simus_rf_grid: 0 = auto;
+                             every other entry point requires nfft > 0 */
+    int32_t n_t;          /* RF samples returned per channel; 0 = nfft; <= nfft */
+    int32_t flags;        /* SIMUS_FLAG_* */
+    int32_t tile_bins;    /* 0 = autotuned; else bins per work item (1..32) */
+    int32_t tile_scat;    /* 0 = autotuned; else scatterers per work item */
+} simus_options;
+
+#define SIMUS_FLAG_NO_MFMA       1   /* never use the MFMA multi-transmit contraction */
+#define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis */
+#define SIMUS_FLAG_NO_DELTA_TABLE 4  /* evaluate the elevation term directly (no table) */
+
+/* Frequency grid of one call. */
+typedef struct {
+    int32_t nfft;         /* transform length */
+    int32_t n_t;          /* RF samples per channel */
+    int32_t j_lo;         /* first evaluated bin (absolute index, w_j = 2 pi j fs / nfft) */
+    int32_t n_bins;       /* number of evaluated bins j_lo .. j_lo + n_bins - 1 */
+    int32_t nu;           /* sub-elements per element */
+    int32_t reserved;
+    double df;            /* bin spacing fs / nfft [Hz] */
+} simus_grid;
+
+int simus_version(void);
+const char* simus_last_error(void);
+
+/* Frequency grid for a call (host only, no GPU).
+ *   t_max = 2 r_max / c + max delay + 10 / fc, r_max = largest distance from a
+ *   sub-element centroid to a scatterer; nfft = options->nfft if > 0, else
+ *   the smallest even 2^a 3^b 5^c >= max(fs t_max, n_t).  Bins j with
+ *   1 <= j < nfft/2 and f_j < 2 fc are candidates (S_T(2 wc) = 2^-126,
+ *   Eq. 49); the evaluated band is per spectral_eps above.
+ * delays: host [n_tx][N] seconds (>= 0; positive = fires later, Eq. 20).
+ * x, y, z: host [n_scat] (y may be NULL).  n_scat >= 0.
+ * Errors: EINVAL for bad parameters; EDOMAIN if a scatterer lies at depth
+ * <= 0 in front of a linear array or within 1e-9 m of a sub-element. */
+int simus_rf_grid(const simus_probe* probe, const simus_medium* medium,
+                  const simus_options* options, int32_t n_tx, const double* delays,
+                  int64_t n_scat, const float* x, const float* y, const float* z,
+                  simus_grid* out);
+
+/* Element spectra X (Eqs. 22, 29-34) on the evaluated band.
+ * delays, apod: host [n_tx][N] (transmit delays [s] and apodisation W).
+ * scat_offsets: host [n_phantoms + 1], non-decreasing, scat_offsets[0] = 0;
+ *   phantom p owns scatterers scat_offsets[p] .. scat_offsets[p+1]-1.
+ * x, y, z, refl: device [scat_offsets[n_phantoms]] float32 (y may be NULL).
+ * spec: device float32 [n_phantoms][n_tx][N][n_bins][2] (re, im).
+ * Requires options->nfft > 0 (from simus_rf_grid). */
+int simus_rf_spectrum(const simus_probe* probe, const simus_medium* medium,
+                      const simus_options* options, int32_t n_tx,
+                      const double* delays, const float* apod,
+                      int32_t n_phantoms, const int64_t* scat_offsets,
+                      const float* x, const float* y, const float* z, const float* refl,
+                      float* spec, void* hip_stream);
+
+/* RF signals: the spectra above followed by the inverse transform of Eq. (1).
+ * rf: device float32 [n_phantoms][n_tx][N][n_t]. */
+int simus_rf(const simus_probe* probe, const simus_medium* medium,
+             const simus_options* options, int32_t n_tx,
+             const double* delays, const float* apod,
+             int32_t n_phantoms, const int64_t* scat_offsets,
+             const float* x, const float* y, const float* z, const float* refl,
+             float* rf, void* hip_stream);
+
+/* Inverse transform alone: rf[c][q] = Re sum_b spec[c][b] exp(-2 pi i (j_lo + b) q / nfft)
+ * for q < n_t.  spec: device [n_chan][n_bins][2]; rf: device [n_chan][n_t]. */
+int simus_spectrum_to_rf(int32_t nfft, int32_t n_t, int32_t j_lo, int32_t n_bins,
+                         int64_t n_chan, const float* spec, float* rf, void* hip_stream);
+
+/* Adjoint of simus_rf: given drf = dL/drf (device, same layout as rf), the
+ * gradients dL/drefl, dL/dx, dL/dy, dL/dz (device [n_scat] each; any may be
+ * NULL to skip; dy requires y != NULL or is returned for y = 0).  The
+ * Green's terms are recomputed per frequency bin, nothing is stored from the
+ * forward pass.  Same grid rules as simus_rf (pass the forward's nfft). */
+int simus_rf_backward(const simus_probe* probe, const simus_medium* medium,
+                      const simus_options* options, int32_t n_tx,
+                      const double* delays, const float* apod,
+                      int32_t n_phantoms, const int64_t* scat_offsets,
+                      const float* x, const float* y, const float* z, const float* refl,
+                      const float* drf, float* drefl, float* dx, float* dy, float* dz,
+                      void* hip_stream);
+
+/* Number of frequency intervals N_f of the RMS field (Section VII, host only):
+ * dw = 2 pi / max over points and sub-elements of (r / c + delay),
+ * N_f = ceil(2 wc / dw).  delays: host [N]; X, Y, Z host [n_pts] (Y may be NULL). */
+int simus_pfield_nf(const simus_probe* probe, const simus_medium* medium,
+                    const simus_options* options, const double* delays,
+                    int64_t n_pts, const float* X, const float* Y, const float* Z,
+                    int32_t* n_f);
+
+/* RMS pressure field (Eqs. 22, 28, 41, 42): P_RMS(X) = sqrt(dw sum_{j=0}^{N_f}
+ * |P(X, w_j)|^2), w_j = 2 wc j / N_f, dw = 2 wc / N_f, P = S_P sqrt(S_T) *
+ * sum_n W e^{i w tau} G_n.  delays, apod: host [N]; X, Y, Z: device [n_pts]
+ * (Y may be NULL); p_rms: device [n_pts].  n_f >= 1. */
+int simus_pfield(const simus_probe* probe, const simus_medium* medium,
+                 const simus_options* options, int32_t n_f,
+                 const double* delays, const float* apod,
+                 int64_t n_pts, const float* X, const float* Y, const float* Z,
+                 float* p_rms, void* hip_stream);
+
+/* Frees every cached workspace (all devices, all streams).  Must not run
+ * concurrently with other calls. */
+void simus_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIMUS_H */

@@ -1,0 +1,238 @@
+"""ctypes binding of libsimus (include/simus.h): argument marshalling only.
+
+Every computation runs in the HIP library; if the library is missing the
+functions raise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsimus.so")
+
+SIMUS_OK = 0
+ERRORS = {-1: "SIMUS_EINVAL", -2: "SIMUS_EDOMAIN", -3: "SIMUS_ENOMEM", -4: "SIMUS_EHIP"}
+FLAG_NO_MFMA = 1
+FLAG_PERSISTENT = 2
+FLAG_NO_DELTA_TABLE = 4
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",
+           "simus_spectrum_to_rf", "simus_rf_backward", "simus_pfield_nf", "simus_pfield",
+           "simus_release_workspace"]
+
+
+class SimusError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Probe(C.Structure):
+    _fields_ = [("n_elements", C.c_int32), ("baffle", C.c_int32), ("fc", C.c_double),
+                ("pitch", C.c_double), ("width", C.c_double), ("height", C.c_double),
+                ("elev_focus", C.c_double), ("bandwidth", C.c_double), ("radius", C.c_double),
+                ("zeta", C.c_double)]
+
+
+class Medium(C.Structure):
+    _fields_ = [("c", C.c_double), ("alpha_db", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("fs", C.c_double), ("n_cycles", C.c_double), ("spectral_eps", C.c_double),
+                ("nu", C.c_int32), ("nfft", C.c_int32), ("n_t", C.c_int32), ("flags", C.c_int32),
+                ("tile_bins", C.c_int32), ("tile_scat", C.c_int32)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nfft", C.c_int32), ("n_t", C.c_int32), ("j_lo", C.c_int32), ("n_bins", C.c_int32),
+                ("nu", C.c_int32), ("reserved", C.c_int32), ("df", C.c_double)]
+
+    def as_dict(self):
+        return dict(nfft=self.nfft, n_t=self.n_t, j_lo=self.j_lo, n_bins=self.n_bins, nu=self.nu,
+                    df=self.df)
+
+
+_lib = None
+
+
+def lib():
+    """Loads libsimus.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SimusError(-4, f"{LIB_PATH} is missing: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        i32, i64, vp = C.c_int32, C.c_int64, C.c_void_p
+        pd, pf, pi64, pi32 = P(C.c_double), P(C.c_float), P(C.c_int64), P(C.c_int32)
+        pP, pM, pO, pG = P(Probe), P(Medium), P(Options), P(Grid)
+        sig = {
+            "simus_version": (C.c_int, []),
+            "simus_last_error": (C.c_char_p, []),
+            "simus_rf_grid": (C.c_int, [pP, pM, pO, i32, pd, i64, pf, pf, pf, pG]),
+            "simus_rf_spectrum": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp, vp]),
+            "simus_rf": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp, vp]),
+            "simus_spectrum_to_rf": (C.c_int, [i32, i32, i32, i32, i64, vp, vp, vp]),
+            "simus_rf_backward": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp,
+                                            vp, vp, vp, vp, vp]),
+            "simus_pfield_nf": (C.c_int, [pP, pM, pO, pd, i64, pf, pf, pf, pi32]),
+            "simus_pfield": (C.c_int, [pP, pM, pO, i32, pd, pf, i64, vp, vp, vp, vp, vp]),
+            "simus_release_workspace": (None, []),
+        }
+        for name, (res, args) in sig.items():
+            if not hasattr(L, name):
+                continue
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != SIMUS_OK:
+        raise SimusError(code, lib().simus_last_error().decode())
+
+
+# ------------------------------------------------------------------ structs
+def make_probe(p: dict) -> Probe:
+    return Probe(int(p["n_elements"]), int(p.get("baffle", 0)), p["fc"], p["pitch"], p["width"],
+                 p["height"], p.get("elev_focus", math.inf), p["bandwidth"], p.get("radius", 0.0),
+                 p.get("zeta", 1.75))
+
+
+def make_medium(m: dict) -> Medium:
+    return Medium(m.get("c", 1540.0), m.get("alpha_db", 0.0))
+
+
+def make_options(o: dict, **over) -> Options:
+    d = dict(o)
+    d.update(over)
+    return Options(d["fs"], d.get("n_cycles", 1.0), d.get("spectral_eps", 1e-7), int(d.get("nu", 0)),
+                   int(d.get("nfft", 0)), int(d.get("n_t", 0)), int(d.get("flags", 0)),
+                   int(d.get("tile_bins", 0)), int(d.get("tile_scat", 0)))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _dev(t):
+    """Device pointer of a CUDA/HIP tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise SimusError(-1, "device tensor expected")
+    if not t.is_contiguous():
+        raise SimusError(-1, "contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ host-only
+def rf_grid(probe: dict, medium: dict, options: dict, delays, x, y, z) -> dict:
+    d = _f64(delays)
+    n_tx = d.size // max(int(probe["n_elements"]), 1)
+    xs, zs = _f32(x), _f32(z)
+    ys = None if y is None else _f32(y)
+    g = Grid()
+    check(lib().simus_rf_grid(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                              C.byref(make_options(options)), n_tx, _p(d, C.c_double), xs.size,
+                              _p(xs, C.c_float), None if ys is None else _p(ys, C.c_float),
+                              _p(zs, C.c_float), C.byref(g)))
+    return g.as_dict()
+
+
+def pfield_nf(probe: dict, medium: dict, options: dict, delays, X, Y, Z) -> int:
+    d = _f64(delays)
+    Xs, Zs = _f32(X), _f32(Z)
+    Ys = None if Y is None else _f32(Y)
+    out = C.c_int32()
+    check(lib().simus_pfield_nf(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                                C.byref(make_options(options)), _p(d, C.c_double), Xs.size,
+                                _p(Xs, C.c_float), None if Ys is None else _p(Ys, C.c_float),
+                                _p(Zs, C.c_float), C.byref(out)))
+    return int(out.value)
+
+
+# ------------------------------------------------------------------ device calls
+def _tx(probe, delays, apod):
+    d = _f64(delays)
+    N = max(int(probe["n_elements"]), 1)
+    n_tx = d.size // N
+    a = _f32(np.ones((n_tx, N)) if apod is None else apod)
+    return d, a, n_tx
+
+
+def _offsets(offsets, n_scat):
+    o = np.ascontiguousarray(np.asarray([0, n_scat] if offsets is None else offsets, dtype=np.int64))
+    return o, o.size - 1
+
+
+def rf_spectrum_into(spec, probe, medium, options, delays, apod, x, y, z, refl,
+                     offsets=None, stream=None):
+    d, a, n_tx = _tx(probe, delays, apod)
+    o, n_ph = _offsets(offsets, x.numel())
+    check(lib().simus_rf_spectrum(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                                  C.byref(make_options(options)), n_tx, _p(d, C.c_double),
+                                  _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y),
+                                  _dev(z), _dev(refl), _dev(spec), _stream(stream)))
+
+
+def rf_into(rf, probe, medium, options, delays, apod, x, y, z, refl, offsets=None, stream=None):
+    d, a, n_tx = _tx(probe, delays, apod)
+    o, n_ph = _offsets(offsets, x.numel())
+    check(lib().simus_rf(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                         C.byref(make_options(options)), n_tx, _p(d, C.c_double), _p(a, C.c_float),
+                         n_ph, _p(o, C.c_int64), _dev(x), _dev(y), _dev(z), _dev(refl), _dev(rf),
+                         _stream(stream)))
+
+
+def spectrum_to_rf_into(rf, spec, nfft, n_t, j_lo, n_bins, n_chan, stream=None):
+    check(lib().simus_spectrum_to_rf(int(nfft), int(n_t), int(j_lo), int(n_bins), int(n_chan),
+                                     _dev(spec), _dev(rf), _stream(stream)))
+
+
+def rf_backward_into(grads, probe, medium, options, delays, apod, x, y, z, refl, drf,
+                     offsets=None, stream=None):
+    """grads: dict with optional device tensors 'refl', 'x', 'y', 'z'."""
+    d, a, n_tx = _tx(probe, delays, apod)
+    o, n_ph = _offsets(offsets, x.numel())
+    check(lib().simus_rf_backward(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                                  C.byref(make_options(options)), n_tx, _p(d, C.c_double),
+                                  _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y),
+                                  _dev(z), _dev(refl), _dev(drf), _dev(grads.get("refl")),
+                                  _dev(grads.get("x")), _dev(grads.get("y")), _dev(grads.get("z")),
+                                  _stream(stream)))
+
+
+def pfield_into(p_rms, probe, medium, options, n_f, delays, apod, X, Y, Z, stream=None):
+    d = _f64(delays)
+    a = _f32(np.ones(d.size) if apod is None else apod)
+    check(lib().simus_pfield(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                             C.byref(make_options(options)), int(n_f), _p(d, C.c_double),
+                             _p(a, C.c_float), X.numel(), _dev(X), _dev(Y), _dev(Z), _dev(p_rms),
+                             _stream(stream)))
+
+
+def release_workspace():
+    lib().simus_release_workspace()

@@ -1,0 +1,457 @@
+// C ABI of libsimus (include/simus.h): validation, planning, workspace and
+// kernel orchestration.  No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "simus.h"
+
+namespace simus {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess)
+        throw Error{SIMUS_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+bool log_enabled()
+{
+    static const bool on = [] {
+        const char* v = std::getenv("SIMUS_LOG");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
+
+// ---------------------------------------------------------------- workspace
+// One device arena and one pinned staging buffer per (device, stream).  The
+// staging buffer is rewritten only after the previous upload from it has
+// completed (event), so no call waits on kernels.
+struct Arena {
+    char* dev = nullptr;
+    size_t dev_cap = 0;
+    char* host = nullptr;
+    size_t host_cap = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, uintptr_t>, Arena> g_arenas;
+
+struct Layout {
+    size_t size = 0;
+    size_t add(size_t bytes)
+    {
+        const size_t off = size;
+        size += (bytes + 255) & ~size_t(255);
+        return off;
+    }
+};
+
+Arena& arena_for(hipStream_t st, size_t dev_bytes, size_t host_bytes)
+{
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Arena& a = g_arenas[{dev, reinterpret_cast<uintptr_t>(st)}];
+    if (!a.staged) hip_check(hipEventCreateWithFlags(&a.staged, hipEventDisableTiming), "hipEventCreate");
+    if (a.staged_pending) {
+        hip_check(hipEventSynchronize(a.staged), "hipEventSynchronize");
+        a.staged_pending = false;
+    }
+    if (dev_bytes > a.dev_cap) {
+        if (a.dev) {
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            hip_check(hipFree(a.dev), "hipFree");
+            a.dev = nullptr;
+            a.dev_cap = 0;
+        }
+        const size_t cap = std::max(dev_bytes, size_t(1) << 20);
+        if (hipMalloc(&a.dev, cap) != hipSuccess) {
+            a.dev = nullptr;
+            (void)hipGetLastError();
+            throw Error{SIMUS_ENOMEM, "device workspace allocation failed"};
+        }
+        a.dev_cap = cap;
+    }
+    if (host_bytes > a.host_cap) {
+        if (a.host) hip_check(hipHostFree(a.host), "hipHostFree");
+        a.host = nullptr;
+        a.host_cap = 0;
+        const size_t cap = std::max(host_bytes, size_t(1) << 16);
+        if (hipHostMalloc(reinterpret_cast<void**>(&a.host), cap, hipHostMallocDefault) != hipSuccess) {
+            a.host = nullptr;
+            (void)hipGetLastError();
+            throw Error{SIMUS_ENOMEM, "pinned staging allocation failed"};
+        }
+        a.host_cap = cap;
+    }
+    return a;
+}
+
+void upload(Arena& a, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return;
+    hip_check(hipMemcpyAsync(a.dev, a.host, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    hip_check(hipEventRecord(a.staged, st), "hipEventRecord");
+    a.staged_pending = true;
+}
+
+template <class T>
+T* at(char* base, size_t off)
+{
+    return reinterpret_cast<T*>(base + off);
+}
+
+// ---------------------------------------------------------------- model constants
+ModelConst model_constants(const Probe& P, const Band& B)
+{
+    ModelConst K{};
+    const double df = B.df;
+    K.turns_per_bin_m = df / P.c;
+    // Eq. (40): k_a = alpha/8.69 * f / 1e4 [Np/m]; exp(-k_a r) = 2^(log2(e) * -k_a r)
+    K.att_per_bin_m = (float)(-(P.alpha_db / 8.69) * (df / 1e4) * M_LOG2E);
+    K.sinc_per_bin = (float)(df * (0.5 * P.width / P.nu) / P.c);
+    K.q_per_bin = (float)(M_PI * df / P.c);
+    K.k_per_bin = (float)(2 * M_PI * df / P.c);
+    K.inv_rf = std::isinf(P.elev_focus) ? 0.f : (float)(1.0 / P.elev_focus);
+    K.zeta = (float)P.zeta;
+    K.baffle = P.baffle;
+    // Eq. (18): A_3 = conj(A_1), B_3 = conj(B_1), A_4 = conj(A_2), B_4 = conj(B_2).
+    const double Ar[4] = {0.187, 0.288, 0.187, 0.288};
+    const double Ai[4] = {0.275, -1.954, -0.275, 1.954};
+    const double Br[4] = {4.558, 8.598, 4.558, 8.598};
+    const double Bi[4] = {-25.59, -7.924, 25.59, 7.924};
+    const double h2 = P.height * P.height;
+    const double sq_pi = std::sqrt(M_PI);
+    for (int g = 0; g < 4; ++g) {
+        K.g.a[g] = (float)(Br[g] / h2);
+        K.g.a2[g] = (float)((Br[g] / h2) * (Br[g] / h2));
+        K.g.b[g] = (float)(Bi[g] / h2);
+        K.g.Ar[g] = (float)(sq_pi * Ar[g]);
+        K.g.Ai[g] = (float)(sq_pi * Ai[g]);
+    }
+    return K;
+}
+
+struct Phantoms {
+    int n = 0;
+    std::vector<int64_t> off;
+    int64_t total = 0;
+};
+
+Phantoms check_phantoms(int32_t n_ph, const int64_t* offs)
+{
+    if (n_ph < 1) throw Error{SIMUS_EINVAL, "n_phantoms must be >= 1"};
+    if (!offs) throw Error{SIMUS_EINVAL, "scat_offsets must be non-NULL"};
+    if (offs[0] != 0) throw Error{SIMUS_EINVAL, "scat_offsets[0] must be 0"};
+    Phantoms ph;
+    ph.n = n_ph;
+    ph.off.assign(offs, offs + n_ph + 1);
+    for (int p = 0; p < n_ph; ++p)
+        if (offs[p + 1] < offs[p]) throw Error{SIMUS_EINVAL, "scat_offsets must be non-decreasing"};
+    ph.total = offs[n_ph];
+    if (ph.total >= (int64_t(1) << 31)) throw Error{SIMUS_EINVAL, "too many scatterers (>= 2^31)"};
+    return ph;
+}
+
+// ---------------------------------------------------------------- forward spectra
+struct Forward {
+    Probe P;
+    Band B;
+    SynthConfig cfg;
+    int n_tx = 0, n_bt = 0, n_tg = 0, slice = 0, n_items = 0;
+};
+
+// Plans and enqueues the spectra; writes spec (device [P][T][N][n_bins] float2).
+// If spec_out is null, spectra go to a workspace buffer whose pointer is
+// returned through *spec_ws together with the arena.
+void forward_spectra(const simus_probe* probe, const simus_medium* medium,
+                     const simus_options* opt, int32_t n_tx, const double* delays,
+                     const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
+                     const float* y, const float* z, const float* refl, float* spec_out,
+                     float* rf_out, hipStream_t st)
+{
+    Forward F;
+    F.P = make_probe(probe, medium, opt);
+    check_transmits(F.P, n_tx, delays, apod);
+    const Phantoms ph = check_phantoms(n_ph, offs);
+    if (opt->nfft <= 0) throw Error{SIMUS_EINVAL, "options.nfft must be > 0 (see simus_rf_grid)"};
+    if (opt->n_t > opt->nfft) throw Error{SIMUS_EINVAL, "options.n_t must be <= nfft"};
+    if (ph.total > 0 && (!x || !z || !refl)) throw Error{SIMUS_EINVAL, "x, z and refl must be non-NULL"};
+    if (!spec_out && !rf_out) throw Error{SIMUS_EINVAL, "output pointer must be non-NULL"};
+    F.B = make_band(F.P, opt->nfft, opt->n_t);
+    F.n_tx = n_tx;
+    const int N = F.P.N, M = F.P.M;
+    const bool has_y = y != nullptr;
+    F.cfg = synth_config(M, n_tx, has_y);
+    const int JT = F.cfg.jt, TT = F.cfg.tt, BS = F.cfg.bs, SC = F.cfg.sc;
+    F.n_bt = (F.B.n_bins + JT - 1) / JT;
+    F.n_tg = (n_tx + TT - 1) / TT;
+    // scatterers per item: about 2048 items over the whole call
+    int64_t slice = opt->tile_scat;
+    if (slice <= 0) {
+        const int64_t work = std::max<int64_t>(1, ph.total) * F.n_bt * F.n_tg;
+        slice = (work + 2047) / 2048;
+    }
+    slice = std::max<int64_t>(slice, 4 * SC);
+    slice = (slice + SC - 1) / SC * SC;
+    F.slice = (int)std::min<int64_t>(slice, int64_t(1) << 30);
+
+    std::vector<Item> items;
+    std::vector<int32_t> pbase(n_ph), nsl(n_ph);
+    for (int p = 0; p < n_ph; ++p) {
+        const int64_t S = ph.off[p + 1] - ph.off[p];
+        const int ns = (int)((S + F.slice - 1) / F.slice);
+        pbase[p] = (int32_t)items.size();
+        nsl[p] = ns;
+        for (int tg = 0; tg < F.n_tg; ++tg)
+            for (int bt = 0; bt < F.n_bt; ++bt)
+                for (int sl = 0; sl < ns; ++sl) {
+                    const int64_t s0 = ph.off[p] + int64_t(sl) * F.slice;
+                    const int64_t s1 = std::min<int64_t>(s0 + F.slice, ph.off[p + 1]);
+                    items.push_back(Item{p, (int32_t)s0, (int32_t)s1, bt | (tg << 16)});
+                }
+    }
+    F.n_items = (int)items.size();
+    if (F.n_bt >= 65536 || F.n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
+
+    // ---- layout
+    const SubElements S = sub_elements(F.P);
+    Layout up;
+    const size_t o_xc = up.add(sizeof(double) * M), o_zc = up.add(sizeof(double) * M);
+    const size_t o_tx = up.add(sizeof(float) * M), o_tz = up.add(sizeof(float) * M);
+    const size_t o_nx = up.add(sizeof(float) * M), o_nz = up.add(sizeof(float) * M);
+    const size_t o_dl = up.add(sizeof(double) * n_tx * N), o_ap = up.add(sizeof(float) * n_tx * N);
+    const size_t o_pw = up.add(sizeof(float2) * std::max(F.B.n_bins, 1));
+    const size_t o_it = up.add(sizeof(Item) * std::max(F.n_items, 1));
+    const size_t o_pb = up.add(sizeof(int32_t) * n_ph), o_ns = up.add(sizeof(int32_t) * n_ph);
+    Layout dv = up;
+    const size_t o_W = dv.add(sizeof(float2) * size_t(std::max(F.B.n_bins, 1)) * n_tx * N);
+    const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(F.n_items, 1)) * JT * TT * BS);
+    const size_t o_tk = dv.add(sizeof(int32_t) * 4);
+    const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(F.B.n_bins, 1);
+    const size_t o_spec = spec_out ? 0 : dv.add(spec_bytes);
+
+    Arena& a = arena_for(st, dv.size, up.size);
+    char* h = a.host;
+    for (int m = 0; m < M; ++m) {
+        at<double>(h, o_xc)[m] = S.xc[m];
+        at<double>(h, o_zc)[m] = S.zc[m];
+        at<float>(h, o_tx)[m] = (float)S.tx[m];
+        at<float>(h, o_tz)[m] = (float)S.tz[m];
+        at<float>(h, o_nx)[m] = (float)S.nx[m];
+        at<float>(h, o_nz)[m] = (float)S.nz[m];
+    }
+    for (int i = 0; i < n_tx * N; ++i) {
+        at<double>(h, o_dl)[i] = delays[i];
+        at<float>(h, o_ap)[i] = apod ? apod[i] : 1.f;
+    }
+    for (int b = 0; b < F.B.n_bins; ++b) {
+        const double w = 2 * M_PI * (F.B.j_lo + b) * F.B.df;
+        const std::complex<double> v = pulse_spectrum(F.P, w) * transducer_spectrum(F.P, w);
+        at<float2>(h, o_pw)[b] = make_float2((float)v.real(), (float)v.imag());
+    }
+    if (F.n_items) std::memcpy(h + o_it, items.data(), sizeof(Item) * F.n_items);
+    std::memcpy(h + o_pb, pbase.data(), sizeof(int32_t) * n_ph);
+    std::memcpy(h + o_ns, nsl.data(), sizeof(int32_t) * n_ph);
+    upload(a, up.size, st);
+
+    char* d = a.dev;
+    float2* W = at<float2>(d, o_W);
+    float2* spec = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(d, o_spec);
+    hip_check(launch_wtable(W, at<double>(d, o_dl), at<float>(d, o_ap), F.B.n_bins, n_tx, N,
+                            F.B.j_lo, F.B.df, st),
+              "wtable launch");
+    SynthArgs A{};
+    A.x = x;
+    A.y = y;
+    A.z = z;
+    A.refl = refl;
+    A.sub = SubGeo{at<double>(d, o_xc), at<double>(d, o_zc), at<float>(d, o_tx),
+                   at<float>(d, o_tz), at<float>(d, o_nx), at<float>(d, o_nz)};
+    A.W = W;
+    A.items = at<Item>(d, o_it);
+    A.n_items = F.n_items;
+    A.part = at<float2>(d, o_part);
+    A.M = M;
+    A.nu = F.P.nu;
+    A.N = N;
+    A.n_tx = n_tx;
+    A.n_bins = F.B.n_bins;
+    A.j_lo = F.B.j_lo;
+    A.K = model_constants(F.P, F.B);
+    A.ticket = nullptr;
+    F.cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
+    if (F.cfg.persistent && F.n_items > 0) {
+        A.ticket = at<int32_t>(d, o_tk);
+        hip_check(launch_zero_i32(A.ticket, 1, st), "zero launch");
+        int per_cu = 0;
+        hipDeviceProp_t prop;
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        per_cu = std::max(1, 1024 / BS);
+        F.cfg.grid = std::min(F.n_items, prop.multiProcessorCount * per_cu);
+    } else {
+        F.cfg.grid = F.n_items;
+    }
+    if (log_enabled())
+        std::fprintf(stderr,
+                     "[simus] N=%d nu=%d M=%d T=%d P=%d S=%lld nfft=%d n_t=%d j_lo=%d bins=%d "
+                     "BS=%d TT=%d SC=%d JT=%d slice=%d items=%d grid=%d y=%d persistent=%d\n",
+                     N, F.P.nu, M, n_tx, n_ph, (long long)ph.total, F.B.nfft, F.B.n_t, F.B.j_lo,
+                     F.B.n_bins, BS, TT, SC, JT, F.slice, F.n_items, F.cfg.grid, (int)has_y,
+                     (int)F.cfg.persistent);
+    hip_check(launch_synth(F.cfg, A, st), "synthesis launch");
+    hip_check(launch_finalize(spec, A.part, at<float2>(d, o_pw), at<int32_t>(d, o_pb),
+                              at<int32_t>(d, o_ns), n_ph, n_tx, N, F.P.nu, F.B.n_bins, BS, TT, JT,
+                              F.n_bt, st),
+              "finalize launch");
+    if (rf_out) {
+        hip_check(launch_idft(rf_out, spec, int64_t(n_ph) * n_tx * N, F.B.n_bins, F.B.j_lo,
+                              F.B.nfft, F.B.n_t, st),
+                  "inverse transform launch");
+    }
+}
+
+template <class Fn>
+int guarded(Fn&& fn)
+{
+    try {
+        fn();
+        return SIMUS_OK;
+    } catch (const Error& e) {
+        return fail(e.code, e.msg);
+    } catch (const std::exception& e) {
+        return fail(SIMUS_EINVAL, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(SIMUS_EINVAL, "internal error");
+    }
+}
+
+}  // namespace
+}  // namespace simus
+
+using namespace simus;
+
+extern "C" {
+
+int simus_version(void) { return SIMUS_VERSION; }
+
+const char* simus_last_error(void) { return g_last_error.c_str(); }
+
+int simus_rf_grid(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+                  int32_t n_tx, const double* delays, int64_t n_scat, const float* x,
+                  const float* y, const float* z, simus_grid* out)
+{
+    return guarded([&] {
+        if (!out) throw Error{SIMUS_EINVAL, "out must be non-NULL"};
+        const Probe P = make_probe(probe, medium, opt);
+        check_transmits(P, n_tx, delays, nullptr);
+        if (n_scat < 0) throw Error{SIMUS_EINVAL, "n_scat must be >= 0"};
+        if (n_scat > 0 && (!x || !z)) throw Error{SIMUS_EINVAL, "x and z must be non-NULL"};
+        const SubElements S = sub_elements(P);
+        check_domain(P, S, n_scat, x, y, z);
+        int64_t nfft = opt->nfft;
+        if (nfft <= 0) {
+            const double rmax = max_distance(S, n_scat, x, y, z);
+            double dmax = 0;
+            for (int64_t i = 0; i < int64_t(n_tx) * P.N; ++i) dmax = std::max(dmax, delays[i]);
+            const double tmax = 2 * rmax / P.c + dmax + 10.0 / P.fc;
+            const int64_t need = std::max<int64_t>((int64_t)std::ceil(P.fs * tmax), opt->n_t);
+            nfft = next_fft_size(need);
+        }
+        if (nfft > (int64_t(1) << 26)) throw Error{SIMUS_EINVAL, "nfft too large"};
+        if (opt->n_t > nfft) throw Error{SIMUS_EINVAL, "options.n_t must be <= nfft"};
+        const Band B = make_band(P, (int)nfft, opt->n_t);
+        out->nfft = B.nfft;
+        out->n_t = B.n_t;
+        out->j_lo = B.j_lo;
+        out->n_bins = B.n_bins;
+        out->nu = P.nu;
+        out->reserved = 0;
+        out->df = B.df;
+    });
+}
+
+int simus_rf_spectrum(const simus_probe* probe, const simus_medium* medium,
+                      const simus_options* opt, int32_t n_tx, const double* delays,
+                      const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
+                      const float* y, const float* z, const float* refl, float* spec,
+                      void* hip_stream)
+{
+    return guarded([&] {
+        if (!spec) throw Error{SIMUS_EINVAL, "spec must be non-NULL"};
+        forward_spectra(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl, spec,
+                        nullptr, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int simus_rf(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+             int32_t n_tx, const double* delays, const float* apod, int32_t n_ph,
+             const int64_t* offs, const float* x, const float* y, const float* z,
+             const float* refl, float* rf, void* hip_stream)
+{
+    return guarded([&] {
+        if (!rf) throw Error{SIMUS_EINVAL, "rf must be non-NULL"};
+        forward_spectra(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl, nullptr,
+                        rf, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int simus_spectrum_to_rf(int32_t nfft, int32_t n_t, int32_t j_lo, int32_t n_bins, int64_t n_chan,
+                         const float* spec, float* rf, void* hip_stream)
+{
+    return guarded([&] {
+        if (nfft < 2 || nfft % 2) throw Error{SIMUS_EINVAL, "nfft must be even and >= 2"};
+        if (n_t < 0 || n_t > nfft) throw Error{SIMUS_EINVAL, "n_t must be in [0, nfft]"};
+        if (n_bins < 0 || j_lo < 0 || int64_t(j_lo) + n_bins > nfft / 2 + 1)
+            throw Error{SIMUS_EINVAL, "bins must lie in [0, nfft/2]"};
+        if (n_chan < 0) throw Error{SIMUS_EINVAL, "n_chan must be >= 0"};
+        if (n_chan > 0 && n_t > 0 && (!spec || !rf)) throw Error{SIMUS_EINVAL, "spec and rf must be non-NULL"};
+        hip_check(launch_idft(rf, reinterpret_cast<const float2*>(spec), n_chan, n_bins, j_lo, nfft,
+                              n_t, static_cast<hipStream_t>(hip_stream)),
+                  "inverse transform launch");
+    });
+}
+
+void simus_release_workspace(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : g_arenas) {
+        Arena& a = kv.second;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.first.first);
+        if (a.staged) (void)hipEventSynchronize(a.staged);
+        (void)hipDeviceSynchronize();
+        if (a.dev) (void)hipFree(a.dev);
+        if (a.host) (void)hipHostFree(a.host);
+        if (a.staged) (void)hipEventDestroy(a.staged);
+        (void)hipSetDevice(cur);
+    }
+    g_arenas.clear();
+}
+
+}  // extern "C"

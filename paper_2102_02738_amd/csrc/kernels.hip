@@ -1,0 +1,398 @@
+// libsimus HIP kernels for gfx950: transmit weights, Green's-tile synthesis
+// with both contractions (Eqs. 22, 29-33), finalisation (Eq. 34) and the
+// inverse transform of Eq. (1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "green.hpp"
+#include "kernels.hpp"
+
+namespace simus {
+
+// ---------------------------------------------------------------------------
+// Transmit weights W[b][t][e] = apod[t][e] exp(i w_j tau[t][e]) (Eqs. 20, 22),
+// phase reduced in FP64.
+// ---------------------------------------------------------------------------
+__global__ void k_wtable(float2* __restrict__ W, const double* __restrict__ delays,
+                         const float* __restrict__ apod, int n_bins, int n_tx, int N, int j_lo,
+                         double df)
+{
+    const int64_t total = (int64_t)n_bins * n_tx * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int te = (int)(i % ((int64_t)n_tx * N));
+        const int b = (int)(i / ((int64_t)n_tx * N));
+        const double turns = (double)(j_lo + b) * df * delays[te];
+        const float t = (float)(turns - rint(turns));
+        const float a = apod ? apod[te] : 1.f;
+        W[i] = make_float2(a * cos_turns(t), a * sin_turns(t));
+    }
+}
+
+hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
+                         int N, int j_lo, double df, hipStream_t st)
+{
+    const int64_t total = (int64_t)n_bins * n_tx * N;
+    if (total == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_wtable, dim3(grid), dim3(256), 0, st, W, delays, apod, n_bins, n_tx, N,
+                       j_lo, df);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis.  One block owns all sub-elements (thread n = sub-element n) and
+// walks the scatterers of one work item in chunks of SC.  For each bin of
+// its tile it
+//   1. builds G[n][s] for the chunk in registers (Green's term, green.hpp),
+//   2. Tx contraction a[s][t] = sum_n W[t][e(n)] G[n][s]: the products go
+//      to LDS and groups of lanes reduce them (no atomics),
+//   3. scales by the reflectivity, c[s][t] = R_s a[s][t],
+//   4. Rx contraction X_sub[n][t] += sum_s G[n][s] c[s][t], accumulated per
+//      sub-element in an LDS slot private to the thread.
+// The per-sub-element partials of every item go to `part`; the finaliser
+// sums them over items and over the nu sub-elements of each element.
+// ---------------------------------------------------------------------------
+template <int BS, int SC, int JT, int TT, bool HASY>
+__global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
+{
+    constexpr int NS = SC * TT;            // sums per bin
+    constexpr int RS = BS + 4;             // LDS row stride (float2)
+    constexpr int GL = (BS / NS >= 64) ? 64 : BS / NS;   // lanes per sum
+    constexpr int PER = BS / GL;           // values per lane
+    static_assert(NS <= BS, "chunk x transmit group must not exceed the block");
+
+    __shared__ float4 s_sc[SC];
+    __shared__ float2 s_red[NS * RS];
+    __shared__ float2 s_c[NS];
+    __shared__ float2 s_acc[JT * TT * BS];
+
+    const int tid = threadIdx.x;
+    const bool active = tid < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? tid : 0);
+    const int e = active ? tid / A.nu : 0;
+
+    // Static launch: one item per block.  Persistent launch: blocks draw
+    // items from a work counter until it passes n_items (every block exits).
+    __shared__ int s_item;
+    int item = blockIdx.x;
+    if (A.ticket) {
+        if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+        __syncthreads();
+        item = s_item;
+    }
+    while (item < A.n_items) {
+        const Item it = A.items[item];
+        const int bt = it.tile & 0xffff, tg = it.tile >> 16;
+        const int jb0 = bt * JT;
+        const int nb = min(JT, A.n_bins - jb0);
+        const int t0 = tg * TT;
+
+        for (int i = tid; i < JT * TT * BS; i += BS) s_acc[i] = make_float2(0.f, 0.f);
+
+        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SC) {
+            if (tid < SC) {
+                const int s = s0 + tid;
+                float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
+                if (s < it.s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
+                s_sc[tid] = v;
+            }
+            __syncthreads();
+            Geo g[SC];
+#pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                const float4 v = s_sc[s];
+                g[s] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+                if (!active) g[s].amp = 0.f;
+            }
+            for (int jj = 0; jj < nb; ++jj) {
+                const int jb = jb0 + jj;
+                const float jf = (float)(A.j_lo + jb);
+                float2 G[SC];
+#pragma unroll
+                for (int s = 0; s < SC; ++s) G[s] = green_step<HASY>(A.K, g[s], jf);
+                float2 W[TT];
+#pragma unroll
+                for (int t = 0; t < TT; ++t) {
+                    W[t] = make_float2(0.f, 0.f);
+                    if (active && t0 + t < A.n_tx) W[t] = A.W[((int64_t)jb * A.n_tx + t0 + t) * A.N + e];
+                }
+#pragma unroll
+                for (int t = 0; t < TT; ++t)
+#pragma unroll
+                    for (int s = 0; s < SC; ++s) s_red[(t * SC + s) * RS + tid] = cmul(W[t], G[s]);
+                __syncthreads();
+                {
+                    const int sid = tid / GL, lg = tid % GL;
+                    if (sid < NS) {
+                        float2 acc = make_float2(0.f, 0.f);
+                        const float2* row = &s_red[sid * RS];
+#pragma unroll
+                        for (int i = 0; i < PER; ++i) {
+                            const float2 v = row[lg + i * GL];
+                            acc.x += v.x;
+                            acc.y += v.y;
+                        }
+#pragma unroll
+                        for (int off = GL / 2; off > 0; off >>= 1) {
+                            acc.x += __shfl_xor(acc.x, off);
+                            acc.y += __shfl_xor(acc.y, off);
+                        }
+                        if (lg == 0) {
+                            const float R = s_sc[sid % SC].w;
+                            s_c[sid] = make_float2(R * acc.x, R * acc.y);
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < TT; ++t) {
+                    float2 x = s_acc[(jj * TT + t) * BS + tid];
+#pragma unroll
+                    for (int s = 0; s < SC; ++s) x = cfma(G[s], s_c[t * SC + s], x);
+                    s_acc[(jj * TT + t) * BS + tid] = x;
+                }
+            }
+            __syncthreads();
+        }
+        float2* out = A.part + (int64_t)item * (JT * TT * BS);
+        for (int i = tid; i < JT * TT * BS; i += BS) out[i] = s_acc[i];
+
+        if (!A.ticket) break;
+        __syncthreads();
+        if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+        __syncthreads();
+        item = s_item;
+    }
+}
+
+SynthConfig synth_config(int M, int n_tx, bool has_y)
+{
+    SynthConfig c{};
+    int bs = 64;
+    while (bs < M) bs *= 2;
+    c.bs = bs;
+    c.tt = n_tx >= 8 ? 8 : n_tx >= 4 ? 4 : n_tx >= 2 ? 2 : 1;
+    if (bs > 512 && c.tt > 4) c.tt = 4;     // LDS: reduction rows + accumulators
+    c.sc = c.tt >= 4 ? 2 : (c.tt == 2 ? 4 : 8);
+    // s_acc (JT * TT * BS float2) kept within 64 KiB
+    int jt = 16;
+    while (jt > 1 && jt * c.tt * bs * 8 > 65536) jt /= 2;
+    c.jt = jt;
+    c.has_y = has_y;
+    return c;
+}
+
+template <int BS, int SC, int JT, int TT>
+static hipError_t launch_synth_y(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
+{
+    if (cfg.has_y)
+        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, true>), dim3(cfg.grid), dim3(BS), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, false>), dim3(cfg.grid), dim3(BS), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int BS>
+static hipError_t launch_synth_bs(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
+{
+    constexpr int J1 = (16 * 1 * BS * 8 <= 65536) ? 16 : 65536 / (8 * BS);
+    constexpr int J2 = (16 * 2 * BS * 8 <= 65536) ? 16 : 65536 / (16 * BS);
+    constexpr int J4 = (16 * 4 * BS * 8 <= 65536) ? 16 : 65536 / (32 * BS);
+    constexpr int J8 = (16 * 8 * BS * 8 <= 65536) ? 16 : 65536 / (64 * BS);
+    switch (cfg.tt) {
+    case 1: return launch_synth_y<BS, 8, J1, 1>(cfg, a, st);
+    case 2: return launch_synth_y<BS, 4, J2, 2>(cfg, a, st);
+    case 4: return launch_synth_y<BS, 2, J4, 4>(cfg, a, st);
+    case 8:
+        if constexpr (BS <= 512) return launch_synth_y<BS, 2, J8, 8>(cfg, a, st);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
+{
+    if (cfg.grid <= 0) return hipSuccess;
+    switch (cfg.bs) {
+    case 64: return launch_synth_bs<64>(cfg, a, st);
+    case 128: return launch_synth_bs<128>(cfg, a, st);
+    case 256: return launch_synth_bs<256>(cfg, a, st);
+    case 512: return launch_synth_bs<512>(cfg, a, st);
+    case 1024: return launch_synth_bs<1024>(cfg, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finaliser: spec[p][t][e][b] = P_b sum_items sum_{mu<nu} part[item][jj][t%TT][e nu + mu]
+// (Eqs. 33-34).  Items of phantom p are ordered (tg, bt, slice); the sum
+// over slices runs in slice order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+__global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__ part,
+                           const float2* __restrict__ pw, const int32_t* __restrict__ pbase,
+                           const int32_t* __restrict__ nsl, int n_ph, int n_tx, int N, int nu,
+                           int n_bins, int bs, int tt, int jt, int n_bt)
+{
+    const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(i % N);
+        int64_t r = i / N;
+        const int b = (int)(r % n_bins);
+        r /= n_bins;
+        const int t = (int)(r % n_tx);
+        const int p = (int)(r / n_tx);
+        const int tg = t / tt, tl = t % tt, bt = b / jt, jj = b % jt;
+        const int ns = nsl[p];
+        const int64_t first = pbase[p] + ((int64_t)tg * n_bt + bt) * ns;
+        float sx = 0.f, sy = 0.f;
+        for (int sl = 0; sl < ns; ++sl) {
+            const float2* src = part + (first + sl) * ((int64_t)jt * tt * bs) + (jj * tt + tl) * bs + e * nu;
+            for (int mu = 0; mu < nu; ++mu) {
+                sx += src[mu].x;
+                sy += src[mu].y;
+            }
+        }
+        const float2 w = pw[b];
+        spec[(((int64_t)p * n_tx + t) * N + e) * n_bins + b] =
+            make_float2(w.x * sx - w.y * sy, w.x * sy + w.y * sx);
+    }
+}
+
+hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
+                           const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
+                           int nu, int n_bins, int bs, int tt, int jt, int n_bt, hipStream_t st)
+{
+    const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
+    if (total == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, spec, part, pw, pbase, nsl, n_ph,
+                       n_tx, N, nu, n_bins, bs, tt, jt, n_bt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Inverse transform (Eq. 1): rf[c][q] = sum_b Re(spec[c][b] e^{-2 pi i j q / nfft}),
+// j = j_lo + b.  The angle index j q mod nfft is carried exactly in integers
+// and turned into turns in [-1/2, 1/2) for the hardware sine/cosine.  One
+// block per (channel, 256 samples); the channel's spectrum is staged in LDS
+// in chunks.
+// ---------------------------------------------------------------------------
+constexpr int DFT_CHUNK = 4096;
+
+__global__ __launch_bounds__(256) void k_idft(float* __restrict__ rf, const float2* __restrict__ spec,
+                                              int64_t ch0, int n_bins, int j_lo, int nfft, int n_t)
+{
+    __shared__ float2 s_x[DFT_CHUNK];
+    const int64_t ch = ch0 + blockIdx.y;
+    const float2* X = spec + ch * n_bins;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = q < n_t;
+    const int qq = live ? q : 0;
+    const float inv_n = 1.f / (float)nfft;
+    const int half = nfft / 2;
+    int m = (int)(((int64_t)j_lo * qq) % nfft);
+    float acc0 = 0.f, acc1 = 0.f;
+    for (int c0 = 0; c0 < n_bins; c0 += DFT_CHUNK) {
+        const int cn = min(DFT_CHUNK, n_bins - c0);
+        __syncthreads();
+        for (int b = threadIdx.x; b < cn; b += blockDim.x) s_x[b] = X[c0 + b];
+        __syncthreads();
+        int b = 0;
+        for (; b + 1 < cn; b += 2) {
+            const int m1 = (m + qq >= nfft) ? m + qq - nfft : m + qq;
+            const float t0 = (float)(m >= half ? m - nfft : m) * inv_n;
+            const float t1 = (float)(m1 >= half ? m1 - nfft : m1) * inv_n;
+            const float2 x0 = s_x[b], x1 = s_x[b + 1];
+            acc0 = fmaf(x0.x, cos_turns(t0), acc0);
+            acc0 = fmaf(x0.y, sin_turns(t0), acc0);
+            acc1 = fmaf(x1.x, cos_turns(t1), acc1);
+            acc1 = fmaf(x1.y, sin_turns(t1), acc1);
+            m = (m1 + qq >= nfft) ? m1 + qq - nfft : m1 + qq;
+        }
+        if (b < cn) {
+            const float t0 = (float)(m >= half ? m - nfft : m) * inv_n;
+            const float2 x0 = s_x[b];
+            acc0 = fmaf(x0.x, cos_turns(t0), acc0);
+            acc0 = fmaf(x0.y, sin_turns(t0), acc0);
+            m = (m + qq >= nfft) ? m + qq - nfft : m + qq;
+        }
+    }
+    if (live) rf[ch * n_t + q] = acc0 + acc1;
+}
+
+hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins, int j_lo,
+                       int nfft, int n_t, hipStream_t st)
+{
+    if (n_chan == 0 || n_t == 0) return hipSuccess;
+    for (int64_t c0 = 0; c0 < n_chan; c0 += 65535) {
+        const unsigned nc = (unsigned)std::min<int64_t>(65535, n_chan - c0);
+        hipLaunchKernelGGL(k_idft, dim3((n_t + 255) / 256, nc), dim3(256), 0, st, rf, spec, c0,
+                           n_bins, j_lo, nfft, n_t);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Adjoint transform: lam[c][b] = sum_q rho[c][q] e^{-2 pi i j q / nfft}.
+__global__ __launch_bounds__(256) void k_dft(float2* __restrict__ lam, const float* __restrict__ rho,
+                                             int64_t ch0, int n_bins, int j_lo, int nfft, int n_t)
+{
+    __shared__ float s_r[2 * DFT_CHUNK];
+    const int64_t ch = ch0 + blockIdx.y;
+    const float* R = rho + ch * n_t;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = b < n_bins;
+    const int j = (j_lo + (live ? b : 0)) % nfft;
+    const float inv_n = 1.f / (float)nfft;
+    const int half = nfft / 2;
+    int m = 0;
+    float re = 0.f, im = 0.f;
+    for (int c0 = 0; c0 < n_t; c0 += 2 * DFT_CHUNK) {
+        const int cn = min(2 * DFT_CHUNK, n_t - c0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cn; q += blockDim.x) s_r[q] = R[c0 + q];
+        __syncthreads();
+        for (int q = 0; q < cn; ++q) {
+            const float t = (float)(m >= half ? m - nfft : m) * inv_n;
+            const float v = s_r[q];
+            re = fmaf(v, cos_turns(t), re);
+            im = fmaf(-v, sin_turns(t), im);
+            m += j;
+            if (m >= nfft) m -= nfft;
+        }
+    }
+    if (live) lam[ch * n_bins + b] = make_float2(re, im);
+}
+
+hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,
+                      int nfft, int n_t, hipStream_t st)
+{
+    if (n_chan == 0 || n_bins == 0) return hipSuccess;
+    for (int64_t c0 = 0; c0 < n_chan; c0 += 65535) {
+        const unsigned nc = (unsigned)std::min<int64_t>(65535, n_chan - c0);
+        hipLaunchKernelGGL(k_dft, dim3((n_bins + 255) / 256, nc), dim3(256), 0, st, lam, rho, c0,
+                           n_bins, j_lo, nfft, n_t);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+__global__ void k_zero_i32(int32_t* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace simus

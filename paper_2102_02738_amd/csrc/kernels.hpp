@@ -1,0 +1,93 @@
+// Device-side argument blocks and launch entry points of libsimus kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace simus {
+
+// Four-Gaussian elevation constants of Eq. (18), scaled by 1/h^2.
+struct Gauss4 {
+    float a[4];    // Re(B_g) / h^2   (> 0)
+    float a2[4];   // a^2
+    float b[4];    // Im(B_g) / h^2
+    float Ar[4];   // sqrt(pi) Re(A_g)
+    float Ai[4];   // sqrt(pi) Im(A_g)
+};
+
+// Per-call model constants.  All "per bin" rates are multiplied by the
+// absolute bin index j (f_j = j df).
+struct ModelConst {
+    double turns_per_bin_m;  // df / c: phase turns of exp(i k r) per bin per metre
+    float att_per_bin_m;     // -(alpha_dB / 8.69) (df / 1e4) log2(e): log2 of exp(-k_a r) per bin per metre
+    float sinc_per_bin;      // df b_sub / c: sinc argument in turns per bin per unit sin(theta)
+    float q_per_bin;         // pi df / c: Im(alpha_g) shift per bin per (1/R_f - 1/r)
+    float k_per_bin;         // 2 pi df / c
+    float inv_rf;            // 1 / R_f (0 for an unfocused element)
+    float zeta;              // baffle impedance ratio
+    int32_t baffle;          // 0 soft, 1 rigid, 2 zeta
+    Gauss4 g;
+};
+
+// Sub-element frames, device arrays of length M = nu N.
+struct SubGeo {
+    const double* xc;
+    const double* zc;
+    const float* tx;
+    const float* tz;
+    const float* nx;
+    const float* nz;
+};
+
+// One work item of the synthesis: scatterers [s_begin, s_end) of a phantom,
+// bin tile `bt`, transmit group `tg`.
+struct Item {
+    int32_t phantom;
+    int32_t s_begin;
+    int32_t s_end;
+    int32_t tile;  // bt | (tg << 16)
+};
+
+struct SynthArgs {
+    const float* x;
+    const float* y;     // may be null (y = 0)
+    const float* z;
+    const float* refl;
+    SubGeo sub;
+    const float2* W;    // [n_bins][n_tx][N] transmit weights W e^{i w tau}
+    const Item* items;
+    int32_t n_items;
+    int32_t* ticket;    // persistent launch: work counter (zeroed before launch)
+    float2* part;       // [n_items][JT][TT][BS] per-sub-element partial spectra
+    int32_t M, nu, N, n_tx, n_bins, j_lo;
+    ModelConst K;
+};
+
+struct SynthConfig {
+    int bs;      // threads per block = sub-elements per block (power of 2, >= M)
+    int tt;      // transmits per group
+    int sc;      // scatterers per chunk
+    int jt;      // bins per tile
+    bool has_y;
+    bool persistent;
+    int grid;    // blocks launched (persistent: resident blocks)
+};
+
+// Picks tt/sc/jt for a block size and transmit count.
+SynthConfig synth_config(int M, int n_tx, bool has_y);
+
+hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
+                         int N, int j_lo, double df, hipStream_t st);
+hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
+hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
+                           const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
+                           int nu, int n_bins, int bs, int tt, int jt, int n_bt,
+                           hipStream_t st);
+hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins, int j_lo,
+                       int nfft, int n_t, hipStream_t st);
+hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,
+                      int nfft, int n_t, hipStream_t st);
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
+
+}  // namespace simus

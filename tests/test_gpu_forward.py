@@ -1,0 +1,188 @@
+"""GPU parity of the forward path (spectra and RF) against the FP64 oracle.
+
+Bar: relative L2 error <= 1e-4 (FP32 path vs FP64 oracle) on RF and on
+spectra; bit-exact integers for the grid; bitwise-identical results for
+repeated calls and for the persistent launch.
+"""
+import numpy as np
+import pytest
+
+from tests.helpers import concat_phantoms, oracle_setup, rel_l2, sample_bins, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2102_02738_amd as S
+    S._lib.lib()
+    return S
+
+
+def _run(S, w, flags=0, with_y=False, spectrum=False, bins=None):
+    x, y, z, R, off = concat_phantoms(w["phantoms"])
+    g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, y if with_y else None, z)
+    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"], flags=flags)
+    dx, dy, dz, dR = to_dev(x, y if with_y else None, z, R)
+    offs = off if len(w["phantoms"]) > 1 else None
+    if spectrum:
+        out = S.rf_spectrum(w["probe"], w["medium"], o, w["delays"], w["apod"], dx, dy, dz, dR,
+                            offsets=offs, n_bins=g["n_bins"])
+    else:
+        out = S.rf(w["probe"], w["medium"], o, w["delays"], w["apod"], dx, dy, dz, dR, offsets=offs)
+    import torch
+    torch.cuda.synchronize()
+    return g, out.cpu().numpy(), (x, y, z, R, off)
+
+
+def _oracle_rf(orc, w, g, data, with_y=False):
+    x, y, z, R, off = data
+    su = oracle_setup(orc, w)
+    out = []
+    for p in range(len(off) - 1):
+        sl = slice(off[p], off[p + 1])
+        yy = y[sl] if with_y else np.zeros(off[p + 1] - off[p])
+        out.append(orc.rf(su, g, w["delays"], w["apod"], x[sl], yy, z[sl], R[sl]))
+    return np.stack(out)
+
+
+def test_rf_pw32_s200_full(S, orc):
+    """32 elements, 1 plane wave, 200 scatterers: full RF parity."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200")
+    g, rf, data = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    print("pw32_s200 rel L2", rel_l2(rf, ref))
+    assert rf.shape == ref.shape
+    assert rel_l2(rf, ref) <= TOL
+
+
+def test_rf_pw128_small_full(S, orc):
+    """128 elements, anechoic disks, attenuation, 50 mm depth, 1000 scatterers:
+    full RF parity (several scatter tiles, ragged tail, n_t < nfft)."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw128_s50k", scale=0.02)
+    g, rf, data = _run(S, w)
+    assert g["n_t"] == 1975
+    ref = _oracle_rf(orc, w, g, data)
+    print("pw128 1000 rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
+def test_spectrum_pw128_s50k_full_size_sampled_bins(S, orc):
+    """Full 50,000-scatterer workload in the benchmark's launch
+    configuration; the oracle evaluates a spread of bins (band edges
+    included) and the GPU spectra must match them."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw128_s50k")
+    g, spec, data = _run(S, w, spectrum=True)
+    bins = sample_bins(g, 6)
+    x, y, z, R, off = data
+    ref = orc.spectrum(oracle_setup(orc, w), g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
+    got = spec[0][:, :, bins - g["j_lo"]]
+    print("pw128_s50k sampled bins rel L2", rel_l2(got, ref))
+    assert rel_l2(got, ref) <= TOL
+    # per-bin bound too (the band edges carry little energy)
+    for k in range(bins.size):
+        assert rel_l2(got[..., k], ref[..., k]) <= 3 * TOL
+
+
+def test_general_y_path(S, orc):
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.5)
+    rng = np.random.default_rng(4)
+    w["phantoms"][0]["y"] = rng.uniform(-1.5e-3, 1.5e-3, w["phantoms"][0]["x"].size).astype(np.float32)
+    g, rf, data = _run(S, w, with_y=True)
+    ref = _oracle_rf(orc, w, g, data, with_y=True)
+    print("y path rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
+@pytest.mark.parametrize("baffle", [1, 2])
+def test_rigid_and_impedance_baffles(S, orc, baffle):
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.5)
+    w["probe"]["baffle"] = baffle
+    g, rf, data = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    assert rel_l2(rf, ref) <= TOL
+
+
+@pytest.mark.parametrize("n_tx", [2, 3, 5, 9])
+def test_multi_transmit(S, orc, n_tx):
+    """Steered plane waves with uneven apodisation; covers transmit groups
+    and a ragged last group."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.5)
+    ang = np.linspace(-12, 12, n_tx)
+    w["delays"] = inputs.plane_wave_delays(w["probe"], ang)
+    w["apod"] = np.random.default_rng(n_tx).uniform(0.2, 1.0, w["delays"].shape).astype(np.float32)
+    g, rf, data = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    print(n_tx, "tx rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
+def test_convex_diverging_waves_uneven_phantoms(S, orc):
+    """Convex probe, 3 diverging waves, 4 phantoms of uneven size (one
+    empty): the batched launch matches per-phantom oracle runs."""
+    from paper_2102_02738_amd import inputs
+    probe = inputs.convex_probe(48)
+    rng = np.random.default_rng(9)
+    phs = [inputs.sector_phantom(rng, n, probe["radius"], 60e-3, 30.0) for n in (37, 0, 120, 5)]
+    dl = inputs.diverging_wave_delays(probe, [-10e-3, 0.0, 12e-3], -60e-3)
+    w = dict(probe=probe, medium=dict(c=1540.0, alpha_db=0.5),
+             options=dict(fs=4 * probe["fc"], n_cycles=1.0, nu=0, spectral_eps=1e-7, nfft=0, n_t=0),
+             delays=dl, apod=np.ones(dl.shape, np.float32), phantoms=phs)
+    g, rf, data = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    assert np.all(rf[1] == 0)
+    print("convex rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+    g2, rf2, _ = _run(S, w, flags=S.FLAG_PERSISTENT)
+    assert np.array_equal(rf, rf2)
+
+
+def test_repeatable_and_persistent_bitwise(S):
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw128_s50k", scale=0.1)
+    _, a, _ = _run(S, w)
+    _, b, _ = _run(S, w)
+    _, c, _ = _run(S, w, flags=S.FLAG_PERSISTENT)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+def test_inverse_transform_full_size(S, orc):
+    """The inverse transform alone at the 128-element, 2400-point size, on a
+    seeded random spectrum, against the oracle's explicit sum."""
+    import torch
+    rng = np.random.default_rng(0)
+    nfft, n_t, j_lo, nb, nch = 2400, 1975, 120, 849, 128
+    X = (rng.standard_normal((nch, nb)) + 1j * rng.standard_normal((nch, nb))).astype(np.complex64)
+    bins = np.arange(j_lo, j_lo + nb)
+    ref = orc.rf_from_spectrum(X.astype(np.complex128), bins, nfft, n_t)
+    got = S.spectrum_to_rf(torch.from_numpy(X).cuda(), nfft, n_t, j_lo).cpu().numpy()
+    print("idft rel L2", rel_l2(got, ref))
+    assert rel_l2(got, ref) <= 1e-5
+
+
+def test_empty_and_degenerate(S):
+    import torch
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.05)
+    x, y, z, R, off = concat_phantoms(w["phantoms"])
+    g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
+    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"])
+    e = torch.empty(0, device="cuda")
+    rf = S.rf(w["probe"], w["medium"], o, w["delays"], w["apod"], e, None, e, e, offsets=[0, 0])
+    torch.cuda.synchronize()
+    assert rf.shape == (1, 1, 32, g["n_t"]) and torch.all(rf == 0)
+    # all-zero reflectivity gives exactly zero RF
+    dx, dz, dR = to_dev(x, z, np.zeros_like(R))
+    rf = S.rf(w["probe"], w["medium"], o, w["delays"], w["apod"], dx, None, dz, dR)
+    torch.cuda.synchronize()
+    assert torch.all(rf == 0)
