@@ -198,6 +198,16 @@ int simus_pfield(const simus_probe* probe, const simus_medium* medium,
  * concurrently with other calls. */
 void simus_release_workspace(void);
 
+/* Kernel timing (diagnostics).  While enabled, each kernel launch of the
+ * library is bracketed by a pair of HIP events recorded on the launch's
+ * stream.  simus_profile_read() waits for the recorded events of one kernel
+ * ("synth", "wtable", "finalize", "idft", "dft", "adjoint", "adjoint_reduce",
+ * "pfield") and returns their summed duration [ms] and launch count since
+ * the last reset.  Returns SIMUS_EINVAL for an unknown name. */
+int simus_profile_enable(int on);
+int simus_profile_read(const char* kernel, double* total_ms, int64_t* launches);
+void simus_profile_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

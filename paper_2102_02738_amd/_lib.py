@@ -23,7 +23,8 @@ FLAG_NO_DELTA_TABLE = 4
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",
            "simus_spectrum_to_rf", "simus_rf_backward", "simus_pfield_nf", "simus_pfield",
-           "simus_release_workspace"]
+           "simus_release_workspace", "simus_profile_enable", "simus_profile_read",
+           "simus_profile_reset"]
 
 
 class SimusError(RuntimeError):
@@ -84,6 +85,9 @@ def lib():
             "simus_pfield_nf": (C.c_int, [pP, pM, pO, pd, i64, pf, pf, pf, pi32]),
             "simus_pfield": (C.c_int, [pP, pM, pO, i32, pd, pf, i64, vp, vp, vp, vp, vp]),
             "simus_release_workspace": (None, []),
+            "simus_profile_enable": (C.c_int, [C.c_int]),
+            "simus_profile_read": (C.c_int, [C.c_char_p, pd, pi64]),
+            "simus_profile_reset": (None, []),
         }
         for name, (res, args) in sig.items():
             if not hasattr(L, name):
@@ -236,3 +240,19 @@ def pfield_into(p_rms, probe, medium, options, n_f, delays, apod, X, Y, Z, strea
 
 def release_workspace():
     lib().simus_release_workspace()
+
+
+def profile_enable(on: bool = True):
+    check(lib().simus_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    lib().simus_profile_reset()
+
+
+def profile_read(kernel: str):
+    """(total_ms, launches) of one library kernel since the last reset."""
+    ms = C.c_double()
+    n = C.c_int64()
+    check(lib().simus_profile_read(kernel.encode(), C.byref(ms), C.byref(n)))
+    return float(ms.value), int(n.value)

@@ -43,6 +43,11 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     subprocess.check_call([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, OUT)
+    diag = os.path.join(PKG, "diag", "valu_rate.hip")
+    if os.path.exists(diag):
+        subprocess.check_call([HIPCC, "-O3", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
+                               "-Xclang", "-packed-fp32-ops", "-o", os.path.join(PKG, "diag", "valu_rate"),
+                               diag])
     if verbose:
         print("built", OUT)
     return OUT

@@ -42,6 +42,75 @@ bool log_enabled()
     return on;
 }
 
+// ---------------------------------------------------------------- kernel timing
+enum Kind { K_SYNTH, K_WTABLE, K_FINALIZE, K_IDFT, K_DFT, K_ADJ, K_ADJRED, K_PFIELD, K_COUNT };
+const char* const kKindNames[K_COUNT] = {"synth", "wtable", "finalize", "idft",
+                                         "dft", "adjoint", "adjoint_reduce", "pfield"};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double total[K_COUNT] = {};
+    int64_t count[K_COUNT] = {};
+
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        return e;
+    }
+    // Waits for every pending record and folds it into the totals.
+    void drain()
+    {
+        for (const Rec& r : pending) {
+            float ms = 0.f;
+            hip_check(hipEventSynchronize(r.b), "hipEventSynchronize");
+            hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+            total[r.kind] += ms;
+            count[r.kind] += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+};
+
+Profiler g_prof;
+
+// Runs `launch` (which enqueues one kernel on st), bracketed by events when
+// timing is enabled.
+template <class F>
+hipError_t timed(Kind k, hipStream_t st, F&& launch)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.on) return launch();
+    }
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = g_prof.take();
+        b = g_prof.take();
+    }
+    hip_check(hipEventRecord(a, st), "hipEventRecord");
+    const hipError_t e = launch();
+    hip_check(hipEventRecord(b, st), "hipEventRecord");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({k, a, b});
+    return e;
+}
+
 // ---------------------------------------------------------------- workspace
 // One device arena and one pinned staging buffer per (device, stream).  The
 // staging buffer is rewritten only after the previous upload from it has
@@ -280,8 +349,10 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     char* d = a.dev;
     float2* W = at<float2>(d, o_W);
     float2* spec = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(d, o_spec);
-    hip_check(launch_wtable(W, at<double>(d, o_dl), at<float>(d, o_ap), F.B.n_bins, n_tx, N,
-                            F.B.j_lo, F.B.df, st),
+    hip_check(timed(K_WTABLE, st, [&] {
+                  return launch_wtable(W, at<double>(d, o_dl), at<float>(d, o_ap), F.B.n_bins, n_tx,
+                                       N, F.B.j_lo, F.B.df, st);
+              }),
               "wtable launch");
     SynthArgs A{};
     A.x = x;
@@ -323,14 +394,18 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
                      N, F.P.nu, M, n_tx, n_ph, (long long)ph.total, F.B.nfft, F.B.n_t, F.B.j_lo,
                      F.B.n_bins, BS, TT, SC, JT, F.slice, F.n_items, F.cfg.grid, (int)has_y,
                      (int)F.cfg.persistent);
-    hip_check(launch_synth(F.cfg, A, st), "synthesis launch");
-    hip_check(launch_finalize(spec, A.part, at<float2>(d, o_pw), at<int32_t>(d, o_pb),
-                              at<int32_t>(d, o_ns), n_ph, n_tx, N, F.P.nu, F.B.n_bins, BS, TT, JT,
-                              F.n_bt, st),
+    hip_check(timed(K_SYNTH, st, [&] { return launch_synth(F.cfg, A, st); }), "synthesis launch");
+    hip_check(timed(K_FINALIZE, st, [&] {
+                  return launch_finalize(spec, A.part, at<float2>(d, o_pw), at<int32_t>(d, o_pb),
+                                         at<int32_t>(d, o_ns), n_ph, n_tx, N, F.P.nu, F.B.n_bins,
+                                         BS, TT, JT, F.n_bt, st);
+              }),
               "finalize launch");
     if (rf_out) {
-        hip_check(launch_idft(rf_out, spec, int64_t(n_ph) * n_tx * N, F.B.n_bins, F.B.j_lo,
-                              F.B.nfft, F.B.n_t, st),
+        hip_check(timed(K_IDFT, st, [&] {
+                      return launch_idft(rf_out, spec, int64_t(n_ph) * n_tx * N, F.B.n_bins,
+                                         F.B.j_lo, F.B.nfft, F.B.n_t, st);
+                  }),
                   "inverse transform launch");
     }
 }
@@ -430,10 +505,49 @@ int simus_spectrum_to_rf(int32_t nfft, int32_t n_t, int32_t j_lo, int32_t n_bins
             throw Error{SIMUS_EINVAL, "bins must lie in [0, nfft/2]"};
         if (n_chan < 0) throw Error{SIMUS_EINVAL, "n_chan must be >= 0"};
         if (n_chan > 0 && n_t > 0 && (!spec || !rf)) throw Error{SIMUS_EINVAL, "spec and rf must be non-NULL"};
-        hip_check(launch_idft(rf, reinterpret_cast<const float2*>(spec), n_chan, n_bins, j_lo, nfft,
-                              n_t, static_cast<hipStream_t>(hip_stream)),
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        hip_check(timed(K_IDFT, st, [&] {
+                      return launch_idft(rf, reinterpret_cast<const float2*>(spec), n_chan, n_bins,
+                                         j_lo, nfft, n_t, st);
+                  }),
                   "inverse transform launch");
     });
+}
+
+int simus_profile_enable(int on)
+{
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        g_prof.on = on != 0;
+    });
+}
+
+int simus_profile_read(const char* kernel, double* total_ms, int64_t* launches)
+{
+    return guarded([&] {
+        if (!kernel) throw Error{SIMUS_EINVAL, "kernel name must be non-NULL"};
+        int k = -1;
+        for (int i = 0; i < K_COUNT; ++i)
+            if (std::strcmp(kernel, kKindNames[i]) == 0) k = i;
+        if (k < 0) throw Error{SIMUS_EINVAL, std::string("unknown kernel name: ") + kernel};
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        g_prof.drain();
+        if (total_ms) *total_ms = g_prof.total[k];
+        if (launches) *launches = g_prof.count[k];
+    });
+}
+
+void simus_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    try {
+        g_prof.drain();
+    } catch (...) {
+    }
+    for (int i = 0; i < K_COUNT; ++i) {
+        g_prof.total[i] = 0;
+        g_prof.count[i] = 0;
+    }
 }
 
 void simus_release_workspace(void)
