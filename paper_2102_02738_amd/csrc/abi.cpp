@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "eq18.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "simus.h"
@@ -207,10 +208,10 @@ ModelConst model_constants(const Probe& P, const Band& B)
     K.zeta = (float)P.zeta;
     K.baffle = P.baffle;
     // Eq. (18): A_3 = conj(A_1), B_3 = conj(B_1), A_4 = conj(A_2), B_4 = conj(B_2).
-    const double Ar[4] = {0.187, 0.288, 0.187, 0.288};
-    const double Ai[4] = {0.275, -1.954, -0.275, 1.954};
-    const double Br[4] = {4.558, 8.598, 4.558, 8.598};
-    const double Bi[4] = {-25.59, -7.924, 25.59, 7.924};
+    using eq18::Ar;
+    using eq18::Ai;
+    using eq18::Br;
+    using eq18::Bi;
     const double h2 = P.height * P.height;
     const double sq_pi = std::sqrt(M_PI);
     for (int g = 0; g < 4; ++g) {
@@ -319,6 +320,9 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     const size_t o_W = dv.add(sizeof(float2) * size_t(std::max(F.B.n_bins, 1)) * n_tx * N);
     const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(F.n_items, 1)) * JT * TT * BS);
     const size_t o_tk = dv.add(sizeof(int32_t) * 4);
+    const size_t o_rr = dv.add(sizeof(uint32_t) * 4);
+    const size_t o_dt = dv.add(sizeof(float4) * 2 * DELTA_NT);
+    const size_t o_dp = dv.add(sizeof(DeltaParams));
     const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(F.B.n_bins, 1);
     const size_t o_spec = spec_out ? 0 : dv.add(spec_bytes);
 
@@ -373,6 +377,17 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     A.j_lo = F.B.j_lo;
     A.K = model_constants(F.P, F.B);
     A.ticket = nullptr;
+    F.cfg.table = !has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
+    A.dtab = nullptr;
+    A.dpar = nullptr;
+    if (F.cfg.table) {
+        A.dtab = at<float4>(d, o_dt);
+        A.dpar = at<DeltaParams>(d, o_dp);
+        hip_check(launch_rrange(at<uint32_t>(d, o_rr), x, y, z, ph.total, A.sub, M, st), "range launch");
+        hip_check(launch_dtable(at<float4>(d, o_dt), at<DeltaParams>(d, o_dp), at<uint32_t>(d, o_rr),
+                                A.K, F.P.height, F.B.j_lo, F.B.j_lo + std::max(F.B.n_bins, 1) - 1, st),
+                  "table launch");
+    }
     F.cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
     if (F.cfg.persistent && F.n_items > 0) {
         A.ticket = at<int32_t>(d, o_tk);
@@ -390,10 +405,10 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     if (log_enabled())
         std::fprintf(stderr,
                      "[simus] N=%d nu=%d M=%d T=%d P=%d S=%lld nfft=%d n_t=%d j_lo=%d bins=%d "
-                     "BS=%d TT=%d SC=%d JT=%d slice=%d items=%d grid=%d y=%d persistent=%d\n",
+                     "BS=%d TT=%d SC=%d JT=%d slice=%d items=%d grid=%d y=%d table=%d persistent=%d\n",
                      N, F.P.nu, M, n_tx, n_ph, (long long)ph.total, F.B.nfft, F.B.n_t, F.B.j_lo,
                      F.B.n_bins, BS, TT, SC, JT, F.slice, F.n_items, F.cfg.grid, (int)has_y,
-                     (int)F.cfg.persistent);
+                     (int)F.cfg.table, (int)F.cfg.persistent);
     hip_check(timed(K_SYNTH, st, [&] { return launch_synth(F.cfg, A, st); }), "synthesis launch");
     hip_check(timed(K_FINALIZE, st, [&] {
                   return launch_finalize(spec, A.part, at<float2>(d, o_pw), at<int32_t>(d, o_pb),

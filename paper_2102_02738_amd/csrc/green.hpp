@@ -3,12 +3,18 @@
 //
 //   G(f_j) = exp(i k r) exp(-k_a r) / r * D(theta, k) * delta(y, r, k)
 //
-// Frequency-independent geometry is computed once per (sub-element,
-// scatterer) pair (struct Geo); each bin then costs a handful of
-// transcendentals.  The phase k r is carried as an unsigned 32-bit fixed
-// point fraction of a turn: its start is reduced in FP64 from r * j df / c,
-// and each next bin adds the FP64-rounded per-bin increment, so the only
-// phase error is the rounding of the increment times the bins walked.
+// A (sub-element, scatterer) pair is set up once per tile of consecutive
+// bins (struct Geo), and each next bin is then reached by recurrences:
+//   - E_j = (obliquity / r) exp((i k_j - k_a,j) r) is a rotor: E_{j+1} = E_j dE.
+//     Its start and step phases are reduced in FP64 from r j df / c, so the
+//     only error is the FP32 rounding of the rotor over the tile's bins.
+//   - s_j = sin(j theta) / theta (sinc(j theta) = s_j / j, theta = 2 pi df
+//     b_sub sin(t) / c) follows the second-order recurrence
+//     d_{j+1} = d_j + lambda s_j, s_{j+1} = s_j + d_{j+1}, lambda = -(theta
+//     sinc(theta/2))^2, which stays accurate for small theta.
+//   - delta(0, r, k) depends on r and k only through q = (k/2)(1/R_f - 1/r);
+//     for y = 0 it is read from a cubic table in w = q / (|q| + L) built for
+//     the call's range of q (DeltaTable); otherwise it is evaluated directly.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,18 +32,8 @@ __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_ex
 __device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Fraction of a turn (x >= 0 or < 0) as a 2^-32 fixed point word.
-__device__ __forceinline__ uint32_t turns_fixed(double x)
-{
-    const double fr = x - floor(x);                       // [0, 1)
-    return (uint32_t)(unsigned long long)rint(fr * 4294967296.0);
-}
-
-// Fixed-point phase -> turns in [-0.5, 0.5).
-__device__ __forceinline__ float fixed_turns(uint32_t p)
-{
-    return (float)(int32_t)p * 2.3283064365386963e-10f;
-}
+// Fraction of a turn as a float in [0, 1), reduced in FP64.
+__device__ __forceinline__ float frac_turns(double x) { return (float)(x - floor(x)); }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
@@ -53,16 +49,31 @@ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c)
     return c;
 }
 
-// Frequency-independent part of one (sub-element, scatterer) pair.
+// sin(x)/x for the set-up: Taylor series to x^12 for |x| < 1 (remainder
+// below 2e-10), hardware sine above.
+__device__ __forceinline__ float sinc_setup(float x)
+{
+    const float x2 = x * x;
+    float p = fmaf(x2, 1.6059043836821613e-10f, -2.5052108385441720e-08f);
+    p = fmaf(x2, p, 2.7557319223985893e-06f);
+    p = fmaf(x2, p, -1.9841269841269841e-04f);
+    p = fmaf(x2, p, 8.3333333333333333e-03f);
+    p = fmaf(x2, p, -1.6666666666666667e-01f);
+    p = fmaf(x2, p, 1.0f);
+    if (fabsf(x) < 1.f) return p;
+    return sin_turns(x * 0.15915494309189535f) / x;
+}
+
+// State of one (sub-element, scatterer) pair at the current bin.
 struct Geo {
-    uint32_t ph;   // phase of exp(i k r) at the current bin, 2^-32 turns
-    uint32_t dph;  // phase increment per bin
-    float amp;     // obliquity / r, 0 behind the face
-    float att;     // log2 attenuation per bin index
-    float sig;     // sinc argument (turns) per bin index
-    float kap;     // Im(alpha) shift per bin index
-    float yr2;     // y^2 / r^2       (y != 0 path)
-    float y2r;     // y^2 / (2 r)     (y != 0 path)
+    float2 E;     // (obliquity / r) exp((i k - k_a) r)
+    float2 dE;    // per-bin factor of E
+    float s;      // sin(j theta) / theta
+    float d;      // s_j - s_{j-1}
+    float lam;    // -(theta sinc(theta/2))^2
+    float kap;    // q per bin index: q_j = j kap
+    float yr2;    // y^2 / r^2        (y != 0 path)
+    float y2r;    // y^2 / (2 r)      (y != 0 path)
 };
 
 struct SubFrame {
@@ -82,11 +93,11 @@ __device__ __forceinline__ SubFrame load_frame(const SubGeo& g, int n)
     return f;
 }
 
-// Local geometry: distance r (FP64), azimuthal angle theta of the point
-// seen from the sub-element face (Eq. 23), obliquity factor of Eq. (39).
+// Set-up of a pair at bin j0: distance r in FP64, azimuthal angle theta of
+// the point seen from the sub-element face (Eq. 23), obliquity of Eq. (39).
 template <bool HASY>
 __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, float px, float py,
-                                        float pz, int j_first)
+                                        float pz, int j0)
 {
     const double dx = (double)px - f.xc;
     const double dz = (double)pz - f.zc;
@@ -104,14 +115,27 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     float obl = ct;                                        // soft baffle
     if (K.baffle == 1) obl = 1.f;                          // rigid
     else if (K.baffle == 2) obl = ct / (ct + K.zeta);      // finite impedance
-    Geo g;
     const float inv_r = 1.f / rf;
-    g.amp = ok ? obl * inv_r : 0.f;
+    const float amp = ok ? obl * inv_r : 0.f;
+    const float jf0 = (float)j0;
+
+    Geo g;
+    // rotor: phase (turns) r j df / c reduced in FP64; attenuation exp2(j a1)
     const double tpb = r * K.turns_per_bin_m;
-    g.ph = turns_fixed(tpb * (double)j_first);
-    g.dph = turns_fixed(tpb);
-    g.att = K.att_per_bin_m * rf;
-    g.sig = K.sinc_per_bin * st;
+    const float t0 = frac_turns(tpb * (double)j0);
+    const float dt = frac_turns(tpb);
+    const float a1 = K.att_per_bin_m * rf;
+    const float m0 = amp * exp2_fast(jf0 * a1);
+    const float m1 = exp2_fast(a1);
+    g.E = make_float2(m0 * cos_turns(t0), m0 * sin_turns(t0));
+    g.dE = make_float2(m1 * cos_turns(dt), m1 * sin_turns(dt));
+    // sinc recurrence, theta = 2 pi sigma, sigma = df b_sub sin(t) / c (turns per bin)
+    const float sigma = K.sinc_per_bin * st;
+    const float theta = 6.283185307179586f * sigma;
+    const float sh = sinc_setup(0.5f * theta);
+    g.s = jf0 * sinc_setup(jf0 * theta);
+    g.d = cos_turns((jf0 - 0.5f) * sigma) * sh;
+    g.lam = -(theta * sh) * (theta * sh);
     g.kap = K.q_per_bin * (K.inv_rf - inv_r);
     if (HASY) {
         const float yf = py;
@@ -125,8 +149,8 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
 }
 
 // Elevation term delta (Eqs. 14-16) for the four Gaussians of Eq. (18),
-// alpha_g = a_g + i (b_g + q).  alpha^{-1/2} is formed without trig:
-// sqrt(alpha) = s + i b/(2 s), s = sqrt((|alpha| + a)/2), and
+// alpha_g = a_g + i (b_g + q), evaluated directly.  alpha^{-1/2} is formed
+// without trig: sqrt(alpha) = s + i b/(2 s), s = sqrt((|alpha| + a)/2),
 // alpha^{-1/2} = conj(sqrt(alpha)) / |alpha|.  For y != 0 each term is
 // multiplied by exp(beta^2 / (4 alpha) + gamma), beta^2 = -k^2 y^2 / r^2,
 // gamma = i k y^2 / (2 r).
@@ -145,8 +169,7 @@ __device__ __forceinline__ float2 elevation(const Gauss4& G, float q, float k, f
         float zr = x * rx * inv_mod;              // Re alpha^{-1/2}
         float zi = -0.5f * bi * rx * inv_mod;     // Im alpha^{-1/2}
         if (HASY) {
-            // 1/alpha = (alpha^{-1/2})^2
-            const float ar = zr * zr - zi * zi, ai = 2.f * zr * zi;
+            const float ar = zr * zr - zi * zi, ai = 2.f * zr * zi;   // 1/alpha
             const float c0 = -0.25f * k * k * yr2;
             const float er = c0 * ar;
             const float ei = c0 * ai + k * y2r;   // radians
@@ -166,21 +189,41 @@ __device__ __forceinline__ float2 elevation(const Gauss4& G, float q, float k, f
     return make_float2(dr, di);
 }
 
-// Green's term at absolute bin j (jf = j as float); advances the phase.
-template <bool HASY>
-__device__ __forceinline__ float2 green_step(const ModelConst& K, Geo& g, float jf)
+// Cubic table of delta(0, r, k) as a function of w = q / (|q| + L):
+// interval k of DELTA_NT holds (c0, c1, c2, c3) complex, delta = c0 + t (c1
+// + t (c2 + t c3)), t in [0, 1).  Stored as two float4 per interval.
+__device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaParams& P, float q)
 {
-    const float pt = fixed_turns(g.ph);
-    g.ph += g.dph;
-    const float cs = cos_turns(pt), sn = sin_turns(pt);
-    const float ea = exp2_fast(jf * g.att);
-    const float v = jf * g.sig;
-    const float snc = (v == 0.f) ? 1.f : sin_turns(v) * rcp_fast(6.283185307179586f * v);
-    const float a = g.amp * ea * snc;
+    const float w = q * rcp_fast(fabsf(q) + P.L);
+    const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
+    const float kf = floorf(u);
+    const float t = u - kf;
+    const int k = (int)kf;
+    const float4 a = tab[2 * k], b = tab[2 * k + 1];
+    float re = fmaf(t, b.z, b.x), im = fmaf(t, b.w, b.y);
+    re = fmaf(t, re, a.z);
+    im = fmaf(t, im, a.w);
+    re = fmaf(t, re, a.x);
+    im = fmaf(t, im, a.y);
+    return make_float2(re, im);
+}
+
+// Green's term at absolute bin j (jf = j, inv_j = 1/j); advances the pair to
+// bin j + 1.
+template <bool HASY, bool TABLE>
+__device__ __forceinline__ float2 green_next(const ModelConst& K, Geo& g, float jf, float inv_j,
+                                             const float4* tab, const DeltaParams& P)
+{
+    const float sn = g.s * inv_j;                         // sinc(j theta)
+    const float2 A = make_float2(g.E.x * sn, g.E.y * sn);
     const float q = jf * g.kap;
-    const float2 d = elevation<HASY>(K.g, q, jf * K.k_per_bin, g.yr2, g.y2r);
-    const float pr = a * cs, pi = a * sn;
-    return make_float2(pr * d.x - pi * d.y, pr * d.y + pi * d.x);
+    float2 d;
+    if (TABLE) d = delta_table(tab, P, q);
+    else d = elevation<HASY>(K.g, q, jf * K.k_per_bin, g.yr2, g.y2r);
+    g.E = cmul(g.E, g.dE);
+    g.d = fmaf(g.lam, g.s, g.d);
+    g.s += g.d;
+    return cmul(A, d);
 }
 
 }  // namespace simus

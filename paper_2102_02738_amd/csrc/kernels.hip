@@ -54,7 +54,7 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 // The per-sub-element partials of every item go to `part`; the finaliser
 // sums them over items and over the nu sub-elements of each element.
 // ---------------------------------------------------------------------------
-template <int BS, int SC, int JT, int TT, bool HASY>
+template <int BS, int SC, int JT, int TT, bool HASY, bool TABLE>
 __global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
 {
     constexpr int NS = SC * TT;            // sums per bin
@@ -67,11 +67,17 @@ __global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
     __shared__ float2 s_red[NS * RS];
     __shared__ float2 s_c[NS];
     __shared__ float2 s_acc[JT * TT * BS];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
     const int tid = threadIdx.x;
     const bool active = tid < A.M;
     const SubFrame fr = load_frame(A.sub, active ? tid : 0);
     const int e = active ? tid / A.nu : 0;
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += BS) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
 
     // Static launch: one item per block.  Persistent launch: blocks draw
     // items from a work counter until it passes n_items (every block exits).
@@ -104,14 +110,15 @@ __global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
             for (int s = 0; s < SC; ++s) {
                 const float4 v = s_sc[s];
                 g[s] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
-                if (!active) g[s].amp = 0.f;
+                if (!active) g[s].E = make_float2(0.f, 0.f);
             }
             for (int jj = 0; jj < nb; ++jj) {
                 const int jb = jb0 + jj;
                 const float jf = (float)(A.j_lo + jb);
+                const float inv_j = rcp_fast(jf);
                 float2 G[SC];
 #pragma unroll
-                for (int s = 0; s < SC; ++s) G[s] = green_step<HASY>(A.K, g[s], jf);
+                for (int s = 0; s < SC; ++s) G[s] = green_next<HASY, TABLE>(A.K, g[s], jf, inv_j, s_tab, P);
                 float2 W[TT];
 #pragma unroll
                 for (int t = 0; t < TT; ++t) {
@@ -188,9 +195,11 @@ template <int BS, int SC, int JT, int TT>
 static hipError_t launch_synth_y(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
 {
     if (cfg.has_y)
-        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, true>), dim3(cfg.grid), dim3(BS), 0, st, a);
+        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, true, false>), dim3(cfg.grid), dim3(BS), 0, st, a);
+    else if (cfg.table)
+        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, false, true>), dim3(cfg.grid), dim3(BS), 0, st, a);
     else
-        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, false>), dim3(cfg.grid), dim3(BS), 0, st, a);
+        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, false, false>), dim3(cfg.grid), dim3(BS), 0, st, a);
     return hipGetLastError();
 }
 

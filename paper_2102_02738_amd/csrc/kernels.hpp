@@ -30,6 +30,16 @@ struct ModelConst {
     Gauss4 g;
 };
 
+// Elevation-term table (y = 0): DELTA_NT cubic intervals in w = q / (|q| + L).
+constexpr int DELTA_NT = 512;
+
+struct DeltaParams {
+    float L;       // map scale
+    float u0;      // -w_lo / dw
+    float inv_dw;  // 1 / dw
+    float umax;    // DELTA_NT - 2^-8
+};
+
 // Sub-element frames, device arrays of length M = nu N.
 struct SubGeo {
     const double* xc;
@@ -60,6 +70,8 @@ struct SynthArgs {
     int32_t n_items;
     int32_t* ticket;    // persistent launch: work counter (zeroed before launch)
     float2* part;       // [n_items][JT][TT][BS] per-sub-element partial spectra
+    const float4* dtab; // [2 * DELTA_NT] elevation table (y = 0 path), or null
+    const DeltaParams* dpar;
     int32_t M, nu, N, n_tx, n_bins, j_lo;
     ModelConst K;
 };
@@ -70,6 +82,7 @@ struct SynthConfig {
     int sc;      // scatterers per chunk
     int jt;      // bins per tile
     bool has_y;
+    bool table;  // elevation term from the table (requires !has_y)
     bool persistent;
     int grid;    // blocks launched (persistent: resident blocks)
 };
@@ -89,5 +102,13 @@ hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins
 hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,
                       int nfft, int n_t, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
+
+// Range of sub-element-to-scatterer distances (as float bits, [0] = min,
+// [1] = max) over all pairs, then the elevation table for the call's range
+// of q = (pi f / c)(1/R_f - 1/r), f over the evaluated band.
+hipError_t launch_rrange(uint32_t* rr, const float* x, const float* y, const float* z, int64_t n,
+                         const SubGeo& sub, int M, hipStream_t st);
+hipError_t launch_dtable(float4* tab, DeltaParams* par, const uint32_t* rr, const ModelConst& K,
+                         double height, int j_first, int j_last, hipStream_t st);
 
 }  // namespace simus

@@ -60,12 +60,14 @@ def test_rf_pw32_s200_full(S, orc):
     assert rel_l2(rf, ref) <= TOL
 
 
-def test_rf_pw128_small_full(S, orc):
+@pytest.mark.parametrize("direct", [False, True])
+def test_rf_pw128_small_full(S, orc, direct):
     """128 elements, anechoic disks, attenuation, 50 mm depth, 1000 scatterers:
-    full RF parity (several scatter tiles, ragged tail, n_t < nfft)."""
+    full RF parity (several scatter tiles, ragged tail, n_t < nfft), with the
+    tabulated and with the directly evaluated elevation term."""
     from paper_2102_02738_amd import inputs
     w = inputs.workload("pw128_s50k", scale=0.02)
-    g, rf, data = _run(S, w)
+    g, rf, data = _run(S, w, flags=S.FLAG_NO_DELTA_TABLE if direct else 0)
     assert g["n_t"] == 1975
     ref = _oracle_rf(orc, w, g, data)
     print("pw128 1000 rel L2", rel_l2(rf, ref))
