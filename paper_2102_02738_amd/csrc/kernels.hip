@@ -46,26 +46,76 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 // walks the scatterers of one work item in chunks of SC.  For each bin of
 // its tile it
 //   1. builds G[n][s] for the chunk in registers (Green's term, green.hpp),
-//   2. Tx contraction a[s][t] = sum_n W[t][e(n)] G[n][s]: the products go
-//      to LDS and groups of lanes reduce them (no atomics),
+//   2. Tx contraction a[s][t] = sum_n W[t][e(n)] G[n][s]: neighbouring lanes
+//      are summed with DPP, the pair sums go to LDS and groups of lanes
+//      reduce them (no atomics, fixed order),
 //   3. scales by the reflectivity, c[s][t] = R_s a[s][t],
 //   4. Rx contraction X_sub[n][t] += sum_s G[n][s] c[s][t], accumulated per
 //      sub-element in an LDS slot private to the thread.
-// The per-sub-element partials of every item go to `part`; the finaliser
-// sums them over items and over the nu sub-elements of each element.
+// Steps 2-3 of bin j and step 4 of bin j-1 share one barrier: the reduction
+// rows and the reduced values are double-buffered, and G of bin j-1 stays in
+// registers.  The per-sub-element partials of every item go to `part`; the
+// finaliser sums them over items and over the nu sub-elements of each element.
 // ---------------------------------------------------------------------------
+
+// Tunables of the synthesis launch (compile-time): scatterers per chunk for
+// single-transmit groups, longest bin tile, and a waves-per-SIMD floor.
+#ifndef SIMUS_SC1
+#define SIMUS_SC1 8
+#endif
+#ifndef SIMUS_JT_MAX
+#define SIMUS_JT_MAX 16
+#endif
+#ifndef SIMUS_WAVES_PER_EU
+#define SIMUS_WAVES_PER_EU 0
+#endif
+#if SIMUS_WAVES_PER_EU > 0
+#define SIMUS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SIMUS_WAVES_PER_EU)))
+#else
+#define SIMUS_OCCUPANCY
+#endif
+
+// DPP lane exchanges within rows of 16 lanes (gfx9 encodings).
+enum : int {
+    DPP_XOR1 = 0xB1,          // quad_perm [1,0,3,2]
+    DPP_XOR2 = 0x4E,          // quad_perm [2,3,0,1]
+    DPP_HALF_MIRROR = 0x141,  // lane i <-> 7 - i within 8
+    DPP_MIRROR = 0x140        // lane i <-> 15 - i within 16
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over an aligned group of GL lanes (GL a power of two <= 64); every
+// lane of the group receives the total.
+template <int GL>
+__device__ __forceinline__ float group_sum(float v)
+{
+    if (GL >= 2) v += dpp<DPP_XOR1>(v);
+    if (GL >= 4) v += dpp<DPP_XOR2>(v);
+    if (GL >= 8) v += dpp<DPP_HALF_MIRROR>(v);
+    if (GL >= 16) v += dpp<DPP_MIRROR>(v);
+    if (GL >= 32) v += __shfl_xor(v, 16);
+    if (GL >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
 template <int BS, int SC, int JT, int TT, bool HASY, bool TABLE>
-__global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
+__global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 {
     constexpr int NS = SC * TT;            // sums per bin
-    constexpr int RS = BS + 4;             // LDS row stride (float2)
-    constexpr int GL = (BS / NS >= 64) ? 64 : BS / NS;   // lanes per sum
-    constexpr int PER = BS / GL;           // values per lane
-    static_assert(NS <= BS, "chunk x transmit group must not exceed the block");
+    constexpr int HB = BS / 2;             // pair sums per row
+    constexpr int RS = HB + 4;             // LDS row stride (float2)
+    constexpr int GL = (HB / NS >= 64) ? 64 : HB / NS;   // lanes per sum
+    constexpr int PER = HB / GL;           // values per lane
+    static_assert(NS <= HB, "chunk x transmit group must not exceed half the block");
 
     __shared__ float4 s_sc[SC];
-    __shared__ float2 s_red[NS * RS];
-    __shared__ float2 s_c[NS];
+    __shared__ float2 s_red[2][NS * RS];
+    __shared__ float2 s_c[2][NS];
     __shared__ float2 s_acc[JT * TT * BS];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
@@ -78,6 +128,48 @@ __global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
         for (int i = tid; i < 2 * DELTA_NT; i += BS) s_tab[i] = A.dtab[i];
         P = *A.dpar;
     }
+
+    // Tx reduction of one bin: rows s_red[buf] -> s_c[buf] (R_s applied).
+    auto reduce = [&](int buf) {
+        const int sid = tid / GL, lg = tid % GL;
+        if (sid < NS) {
+            // two independent partial sums shorten the dependency chain
+            float2 acc = make_float2(0.f, 0.f), acc2 = make_float2(0.f, 0.f);
+            const float2* row = &s_red[buf][sid * RS];
+#pragma unroll
+            for (int i = 0; i < PER; i += 2) {
+                const float2 v = row[lg + i * GL];
+                acc.x += v.x;
+                acc.y += v.y;
+                if (i + 1 < PER) {
+                    const float2 u = row[lg + (i + 1) * GL];
+                    acc2.x += u.x;
+                    acc2.y += u.y;
+                }
+            }
+            acc.x += acc2.x;
+            acc.y += acc2.y;
+            acc.x = group_sum<GL>(acc.x);
+            acc.y = group_sum<GL>(acc.y);
+            if (lg == 0) {
+                const float R = s_sc[sid % SC].w;
+                s_c[buf][sid] = make_float2(R * acc.x, R * acc.y);
+            }
+        }
+    };
+    // Rx accumulation of local bin jj from s_c[buf].
+    auto receive = [&](int jj, int buf, const float2* G) {
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+            float2 x = s_acc[(jj * TT + t) * BS + tid], y = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int s = 0; s < SC; s += 2) {
+                x = cfma(G[s], s_c[buf][t * SC + s], x);
+                if (s + 1 < SC) y = cfma(G[s + 1], s_c[buf][t * SC + s + 1], y);
+            }
+            s_acc[(jj * TT + t) * BS + tid] = make_float2(x.x + y.x, x.y + y.y);
+        }
+    };
 
     // Static launch: one item per block.  Persistent launch: blocks draw
     // items from a work counter until it passes n_items (every block exits).
@@ -112,8 +204,10 @@ __global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
                 g[s] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g[s].E = make_float2(0.f, 0.f);
             }
+            float2 Gp[SC];
             for (int jj = 0; jj < nb; ++jj) {
                 const int jb = jb0 + jj;
+                const int buf = jj & 1;
                 const float jf = (float)(A.j_lo + jb);
                 const float inv_j = rcp_fast(jf);
                 float2 G[SC];
@@ -128,39 +222,20 @@ __global__ __launch_bounds__(BS) void k_synth(SynthArgs A)
 #pragma unroll
                 for (int t = 0; t < TT; ++t)
 #pragma unroll
-                    for (int s = 0; s < SC; ++s) s_red[(t * SC + s) * RS + tid] = cmul(W[t], G[s]);
-                __syncthreads();
-                {
-                    const int sid = tid / GL, lg = tid % GL;
-                    if (sid < NS) {
-                        float2 acc = make_float2(0.f, 0.f);
-                        const float2* row = &s_red[sid * RS];
-#pragma unroll
-                        for (int i = 0; i < PER; ++i) {
-                            const float2 v = row[lg + i * GL];
-                            acc.x += v.x;
-                            acc.y += v.y;
-                        }
-#pragma unroll
-                        for (int off = GL / 2; off > 0; off >>= 1) {
-                            acc.x += __shfl_xor(acc.x, off);
-                            acc.y += __shfl_xor(acc.y, off);
-                        }
-                        if (lg == 0) {
-                            const float R = s_sc[sid % SC].w;
-                            s_c[sid] = make_float2(R * acc.x, R * acc.y);
-                        }
+                    for (int s = 0; s < SC; ++s) {
+                        float2 p = cmul(W[t], G[s]);
+                        p.x += dpp<DPP_XOR1>(p.x);
+                        p.y += dpp<DPP_XOR1>(p.y);
+                        if (!(tid & 1)) s_red[buf][(t * SC + s) * RS + (tid >> 1)] = p;
                     }
-                }
                 __syncthreads();
+                reduce(buf);
+                if (jj > 0) receive(jj - 1, buf ^ 1, Gp);
 #pragma unroll
-                for (int t = 0; t < TT; ++t) {
-                    float2 x = s_acc[(jj * TT + t) * BS + tid];
-#pragma unroll
-                    for (int s = 0; s < SC; ++s) x = cfma(G[s], s_c[t * SC + s], x);
-                    s_acc[(jj * TT + t) * BS + tid] = x;
-                }
+                for (int s = 0; s < SC; ++s) Gp[s] = G[s];
             }
+            __syncthreads();
+            if (nb > 0) receive(nb - 1, (nb - 1) & 1, Gp);
             __syncthreads();
         }
         float2* out = A.part + (int64_t)item * (JT * TT * BS);
@@ -182,9 +257,9 @@ SynthConfig synth_config(int M, int n_tx, bool has_y)
     c.bs = bs;
     c.tt = n_tx >= 8 ? 8 : n_tx >= 4 ? 4 : n_tx >= 2 ? 2 : 1;
     if (bs > 512 && c.tt > 4) c.tt = 4;     // LDS: reduction rows + accumulators
-    c.sc = c.tt >= 4 ? 2 : (c.tt == 2 ? 4 : 8);
+    c.sc = c.tt >= 4 ? 2 : (c.tt == 2 ? 4 : SIMUS_SC1);
     // s_acc (JT * TT * BS float2) kept within 64 KiB
-    int jt = 16;
+    int jt = SIMUS_JT_MAX;
     while (jt > 1 && jt * c.tt * bs * 8 > 65536) jt /= 2;
     c.jt = jt;
     c.has_y = has_y;
@@ -206,12 +281,13 @@ static hipError_t launch_synth_y(const SynthConfig& cfg, const SynthArgs& a, hip
 template <int BS>
 static hipError_t launch_synth_bs(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
 {
-    constexpr int J1 = (16 * 1 * BS * 8 <= 65536) ? 16 : 65536 / (8 * BS);
-    constexpr int J2 = (16 * 2 * BS * 8 <= 65536) ? 16 : 65536 / (16 * BS);
-    constexpr int J4 = (16 * 4 * BS * 8 <= 65536) ? 16 : 65536 / (32 * BS);
-    constexpr int J8 = (16 * 8 * BS * 8 <= 65536) ? 16 : 65536 / (64 * BS);
+    constexpr int JM = SIMUS_JT_MAX;
+    constexpr int J1 = (JM * 1 * BS * 8 <= 65536) ? JM : 65536 / (8 * BS);
+    constexpr int J2 = (JM * 2 * BS * 8 <= 65536) ? JM : 65536 / (16 * BS);
+    constexpr int J4 = (JM * 4 * BS * 8 <= 65536) ? JM : 65536 / (32 * BS);
+    constexpr int J8 = (JM * 8 * BS * 8 <= 65536) ? JM : 65536 / (64 * BS);
     switch (cfg.tt) {
-    case 1: return launch_synth_y<BS, 8, J1, 1>(cfg, a, st);
+    case 1: return launch_synth_y<BS, SIMUS_SC1, J1, 1>(cfg, a, st);
     case 2: return launch_synth_y<BS, 4, J2, 2>(cfg, a, st);
     case 4: return launch_synth_y<BS, 2, J4, 4>(cfg, a, st);
     case 8:
