@@ -204,6 +204,8 @@ ModelConst model_constants(const Probe& P, const Band& B)
     K.sinc_per_bin = (float)(df * (0.5 * P.width / P.nu) / P.c);
     K.q_per_bin = (float)(M_PI * df / P.c);
     K.k_per_bin = (float)(2 * M_PI * df / P.c);
+    K.ka_per_bin = (float)((P.alpha_db / 8.69) * (df / 1e4));
+    K.b_sub = (float)(0.5 * P.width / P.nu);
     K.inv_rf = std::isinf(P.elev_focus) ? 0.f : (float)(1.0 / P.elev_focus);
     K.zeta = (float)P.zeta;
     K.baffle = P.baffle;
@@ -245,184 +247,413 @@ Phantoms check_phantoms(int32_t n_ph, const int64_t* offs)
     return ph;
 }
 
-// ---------------------------------------------------------------- forward spectra
-struct Forward {
+// ---------------------------------------------------------------- common preparation
+// Validated call description shared by the forward and adjoint paths.
+struct Common {
     Probe P;
     Band B;
-    SynthConfig cfg;
-    int n_tx = 0, n_bt = 0, n_tg = 0, slice = 0, n_items = 0;
+    SubElements S;
+    Phantoms ph;
+    ModelConst K;
+    int n_tx = 0;
+    bool has_y = false, table = false;
 };
 
-// Plans and enqueues the spectra; writes spec (device [P][T][N][n_bins] float2).
-// If spec_out is null, spectra go to a workspace buffer whose pointer is
-// returned through *spec_ws together with the arena.
+Common make_common(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+                   int32_t n_tx, const double* delays, const float* apod, int32_t n_ph,
+                   const int64_t* offs, const float* x, const float* y, const float* z,
+                   const float* refl)
+{
+    Common C;
+    C.P = make_probe(probe, medium, opt);
+    check_transmits(C.P, n_tx, delays, apod);
+    C.ph = check_phantoms(n_ph, offs);
+    if (opt->nfft <= 0) throw Error{SIMUS_EINVAL, "options.nfft must be > 0 (see simus_rf_grid)"};
+    if (opt->n_t > opt->nfft) throw Error{SIMUS_EINVAL, "options.n_t must be <= nfft"};
+    if (C.ph.total > 0 && (!x || !z || !refl)) throw Error{SIMUS_EINVAL, "x, z and refl must be non-NULL"};
+    C.B = make_band(C.P, opt->nfft, opt->n_t);
+    C.S = sub_elements(C.P);
+    C.K = model_constants(C.P, C.B);
+    C.n_tx = n_tx;
+    C.has_y = y != nullptr;
+    C.table = !C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
+    return C;
+}
+
+// Host tables uploaded by every call, and device tables built on the device.
+struct CommonLayout {
+    size_t xc, zc, tx, tz, nx, nz, dl, ap, pw;   // upload region
+    size_t W, rr, dt, dp;                        // device-only region
+};
+
+void layout_upload(Layout& up, CommonLayout& L, const Common& C)
+{
+    const int M = C.P.M, TN = C.n_tx * C.P.N;
+    L.xc = up.add(sizeof(double) * M);
+    L.zc = up.add(sizeof(double) * M);
+    L.tx = up.add(sizeof(float) * M);
+    L.tz = up.add(sizeof(float) * M);
+    L.nx = up.add(sizeof(float) * M);
+    L.nz = up.add(sizeof(float) * M);
+    L.dl = up.add(sizeof(double) * TN);
+    L.ap = up.add(sizeof(float) * TN);
+    L.pw = up.add(sizeof(float2) * std::max(C.B.n_bins, 1));
+}
+
+void layout_device(Layout& dv, CommonLayout& L, const Common& C)
+{
+    L.W = dv.add(sizeof(float2) * size_t(std::max(C.B.n_bins, 1)) * C.n_tx * C.P.N);
+    L.rr = dv.add(sizeof(uint32_t) * 4);
+    L.dt = dv.add(sizeof(float4) * 2 * DELTA_NT);
+    L.dp = dv.add(sizeof(DeltaParams));
+}
+
+void fill_upload(char* h, const CommonLayout& L, const Common& C, const double* delays,
+                 const float* apod)
+{
+    for (int m = 0; m < C.P.M; ++m) {
+        at<double>(h, L.xc)[m] = C.S.xc[m];
+        at<double>(h, L.zc)[m] = C.S.zc[m];
+        at<float>(h, L.tx)[m] = (float)C.S.tx[m];
+        at<float>(h, L.tz)[m] = (float)C.S.tz[m];
+        at<float>(h, L.nx)[m] = (float)C.S.nx[m];
+        at<float>(h, L.nz)[m] = (float)C.S.nz[m];
+    }
+    for (int i = 0; i < C.n_tx * C.P.N; ++i) {
+        at<double>(h, L.dl)[i] = delays[i];
+        at<float>(h, L.ap)[i] = apod ? apod[i] : 1.f;
+    }
+    for (int b = 0; b < C.B.n_bins; ++b) {
+        const double w = 2 * M_PI * (C.B.j_lo + b) * C.B.df;
+        const std::complex<double> v = pulse_spectrum(C.P, w) * transducer_spectrum(C.P, w);
+        at<float2>(h, L.pw)[b] = make_float2((float)v.real(), (float)v.imag());
+    }
+}
+
+SubGeo sub_geo(char* d, const CommonLayout& L)
+{
+    return SubGeo{at<double>(d, L.xc), at<double>(d, L.zc), at<float>(d, L.tx),
+                  at<float>(d, L.tz), at<float>(d, L.nx), at<float>(d, L.nz)};
+}
+
+// Transmit weights, and for y = 0 the elevation table of the call.
+void launch_common(char* d, const CommonLayout& L, const Common& C, const float* x, const float* y,
+                   const float* z, hipStream_t st)
+{
+    hip_check(timed(K_WTABLE, st, [&] {
+                  return launch_wtable(at<float2>(d, L.W), at<double>(d, L.dl), at<float>(d, L.ap),
+                                       C.B.n_bins, C.n_tx, C.P.N, C.B.j_lo, C.B.df, st);
+              }),
+              "wtable launch");
+    if (C.table) {
+        hip_check(launch_rrange(at<uint32_t>(d, L.rr), x, y, z, C.ph.total, sub_geo(d, L), C.P.M, st),
+                  "range launch");
+        hip_check(launch_dtable(at<float4>(d, L.dt), at<DeltaParams>(d, L.dp), at<uint32_t>(d, L.rr),
+                                C.K, C.P.height, C.B.j_lo, C.B.j_lo + std::max(C.B.n_bins, 1) - 1, st),
+                  "table launch");
+    }
+}
+
+// ---------------------------------------------------------------- forward spectra
+// Plans and enqueues the spectra into spec_out (device [P][T][N][n_bins]
+// float2), or into a workspace buffer followed by the inverse transform
+// into rf_out.
 void forward_spectra(const simus_probe* probe, const simus_medium* medium,
                      const simus_options* opt, int32_t n_tx, const double* delays,
                      const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
                      const float* y, const float* z, const float* refl, float* spec_out,
                      float* rf_out, hipStream_t st)
 {
-    Forward F;
-    F.P = make_probe(probe, medium, opt);
-    check_transmits(F.P, n_tx, delays, apod);
-    const Phantoms ph = check_phantoms(n_ph, offs);
-    if (opt->nfft <= 0) throw Error{SIMUS_EINVAL, "options.nfft must be > 0 (see simus_rf_grid)"};
-    if (opt->n_t > opt->nfft) throw Error{SIMUS_EINVAL, "options.n_t must be <= nfft"};
-    if (ph.total > 0 && (!x || !z || !refl)) throw Error{SIMUS_EINVAL, "x, z and refl must be non-NULL"};
     if (!spec_out && !rf_out) throw Error{SIMUS_EINVAL, "output pointer must be non-NULL"};
-    F.B = make_band(F.P, opt->nfft, opt->n_t);
-    F.n_tx = n_tx;
-    const int N = F.P.N, M = F.P.M;
-    const bool has_y = y != nullptr;
-    F.cfg = synth_config(M, n_tx, has_y);
-    const int JT = F.cfg.jt, TT = F.cfg.tt, BS = F.cfg.bs, SC = F.cfg.sc;
-    F.n_bt = (F.B.n_bins + JT - 1) / JT;
-    F.n_tg = (n_tx + TT - 1) / TT;
-    // scatterers per item: about 2048 items over the whole call
+    const Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl);
+    const int N = C.P.N, M = C.P.M;
+    SynthConfig cfg = synth_config(M, n_tx, C.has_y);
+    cfg.table = C.table;
+    const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;
+    const int n_bt = (C.B.n_bins + JT - 1) / JT;
+    const int n_tg = (n_tx + TT - 1) / TT;
+    if (n_bt >= 65536 || n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
+    // scatterers per item: about 6000 items over the whole call
     int64_t slice = opt->tile_scat;
     if (slice <= 0) {
-        const int64_t work = std::max<int64_t>(1, ph.total) * F.n_bt * F.n_tg;
-        slice = (work + 2047) / 2048;
+        const int64_t work = std::max<int64_t>(1, C.ph.total) * n_bt * n_tg;
+        slice = (work + 5999) / 6000;
     }
     slice = std::max<int64_t>(slice, 4 * SC);
     slice = (slice + SC - 1) / SC * SC;
-    F.slice = (int)std::min<int64_t>(slice, int64_t(1) << 30);
+    slice = std::min<int64_t>(slice, int64_t(1) << 30);
 
     std::vector<Item> items;
     std::vector<int32_t> pbase(n_ph), nsl(n_ph);
     for (int p = 0; p < n_ph; ++p) {
-        const int64_t S = ph.off[p + 1] - ph.off[p];
-        const int ns = (int)((S + F.slice - 1) / F.slice);
+        const int64_t Sp = C.ph.off[p + 1] - C.ph.off[p];
+        const int ns = (int)((Sp + slice - 1) / slice);
         pbase[p] = (int32_t)items.size();
         nsl[p] = ns;
-        for (int tg = 0; tg < F.n_tg; ++tg)
-            for (int bt = 0; bt < F.n_bt; ++bt)
+        for (int tg = 0; tg < n_tg; ++tg)
+            for (int bt = 0; bt < n_bt; ++bt)
                 for (int sl = 0; sl < ns; ++sl) {
-                    const int64_t s0 = ph.off[p] + int64_t(sl) * F.slice;
-                    const int64_t s1 = std::min<int64_t>(s0 + F.slice, ph.off[p + 1]);
+                    const int64_t s0 = C.ph.off[p] + int64_t(sl) * slice;
+                    const int64_t s1 = std::min<int64_t>(s0 + slice, C.ph.off[p + 1]);
                     items.push_back(Item{p, (int32_t)s0, (int32_t)s1, bt | (tg << 16)});
                 }
     }
-    F.n_items = (int)items.size();
-    if (F.n_bt >= 65536 || F.n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
+    const int n_items = (int)items.size();
 
-    // ---- layout
-    const SubElements S = sub_elements(F.P);
     Layout up;
-    const size_t o_xc = up.add(sizeof(double) * M), o_zc = up.add(sizeof(double) * M);
-    const size_t o_tx = up.add(sizeof(float) * M), o_tz = up.add(sizeof(float) * M);
-    const size_t o_nx = up.add(sizeof(float) * M), o_nz = up.add(sizeof(float) * M);
-    const size_t o_dl = up.add(sizeof(double) * n_tx * N), o_ap = up.add(sizeof(float) * n_tx * N);
-    const size_t o_pw = up.add(sizeof(float2) * std::max(F.B.n_bins, 1));
-    const size_t o_it = up.add(sizeof(Item) * std::max(F.n_items, 1));
+    CommonLayout L;
+    layout_upload(up, L, C);
+    const size_t o_it = up.add(sizeof(Item) * std::max(n_items, 1));
     const size_t o_pb = up.add(sizeof(int32_t) * n_ph), o_ns = up.add(sizeof(int32_t) * n_ph);
     Layout dv = up;
-    const size_t o_W = dv.add(sizeof(float2) * size_t(std::max(F.B.n_bins, 1)) * n_tx * N);
-    const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(F.n_items, 1)) * JT * TT * BS);
+    layout_device(dv, L, C);
+    const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * JT * TT * BS);
     const size_t o_tk = dv.add(sizeof(int32_t) * 4);
-    const size_t o_rr = dv.add(sizeof(uint32_t) * 4);
-    const size_t o_dt = dv.add(sizeof(float4) * 2 * DELTA_NT);
-    const size_t o_dp = dv.add(sizeof(DeltaParams));
-    const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(F.B.n_bins, 1);
+    const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(C.B.n_bins, 1);
     const size_t o_spec = spec_out ? 0 : dv.add(spec_bytes);
 
     Arena& a = arena_for(st, dv.size, up.size);
     char* h = a.host;
-    for (int m = 0; m < M; ++m) {
-        at<double>(h, o_xc)[m] = S.xc[m];
-        at<double>(h, o_zc)[m] = S.zc[m];
-        at<float>(h, o_tx)[m] = (float)S.tx[m];
-        at<float>(h, o_tz)[m] = (float)S.tz[m];
-        at<float>(h, o_nx)[m] = (float)S.nx[m];
-        at<float>(h, o_nz)[m] = (float)S.nz[m];
-    }
-    for (int i = 0; i < n_tx * N; ++i) {
-        at<double>(h, o_dl)[i] = delays[i];
-        at<float>(h, o_ap)[i] = apod ? apod[i] : 1.f;
-    }
-    for (int b = 0; b < F.B.n_bins; ++b) {
-        const double w = 2 * M_PI * (F.B.j_lo + b) * F.B.df;
-        const std::complex<double> v = pulse_spectrum(F.P, w) * transducer_spectrum(F.P, w);
-        at<float2>(h, o_pw)[b] = make_float2((float)v.real(), (float)v.imag());
-    }
-    if (F.n_items) std::memcpy(h + o_it, items.data(), sizeof(Item) * F.n_items);
+    fill_upload(h, L, C, delays, apod);
+    if (n_items) std::memcpy(h + o_it, items.data(), sizeof(Item) * n_items);
     std::memcpy(h + o_pb, pbase.data(), sizeof(int32_t) * n_ph);
     std::memcpy(h + o_ns, nsl.data(), sizeof(int32_t) * n_ph);
     upload(a, up.size, st);
 
     char* d = a.dev;
-    float2* W = at<float2>(d, o_W);
     float2* spec = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(d, o_spec);
-    hip_check(timed(K_WTABLE, st, [&] {
-                  return launch_wtable(W, at<double>(d, o_dl), at<float>(d, o_ap), F.B.n_bins, n_tx,
-                                       N, F.B.j_lo, F.B.df, st);
-              }),
-              "wtable launch");
+    launch_common(d, L, C, x, y, z, st);
     SynthArgs A{};
     A.x = x;
     A.y = y;
     A.z = z;
     A.refl = refl;
-    A.sub = SubGeo{at<double>(d, o_xc), at<double>(d, o_zc), at<float>(d, o_tx),
-                   at<float>(d, o_tz), at<float>(d, o_nx), at<float>(d, o_nz)};
-    A.W = W;
+    A.sub = sub_geo(d, L);
+    A.W = at<float2>(d, L.W);
     A.items = at<Item>(d, o_it);
-    A.n_items = F.n_items;
+    A.n_items = n_items;
     A.part = at<float2>(d, o_part);
     A.M = M;
-    A.nu = F.P.nu;
+    A.nu = C.P.nu;
     A.N = N;
     A.n_tx = n_tx;
-    A.n_bins = F.B.n_bins;
-    A.j_lo = F.B.j_lo;
-    A.K = model_constants(F.P, F.B);
+    A.n_bins = C.B.n_bins;
+    A.j_lo = C.B.j_lo;
+    A.K = C.K;
+    A.dtab = C.table ? at<float4>(d, L.dt) : nullptr;
+    A.dpar = C.table ? at<DeltaParams>(d, L.dp) : nullptr;
     A.ticket = nullptr;
-    F.cfg.table = !has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
-    A.dtab = nullptr;
-    A.dpar = nullptr;
-    if (F.cfg.table) {
-        A.dtab = at<float4>(d, o_dt);
-        A.dpar = at<DeltaParams>(d, o_dp);
-        hip_check(launch_rrange(at<uint32_t>(d, o_rr), x, y, z, ph.total, A.sub, M, st), "range launch");
-        hip_check(launch_dtable(at<float4>(d, o_dt), at<DeltaParams>(d, o_dp), at<uint32_t>(d, o_rr),
-                                A.K, F.P.height, F.B.j_lo, F.B.j_lo + std::max(F.B.n_bins, 1) - 1, st),
-                  "table launch");
-    }
-    F.cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
-    if (F.cfg.persistent && F.n_items > 0) {
+    cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
+    if (cfg.persistent && n_items > 0) {
         A.ticket = at<int32_t>(d, o_tk);
         hip_check(launch_zero_i32(A.ticket, 1, st), "zero launch");
-        int per_cu = 0;
         hipDeviceProp_t prop;
         int dev = 0;
         hip_check(hipGetDevice(&dev), "hipGetDevice");
         hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        per_cu = std::max(1, 1024 / BS);
-        F.cfg.grid = std::min(F.n_items, prop.multiProcessorCount * per_cu);
+        const int per_cu = std::max(1, 512 / BS);
+        cfg.grid = std::min(n_items, prop.multiProcessorCount * per_cu);
     } else {
-        F.cfg.grid = F.n_items;
+        cfg.grid = n_items;
     }
     if (log_enabled())
         std::fprintf(stderr,
                      "[simus] N=%d nu=%d M=%d T=%d P=%d S=%lld nfft=%d n_t=%d j_lo=%d bins=%d "
-                     "BS=%d TT=%d SC=%d JT=%d slice=%d items=%d grid=%d y=%d table=%d persistent=%d\n",
-                     N, F.P.nu, M, n_tx, n_ph, (long long)ph.total, F.B.nfft, F.B.n_t, F.B.j_lo,
-                     F.B.n_bins, BS, TT, SC, JT, F.slice, F.n_items, F.cfg.grid, (int)has_y,
-                     (int)F.cfg.table, (int)F.cfg.persistent);
-    hip_check(timed(K_SYNTH, st, [&] { return launch_synth(F.cfg, A, st); }), "synthesis launch");
+                     "BS=%d TT=%d SC=%d JT=%d slice=%lld items=%d grid=%d y=%d table=%d persistent=%d\n",
+                     N, C.P.nu, M, n_tx, n_ph, (long long)C.ph.total, C.B.nfft, C.B.n_t, C.B.j_lo,
+                     C.B.n_bins, BS, TT, SC, JT, (long long)slice, n_items, cfg.grid, (int)C.has_y,
+                     (int)C.table, (int)cfg.persistent);
+    hip_check(timed(K_SYNTH, st, [&] { return launch_synth(cfg, A, st); }), "synthesis launch");
     hip_check(timed(K_FINALIZE, st, [&] {
-                  return launch_finalize(spec, A.part, at<float2>(d, o_pw), at<int32_t>(d, o_pb),
-                                         at<int32_t>(d, o_ns), n_ph, n_tx, N, F.P.nu, F.B.n_bins,
-                                         BS, TT, JT, F.n_bt, st);
+                  return launch_finalize(spec, A.part, at<float2>(d, L.pw), at<int32_t>(d, o_pb),
+                                         at<int32_t>(d, o_ns), n_ph, n_tx, N, C.P.nu, C.B.n_bins,
+                                         BS, TT, JT, n_bt, st);
               }),
               "finalize launch");
     if (rf_out) {
         hip_check(timed(K_IDFT, st, [&] {
-                      return launch_idft(rf_out, spec, int64_t(n_ph) * n_tx * N, F.B.n_bins,
-                                         F.B.j_lo, F.B.nfft, F.B.n_t, st);
+                      return launch_idft(rf_out, spec, int64_t(n_ph) * n_tx * N, C.B.n_bins,
+                                         C.B.j_lo, C.B.nfft, C.B.n_t, st);
                   }),
                   "inverse transform launch");
     }
+}
+
+// ---------------------------------------------------------------- adjoint
+void backward(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+              int32_t n_tx, const double* delays, const float* apod, int32_t n_ph,
+              const int64_t* offs, const float* x, const float* y, const float* z,
+              const float* refl, const float* drf, float* dR, float* dX, float* dY, float* dZ,
+              hipStream_t st)
+{
+    const Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl);
+    if (C.ph.total > 0 && !drf) throw Error{SIMUS_EINVAL, "drf must be non-NULL"};
+    if (!dR && !dX && !dY && !dZ) return;
+    if (C.ph.total == 0) return;
+    const int N = C.P.N;
+    AdjConfig cfg = adjoint_config(n_tx, C.has_y);
+    cfg.table = C.table;
+    // items: (phantom, 256 scatterers, bin range); about 3000 items
+    int64_t n_sb = 0;
+    for (int p = 0; p < n_ph; ++p) n_sb += (C.ph.off[p + 1] - C.ph.off[p] + 255) / 256;
+    int64_t rb = (int64_t(std::max(C.B.n_bins, 1)) * n_sb + 2999) / 3000;
+    rb = std::max<int64_t>(rb, cfg.jt);
+    rb = (rb + cfg.jt - 1) / cfg.jt * cfg.jt;
+    const int range_bins = (int)std::min<int64_t>(rb, std::max(C.B.n_bins, 1));
+    const int n_ranges = (std::max(C.B.n_bins, 1) + range_bins - 1) / range_bins;
+    std::vector<AdjItem> items;
+    for (int p = 0; p < n_ph; ++p)
+        for (int64_t s0 = C.ph.off[p]; s0 < C.ph.off[p + 1]; s0 += 256)
+            for (int r = 0; r < n_ranges; ++r)
+                items.push_back(AdjItem{p, (int32_t)s0,
+                                        (int32_t)std::min<int64_t>(s0 + 256, C.ph.off[p + 1]), r});
+    const int n_items = (int)items.size();
+
+    Layout up;
+    CommonLayout L;
+    layout_upload(up, L, C);
+    const size_t o_it = up.add(sizeof(AdjItem) * std::max(n_items, 1));
+    Layout dv = up;
+    layout_device(dv, L, C);
+    const size_t o_lam =
+        dv.add(sizeof(float2) * size_t(n_ph) * std::max(C.B.n_bins, 1) * n_tx * N);
+    const size_t o_part = dv.add(sizeof(float4) * size_t(n_ranges) * C.ph.total);
+
+    Arena& a = arena_for(st, dv.size, up.size);
+    fill_upload(a.host, L, C, delays, apod);
+    std::memcpy(a.host + o_it, items.data(), sizeof(AdjItem) * n_items);
+    upload(a, up.size, st);
+    char* d = a.dev;
+    launch_common(d, L, C, x, y, z, st);
+    hip_check(timed(K_DFT, st, [&] {
+                  return launch_dft_t(at<float2>(d, o_lam), drf, int64_t(n_ph) * n_tx * N,
+                                      C.B.n_bins, C.B.j_lo, C.B.nfft, C.B.n_t, n_tx, N, st);
+              }),
+              "residual transform launch");
+    AdjArgs A{};
+    A.x = x;
+    A.y = y;
+    A.z = z;
+    A.refl = refl;
+    A.sub = sub_geo(d, L);
+    A.W = at<float2>(d, L.W);
+    A.lam = at<float2>(d, o_lam);
+    A.pw = at<float2>(d, L.pw);
+    A.items = at<AdjItem>(d, o_it);
+    A.part = at<float4>(d, o_part);
+    A.dtab = C.table ? at<float4>(d, L.dt) : nullptr;
+    A.dpar = C.table ? at<DeltaParams>(d, L.dp) : nullptr;
+    A.S_total = C.ph.total;
+    A.M = C.P.M;
+    A.nu = C.P.nu;
+    A.N = N;
+    A.n_tx = n_tx;
+    A.n_bins = C.B.n_bins;
+    A.j_lo = C.B.j_lo;
+    A.range_bins = range_bins;
+    A.K = C.K;
+    if (log_enabled())
+        std::fprintf(stderr, "[simus] adjoint S=%lld T=%d bins=%d TT=%d JT=%d range=%d items=%d y=%d table=%d\n",
+                     (long long)C.ph.total, n_tx, C.B.n_bins, cfg.tt, cfg.jt, range_bins, n_items,
+                     (int)C.has_y, (int)C.table);
+    hip_check(timed(K_ADJ, st, [&] { return launch_adjoint(cfg, A, n_items, st); }), "adjoint launch");
+    hip_check(timed(K_ADJRED, st, [&] {
+                  return launch_adjoint_reduce(A.part, n_ranges, C.ph.total, refl, dR, dX, dY, dZ, st);
+              }),
+              "adjoint reduce launch");
+}
+
+// ---------------------------------------------------------------- RMS field
+int pfield_nf_host(const Probe& P, const SubElements& S, const double* delays, int64_t n,
+                   const float* X, const float* Y, const float* Z)
+{
+    // Section VII: dw = 2 pi / max(r / c + delay) over points and sub-elements,
+    // N_f = ceil(2 wc / dw) = ceil(2 fc max(r / c + delay)).
+    double tmax = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const double yy = Y ? double(Y[p]) : 0.0;
+        for (int m = 0; m < P.M; ++m) {
+            const double dx = double(X[p]) - S.xc[m], dz = double(Z[p]) - S.zc[m];
+            tmax = std::max(tmax, std::sqrt(dx * dx + dz * dz + yy * yy) / P.c + delays[m / P.nu]);
+        }
+    }
+    const double nf = std::ceil(2.0 * P.fc * tmax);
+    if (!(nf >= 1) || nf > 1e6) throw Error{SIMUS_EINVAL, "field frequency count out of range"};
+    return (int)nf;
+}
+
+void pfield(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+            int32_t n_f, const double* delays, const float* apod, int64_t n_pts, const float* X,
+            const float* Y, const float* Z, float* out, hipStream_t st)
+{
+    Common C;
+    C.P = make_probe(probe, medium, opt);
+    check_transmits(C.P, 1, delays, apod);
+    if (n_f < 1 || n_f > 1000000) throw Error{SIMUS_EINVAL, "n_f must be in [1, 1e6]"};
+    if (n_pts < 0) throw Error{SIMUS_EINVAL, "n_pts must be >= 0"};
+    if (n_pts > 0 && (!X || !Z || !out)) throw Error{SIMUS_EINVAL, "X, Z and p_rms must be non-NULL"};
+    if (n_pts == 0) return;
+    // nodes w_j = 2 wc j / N_f, j = 1 .. N_f (j = 0 carries S_P(0) = 0)
+    C.B.nfft = 0;
+    C.B.n_t = 0;
+    C.B.j_lo = 1;
+    C.B.n_bins = n_f;
+    C.B.df = 2.0 * C.P.fc / n_f;
+    C.S = sub_elements(C.P);
+    C.K = model_constants(C.P, C.B);
+    C.n_tx = 1;
+    C.has_y = Y != nullptr;
+    C.table = !C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
+    C.ph.n = 1;
+    C.ph.total = n_pts;
+    const int JT = 8;
+    // frequency ranges: about 2000 blocks
+    const int64_t n_pb = (n_pts + 255) / 256;
+    int64_t rb = (int64_t(n_f) * n_pb + 1999) / 2000;
+    rb = std::max<int64_t>(JT, (rb + JT - 1) / JT * JT);
+    const int range_bins = (int)std::min<int64_t>(rb, n_f);
+    const int n_ranges = (n_f + range_bins - 1) / range_bins;
+    if (n_pb > 0x7fffffff || n_ranges > 65535) throw Error{SIMUS_EINVAL, "too many field points"};
+
+    Layout up;
+    CommonLayout L;
+    layout_upload(up, L, C);
+    const size_t o_ptx = up.add(sizeof(float2) * n_f);
+    Layout dv = up;
+    layout_device(dv, L, C);
+    const size_t o_part = dv.add(sizeof(float) * size_t(n_ranges) * n_pts);
+    Arena& a = arena_for(st, dv.size, up.size);
+    fill_upload(a.host, L, C, delays, apod);
+    for (int j = 1; j <= n_f; ++j) {
+        const double w = 2 * M_PI * j * C.B.df;
+        const std::complex<double> v = pulse_spectrum(C.P, w) * std::sqrt(transducer_spectrum(C.P, w));
+        at<float2>(a.host, o_ptx)[j - 1] = make_float2((float)v.real(), (float)v.imag());
+    }
+    upload(a, up.size, st);
+    char* d = a.dev;
+    launch_common(d, L, C, X, Y, Z, st);
+    FieldArgs F{};
+    F.X = X;
+    F.Y = Y;
+    F.Z = Z;
+    F.sub = sub_geo(d, L);
+    F.W = at<float2>(d, L.W);
+    F.ptx = at<float2>(d, o_ptx);
+    F.part = at<float>(d, o_part);
+    F.dtab = C.table ? at<float4>(d, L.dt) : nullptr;
+    F.dpar = C.table ? at<DeltaParams>(d, L.dp) : nullptr;
+    F.n_pts = n_pts;
+    F.M = C.P.M;
+    F.nu = C.P.nu;
+    F.N = C.P.N;
+    F.n_bins = n_f;
+    F.j_lo = 1;
+    F.range_bins = range_bins;
+    F.K = C.K;
+    hip_check(timed(K_PFIELD, st, [&] { return launch_pfield(F, C.has_y, C.table, n_ranges, st); }),
+              "field launch");
+    const float dw = (float)(2.0 * M_PI * C.B.df);
+    hip_check(launch_pfield_reduce(F.part, n_ranges, n_pts, dw, out, st), "field reduce launch");
 }
 
 template <class Fn>
@@ -507,6 +738,42 @@ int simus_rf(const simus_probe* probe, const simus_medium* medium, const simus_o
         if (!rf) throw Error{SIMUS_EINVAL, "rf must be non-NULL"};
         forward_spectra(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl, nullptr,
                         rf, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int simus_rf_backward(const simus_probe* probe, const simus_medium* medium,
+                      const simus_options* opt, int32_t n_tx, const double* delays,
+                      const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
+                      const float* y, const float* z, const float* refl, const float* drf,
+                      float* drefl, float* dx, float* dy, float* dz, void* hip_stream)
+{
+    return guarded([&] {
+        backward(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl, drf, drefl, dx,
+                 dy, dz, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int simus_pfield_nf(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+                    const double* delays, int64_t n_pts, const float* X, const float* Y,
+                    const float* Z, int32_t* n_f)
+{
+    return guarded([&] {
+        if (!n_f) throw Error{SIMUS_EINVAL, "n_f must be non-NULL"};
+        const Probe P = make_probe(probe, medium, opt);
+        check_transmits(P, 1, delays, nullptr);
+        if (n_pts < 1 || !X || !Z) throw Error{SIMUS_EINVAL, "at least one point (X, Z non-NULL) is required"};
+        const SubElements S = sub_elements(P);
+        *n_f = pfield_nf_host(P, S, delays, n_pts, X, Y, Z);
+    });
+}
+
+int simus_pfield(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+                 int32_t n_f, const double* delays, const float* apod, int64_t n_pts,
+                 const float* X, const float* Y, const float* Z, float* p_rms, void* hip_stream)
+{
+    return guarded([&] {
+        pfield(probe, medium, opt, n_f, delays, apod, n_pts, X, Y, Z, p_rms,
+               static_cast<hipStream_t>(hip_stream));
     });
 }
 

@@ -93,11 +93,25 @@ __device__ __forceinline__ SubFrame load_frame(const SubGeo& g, int n)
     return f;
 }
 
+// Frequency-independent derivative data of a pair for the adjoint, per
+// scatterer coordinate xi in (X, Y, Z) (index 0, 1, 2):
+//   la = d ln(obliquity / r) / d xi,  rd = dr / d xi,
+//   ud = b_sub d sin(theta) / d xi  (du = k ud, u = k b_sub sin(theta)),
+//   qd = (dr / d xi) / (2 r^2)     (dq = k qd for y = 0).
+// c, dc carry cos(j theta) by the same recurrence as s (for sinc'(u)).
+struct GeoD {
+    float la[3], rd[3], ud[3], qd[3];
+    float c, dc;
+    float inv_theta;
+    float r, y;
+};
+
 // Set-up of a pair at bin j0: distance r in FP64, azimuthal angle theta of
 // the point seen from the sub-element face (Eq. 23), obliquity of Eq. (39).
+// With D != nullptr also the derivative data of the pair.
 template <bool HASY>
 __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, float px, float py,
-                                        float pz, int j0)
+                                        float pz, int j0, GeoD* D = nullptr)
 {
     const double dx = (double)px - f.xc;
     const double dz = (double)pz - f.zc;
@@ -112,9 +126,15 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     const float inv_rho = ok ? 1.f / rho : 0.f;
     const float st = xl * inv_rho;
     const float ct = ok ? zl * inv_rho : 1.f;
-    float obl = ct;                                        // soft baffle
-    if (K.baffle == 1) obl = 1.f;                          // rigid
-    else if (K.baffle == 2) obl = ct / (ct + K.zeta);      // finite impedance
+    float obl = ct, dobl = 1.f;                            // soft baffle
+    if (K.baffle == 1) {                                   // rigid
+        obl = 1.f;
+        dobl = 0.f;
+    } else if (K.baffle == 2) {                            // finite impedance
+        const float den = 1.f / (ct + K.zeta);
+        obl = ct * den;
+        dobl = K.zeta * den * den;
+    }
     const float inv_r = 1.f / rf;
     const float amp = ok ? obl * inv_r : 0.f;
     const float jf0 = (float)j0;
@@ -144,6 +164,29 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     } else {
         g.yr2 = 0.f;
         g.y2r = 0.f;
+    }
+    if (D) {
+        const float yf = HASY ? py : 0.f;
+        const float dxl[3] = {f.tx, 0.f, f.tz};
+        const float dzl[3] = {f.nx, 0.f, f.nz};
+        const float dyy[3] = {0.f, 1.f, 0.f};
+        const float inv_obl = ok ? 1.f / obl : 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float drho = (xl * dxl[a] + zl * dzl[a]) * inv_rho;
+            const float dr = (xl * dxl[a] + zl * dzl[a] + yf * dyy[a]) * inv_r;
+            const float dst = (dxl[a] - st * drho) * inv_rho;
+            const float dct = (dzl[a] - ct * drho) * inv_rho;
+            D->la[a] = ok ? dobl * dct * inv_obl - dr * inv_r : 0.f;
+            D->rd[a] = ok ? dr : 0.f;
+            D->ud[a] = ok ? K.b_sub * dst : 0.f;
+            D->qd[a] = ok ? 0.5f * dr * inv_r * inv_r : 0.f;
+        }
+        D->c = cos_turns(jf0 * sigma);
+        D->dc = -theta * sin_turns((jf0 - 0.5f) * sigma) * sh;
+        D->inv_theta = (theta != 0.f) ? 1.f / theta : 0.f;
+        D->r = rf;
+        D->y = yf;
     }
     return g;
 }
@@ -206,6 +249,133 @@ __device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaPara
     re = fmaf(t, re, a.x);
     im = fmaf(t, im, a.y);
     return make_float2(re, im);
+}
+
+// delta with its partial derivatives in r and y, evaluated directly
+// (y != 0 path of the adjoint, or without the table).  Per Gaussian,
+// T = A sqrt(pi) alpha^{-1/2} exp(phi), phi = beta^2/(4 alpha) + gamma, and
+// dT = T (-1/2 dalpha / alpha + dphi).
+template <bool HASY>
+__device__ __forceinline__ void elevation_grad(const Gauss4& G, float inv_rf, float k, float r,
+                                               float y, float2& dl, float2& d_r, float2& d_y)
+{
+    const float inv_r = 1.f / r;
+    const float q = 0.5f * k * (inv_rf - inv_r);
+    const float ar_i = 0.5f * k * inv_r * inv_r;          // d alpha / dr = i ar_i
+    dl = d_r = d_y = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float bi = G.b[g] + q;
+        const float m2 = fmaf(bi, bi, G.a2[g]);
+        const float inv_mod = rsq_fast(m2);
+        const float mod = m2 * inv_mod;
+        const float x = 0.5f * (mod + G.a[g]);
+        const float rx = rsq_fast(x);
+        const float zr = x * rx * inv_mod, zi = -0.5f * bi * rx * inv_mod;   // alpha^{-1/2}
+        const float2 ia = make_float2(zr * zr - zi * zi, 2.f * zr * zi);     // 1/alpha
+        float2 T = make_float2(G.Ar[g] * zr - G.Ai[g] * zi, G.Ar[g] * zi + G.Ai[g] * zr);
+        // -1/2 (d alpha/dr) / alpha = -1/2 (i ar_i) ia
+        float2 lr = make_float2(0.5f * ar_i * ia.y, -0.5f * ar_i * ia.x);
+        float2 ly = make_float2(0.f, 0.f);
+        if (HASY) {
+            const float b2 = -k * k * y * y * inv_r * inv_r;               // beta^2 (real)
+            const float gam = 0.5f * k * y * y * inv_r;                    // gamma = i gam
+            const float2 phi = make_float2(0.25f * b2 * ia.x, 0.25f * b2 * ia.y + gam);
+            // beta = -i k y / r, dbeta/dr = i k y / r^2, dbeta/dy = -i k / r
+            // 2 beta dbeta/dr = 2 k^2 y^2 / r^3 (real); 2 beta dbeta/dy = -2 k^2 y / r^2
+            const float bbr = 2.f * k * k * y * y * inv_r * inv_r * inv_r;
+            const float bby = -2.f * k * k * y * inv_r * inv_r;
+            // - beta^2 dalpha/dr / (4 alpha^2) = -(b2 / 4) (i ar_i) ia^2
+            const float2 ia2 = cmul(ia, ia);
+            const float2 t2 = make_float2(0.25f * b2 * ar_i * ia2.y, -0.25f * b2 * ar_i * ia2.x);
+            lr.x += 0.25f * bbr * ia.x + t2.x;
+            lr.y += 0.25f * bbr * ia.y + t2.y - 0.5f * k * y * y * inv_r * inv_r;
+            ly = make_float2(0.25f * bby * ia.x, 0.25f * bby * ia.y + k * y * inv_r);
+            float et = phi.y * 0.15915494309189535f;
+            et -= rintf(et);
+            const float mag = exp2_fast(phi.x * 1.4426950408889634f);
+            T = cmul(T, make_float2(mag * cos_turns(et), mag * sin_turns(et)));
+        }
+        dl.x += T.x;
+        dl.y += T.y;
+        const float2 tr = cmul(T, lr), ty = cmul(T, ly);
+        d_r.x += tr.x;
+        d_r.y += tr.y;
+        d_y.x += ty.x;
+        d_y.y += ty.y;
+    }
+}
+
+// Table lookup returning delta and d delta / dq.
+__device__ __forceinline__ float2 delta_table_d(const float4* tab, const DeltaParams& P, float q,
+                                                float2& dq)
+{
+    const float den = rcp_fast(fabsf(q) + P.L);
+    const float w = q * den;
+    const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
+    const float kf = floorf(u);
+    const float t = u - kf;
+    const int k = (int)kf;
+    const float4 a = tab[2 * k], b = tab[2 * k + 1];
+    float re = fmaf(t, b.z, b.x), im = fmaf(t, b.w, b.y);
+    // derivative in t: c1 + t (2 c2 + 3 t c3)
+    float gr = fmaf(3.f * t, b.z, 2.f * b.x), gi = fmaf(3.f * t, b.w, 2.f * b.y);
+    gr = fmaf(t, gr, a.z);
+    gi = fmaf(t, gi, a.w);
+    re = fmaf(t, re, a.z);
+    im = fmaf(t, im, a.w);
+    re = fmaf(t, re, a.x);
+    im = fmaf(t, im, a.y);
+    const float dwdq = P.L * den * den * P.inv_dw;         // dt/dq
+    dq = make_float2(gr * dwdq, gi * dwdq);
+    return make_float2(re, im);
+}
+
+// Green's term and its gradient in the scatterer coordinates at bin j;
+// advances the pair (and its cosine recurrence) to bin j + 1.
+template <bool HASY, bool TABLE, int NX>
+__device__ __forceinline__ float2 green_grad_next(const ModelConst& K, Geo& g, GeoD& D, float jf,
+                                                  float inv_j, const float4* tab,
+                                                  const DeltaParams& P, float2 (&dG)[NX])
+{
+    const float sn = g.s * inv_j;                          // sinc(u)
+    const float k = jf * K.k_per_bin;
+    const float ka = jf * K.ka_per_bin;
+    const float2 A = make_float2(g.E.x * sn, g.E.y * sn);
+    float2 dl, d_dq, d_r, d_y;
+    if (TABLE) {
+        dl = delta_table_d(tab, P, jf * g.kap, d_dq);
+    } else {
+        elevation_grad<HASY>(K.g, K.inv_rf, k, D.r, D.y, dl, d_r, d_y);
+    }
+    const float2 Gv = cmul(A, dl);
+    const float2 Ed = cmul(g.E, dl);
+    const float dsn = (D.c - sn) * inv_j * D.inv_theta;    // sinc'(u)
+    constexpr int idx[3] = {0, 2, 1};                      // X, Z, Y
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        const int a = idx[i];
+        const float2 phi = make_float2(D.la[a] - ka * D.rd[a], k * D.rd[a]);
+        float2 v = cmul(Gv, phi);
+        const float su = dsn * k * D.ud[a];
+        v.x = fmaf(Ed.x, su, v.x);
+        v.y = fmaf(Ed.y, su, v.y);
+        float2 dd;
+        if (TABLE) {
+            const float s = k * D.qd[a];
+            dd = make_float2(d_dq.x * s, d_dq.y * s);
+        } else {
+            dd = make_float2(d_r.x * D.rd[a] + (a == 1 ? d_y.x : 0.f),
+                             d_r.y * D.rd[a] + (a == 1 ? d_y.y : 0.f));
+        }
+        dG[i] = cfma(A, dd, v);
+    }
+    g.E = cmul(g.E, g.dE);
+    g.d = fmaf(g.lam, g.s, g.d);
+    g.s += g.d;
+    D.dc = fmaf(g.lam, D.c, D.dc);
+    D.c += D.dc;
+    return Gv;
 }
 
 // Green's term at absolute bin j (jf = j, inv_j = 1/j); advances the pair to

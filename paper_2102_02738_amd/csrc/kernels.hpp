@@ -24,6 +24,8 @@ struct ModelConst {
     float sinc_per_bin;      // df b_sub / c: sinc argument in turns per bin per unit sin(theta)
     float q_per_bin;         // pi df / c: Im(alpha_g) shift per bin per (1/R_f - 1/r)
     float k_per_bin;         // 2 pi df / c
+    float ka_per_bin;        // (alpha_dB / 8.69) df / 1e4: k_a per bin [Np/m]
+    float b_sub;             // sub-element half-width b / nu
     float inv_rf;            // 1 / R_f (0 for an unfocused element)
     float zeta;              // baffle impedance ratio
     int32_t baffle;          // 0 soft, 1 rigid, 2 zeta
@@ -86,6 +88,66 @@ struct SynthConfig {
     bool persistent;
     int grid;    // blocks launched (persistent: resident blocks)
 };
+
+// Adjoint work item: scatterers [s_begin, s_end) (at most 256) of one
+// phantom, bin range `range` (bins range * range_bins ...).
+struct AdjItem {
+    int32_t phantom;
+    int32_t s_begin;
+    int32_t s_end;
+    int32_t range;
+};
+
+struct AdjArgs {
+    const float* x;
+    const float* y;      // may be null
+    const float* z;
+    const float* refl;
+    SubGeo sub;
+    const float2* W;     // [n_bins][n_tx][N]
+    const float2* lam;   // [n_ph][n_bins][n_tx][N] residual spectra
+    const float2* pw;    // [n_bins] S_P S_T
+    const AdjItem* items;
+    float4* part;        // [n_ranges][S_total] (dR, dX, dY, dZ) before R_s
+    const float4* dtab;
+    const DeltaParams* dpar;
+    int64_t S_total;
+    int32_t M, nu, N, n_tx, n_bins, j_lo, range_bins;
+    ModelConst K;
+};
+
+struct AdjConfig {
+    int tt;      // transmits per group
+    int jt;      // bins per tile
+    bool has_y;
+    bool table;
+};
+
+AdjConfig adjoint_config(int n_tx, bool has_y);
+hipError_t launch_adjoint(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st);
+hipError_t launch_adjoint_reduce(const float4* part, int n_ranges, int64_t S, const float* refl,
+                                 float* dR, float* dX, float* dY, float* dZ, hipStream_t st);
+hipError_t launch_dft_t(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo, int nfft,
+                        int n_t, int n_tx, int N, hipStream_t st);
+
+struct FieldArgs {
+    const float* X;
+    const float* Y;      // may be null
+    const float* Z;
+    SubGeo sub;
+    const float2* W;     // [n_bins][N] transmit weights
+    const float2* ptx;   // [n_bins] S_P sqrt(S_T)
+    float* part;         // [n_ranges][n_pts] partial sums of |P|^2
+    const float4* dtab;
+    const DeltaParams* dpar;
+    int64_t n_pts;
+    int32_t M, nu, N, n_bins, j_lo, range_bins;
+    ModelConst K;
+};
+
+hipError_t launch_pfield(const FieldArgs& a, bool has_y, bool table, int n_ranges, hipStream_t st);
+hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, float dw, float* out,
+                                hipStream_t st);
 
 // Picks tt/sc/jt for a block size and transmit count.
 SynthConfig synth_config(int M, int n_tx, bool has_y);

@@ -1,0 +1,71 @@
+"""GPU parity of the RMS pressure field (simus_pfield, Eqs. 22, 41-42)
+against the FP64 oracle, on field grids shaped like the paper's Figs. 9-10."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.helpers import oracle_setup, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2102_02738_amd as S
+    S._lib.lib()
+    return S
+
+
+def _case(kind):
+    from paper_2102_02738_amd import inputs
+    if kind == "linear_pw10":
+        # 128-element 7.6 MHz linear array, 10-degree plane wave (cf. Fig. 10)
+        probe = inputs.linear_probe(128)
+        dl = inputs.plane_wave_delays(probe, [10.0])[0]
+        xs, zs = np.linspace(-15e-3, 15e-3, 41), np.linspace(2e-3, 40e-3, 31)
+        ys = None
+    elif kind == "phased_focused":
+        # 64-element 2.7 MHz phased array, kerf 50 um, focused at 60 mm (cf. Fig. 9)
+        probe = dict(n_elements=64, fc=2.7e6, pitch=0.3e-3, width=0.25e-3, height=14e-3,
+                     elev_focus=60e-3, bandwidth=0.74, radius=0.0, baffle=0, zeta=1.75)
+        xe = 0.3e-3 * (np.arange(64) - 31.5)
+        fx, fz = 10e-3, 60e-3
+        d = np.hypot(xe - fx, fz) / 1540.0
+        dl = d.max() - d
+        xs, zs = np.linspace(-40e-3, 40e-3, 33), np.linspace(5e-3, 100e-3, 25)
+        ys = None
+    else:
+        # elevation plane of the linear array (y != 0 path)
+        probe = inputs.linear_probe(32)
+        dl = np.zeros(32)
+        xs, zs = np.linspace(-4e-3, 4e-3, 9), np.linspace(5e-3, 30e-3, 11)
+        ys = 1.2e-3
+    X, Z = np.meshgrid(xs, zs)
+    X, Z = X.ravel().astype(np.float32), Z.ravel().astype(np.float32)
+    Y = None if ys is None else np.full_like(X, ys)
+    w = dict(probe=probe, medium=dict(c=1540.0, alpha_db=0.5),
+             options=dict(fs=4 * probe["fc"], n_cycles=1.0, nu=0, spectral_eps=1e-7, nfft=0, n_t=0))
+    return w, dl, X, Y, Z
+
+
+@pytest.mark.parametrize("kind", ["linear_pw10", "phased_focused", "elevation"])
+@pytest.mark.parametrize("direct", [False, True])
+def test_pfield_matches_oracle(S, orc, kind, direct):
+    import torch
+    w, dl, X, Y, Z = _case(kind)
+    apod = np.ones(w["probe"]["n_elements"], np.float32)
+    nf = S.pfield_nf(w["probe"], w["medium"], w["options"], dl, X, Y, Z)
+    su = oracle_setup(orc, w)
+    assert nf == orc.pfield_nf(su, dl, X, np.zeros_like(X) if Y is None else Y, Z)
+    dX, dY, dZ = to_dev(X, Y, Z)
+    o = dict(w["options"], flags=S.FLAG_NO_DELTA_TABLE if direct else 0)
+    got = S.pfield(w["probe"], w["medium"], o, nf, dl, apod, dX, dY, dZ)
+    torch.cuda.synchronize()
+    ref = orc.pfield(su, dl, apod, nf, X, np.zeros_like(X) if Y is None else Y, Z)
+    e = rel_l2(got.cpu().numpy(), ref)
+    print(kind, "nf", nf, "rel L2", e)
+    assert e <= TOL
