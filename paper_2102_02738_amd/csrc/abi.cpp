@@ -367,9 +367,13 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     if (!spec_out && !rf_out) throw Error{SIMUS_EINVAL, "output pointer must be non-NULL"};
     const Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl);
     const int N = C.P.N, M = C.P.M;
-    SynthConfig cfg = synth_config(M, n_tx, C.has_y);
+    const bool use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx);
+    SynthConfig cfg = use_mt ? mt_config(M, N, n_tx, C.has_y) : synth_config(M, n_tx, C.has_y);
     cfg.table = C.table;
     const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;
+    // partial slots per (item, bin, transmit): sub-elements (VALU path) or elements (MFMA path)
+    const int slots = use_mt ? N : BS;
+    const int fin_nu = use_mt ? 1 : C.P.nu;
     const int n_bt = (C.B.n_bins + JT - 1) / JT;
     const int n_tg = (n_tx + TT - 1) / TT;
     if (n_bt >= 65536 || n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
@@ -378,6 +382,7 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     if (slice <= 0) {
         const int64_t work = std::max<int64_t>(1, C.ph.total) * n_bt * n_tg;
         slice = (work + 5999) / 6000;
+        if (use_mt) slice = (work + 2999) / 3000;
     }
     slice = std::max<int64_t>(slice, 4 * SC);
     slice = (slice + SC - 1) / SC * SC;
@@ -407,7 +412,7 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     const size_t o_pb = up.add(sizeof(int32_t) * n_ph), o_ns = up.add(sizeof(int32_t) * n_ph);
     Layout dv = up;
     layout_device(dv, L, C);
-    const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * JT * TT * BS);
+    const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * JT * TT * slots);
     const size_t o_tk = dv.add(sizeof(int32_t) * 4);
     const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(C.B.n_bins, 1);
     const size_t o_spec = spec_out ? 0 : dv.add(spec_bytes);
@@ -443,7 +448,7 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     A.dtab = C.table ? at<float4>(d, L.dt) : nullptr;
     A.dpar = C.table ? at<DeltaParams>(d, L.dp) : nullptr;
     A.ticket = nullptr;
-    cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
+    cfg.persistent = !use_mt && (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
     if (cfg.persistent && n_items > 0) {
         A.ticket = at<int32_t>(d, o_tk);
         hip_check(launch_zero_i32(A.ticket, 1, st), "zero launch");
@@ -459,15 +464,18 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
     if (log_enabled())
         std::fprintf(stderr,
                      "[simus] N=%d nu=%d M=%d T=%d P=%d S=%lld nfft=%d n_t=%d j_lo=%d bins=%d "
-                     "BS=%d TT=%d SC=%d JT=%d slice=%lld items=%d grid=%d y=%d table=%d persistent=%d\n",
+                     "BS=%d TT=%d SC=%d JT=%d slice=%lld items=%d grid=%d y=%d table=%d persistent=%d mfma=%d\n",
                      N, C.P.nu, M, n_tx, n_ph, (long long)C.ph.total, C.B.nfft, C.B.n_t, C.B.j_lo,
                      C.B.n_bins, BS, TT, SC, JT, (long long)slice, n_items, cfg.grid, (int)C.has_y,
-                     (int)C.table, (int)cfg.persistent);
-    hip_check(timed(K_SYNTH, st, [&] { return launch_synth(cfg, A, st); }), "synthesis launch");
+                     (int)C.table, (int)cfg.persistent, (int)use_mt);
+    hip_check(timed(K_SYNTH, st, [&] {
+                  return use_mt ? launch_synth_mt(cfg, A, st) : launch_synth(cfg, A, st);
+              }),
+              "synthesis launch");
     hip_check(timed(K_FINALIZE, st, [&] {
                   return launch_finalize(spec, A.part, at<float2>(d, L.pw), at<int32_t>(d, o_pb),
-                                         at<int32_t>(d, o_ns), n_ph, n_tx, N, C.P.nu, C.B.n_bins,
-                                         BS, TT, JT, n_bt, st);
+                                         at<int32_t>(d, o_ns), n_ph, n_tx, N, fin_nu, C.B.n_bins,
+                                         slots, TT, JT, n_bt, st);
               }),
               "finalize launch");
     if (rf_out) {

@@ -86,6 +86,8 @@ struct SynthConfig {
     bool has_y;
     bool table;  // elevation term from the table (requires !has_y)
     bool persistent;
+    bool mfma;   // transmit contraction on the matrix cores (synth_mfma.hip)
+    int nq;      // MFMA path: transmit quarters per receive thread group
     int grid;    // blocks launched (persistent: resident blocks)
 };
 
@@ -155,6 +157,9 @@ SynthConfig synth_config(int M, int n_tx, bool has_y);
 hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
                          int N, int j_lo, double df, hipStream_t st);
 hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
+bool mt_supported(int M, int N, int n_tx);
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y);
+hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
                            int nu, int n_bins, int bs, int tt, int jt, int n_bt,

@@ -1,0 +1,227 @@
+// Synthesis for many transmits: the transmit contraction of Eq. (29),
+//   a[s][t] = sum_n G[n][s] W[n][t],
+// is a complex GEMM (16 scatterers x nu N sub-elements x up to 32 transmits
+// per group) and runs on the matrix cores with FP32 MFMA (16x16x4), while
+// the Green's terms are synthesised on the VALU (green.hpp) and the receive
+// contraction of Eqs. (32)-(33),
+//   X[e][t] += sum_s (sum_{mu in e} G[mu][s]) R_s a[s][t],
+// accumulates per element in registers across all scatterers of the item.
+//
+// Block: 512 threads (8 waves).  Synthesis: thread = (sub-element n, half of
+// the 16-scatterer chunk), 8 pairs stepped across the item's bin tile.
+// Transmit GEMM: a complex product is four real MFMA products; the 2 * NTP
+// output tiles (re/im of each 16-transmit tile) are spread over the 8 waves,
+// each wave covering a share of the sub-elements, and the shares are summed
+// in LDS in a fixed order.  Receive: thread = (element e, quarter of the
+// transmits).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "green.hpp"
+#include "kernels.hpp"
+
+namespace simus {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int NTP, int NQ, int JT, bool HASY, bool TABLE>
+__global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
+{
+    constexpr int NB = 512;
+    constexpr int MS = 256;                 // sub-element slots
+    constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
+    constexpr int GS = MS + 4;              // LDS row stride of the G tile (float2)
+    constexpr int TPG = 16 * NTP;           // transmit columns of the group
+    constexpr int NOUT = 2 * NTP;           // output tiles (re, im per column tile)
+    constexpr int KSPLIT = 8 / NOUT;        // waves per output tile
+    constexpr int KW = MS / KSPLIT;         // sub-elements per wave
+    constexpr int TQ = TPG / NQ;            // transmits per receive thread
+    constexpr int EP = NB / NQ;             // element slots
+
+    __shared__ float4 s_sc[SCH];
+    __shared__ float2 s_G[SCH * GS];
+    __shared__ float s_part[8][256];
+    __shared__ float2 s_c[SCH][TPG];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    // synthesis role
+    const int n = tid & (MS - 1), sh = tid / MS;
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    // receive role
+    const int re_e = tid % EP, re_q = tid / EP;
+    const bool re_live = re_e < A.N;
+    // GEMM role
+    const int otile = wave % NOUT, kpart = wave / NOUT;
+    const int ct = otile >> 1;              // column tile
+    const bool out_im = otile & 1;
+
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
+
+    const Item it = A.items[blockIdx.x];
+    const int bt = it.tile & 0xffff, tg = it.tile >> 16;
+    const int jb0 = bt * JT;
+    const int nb = min(JT, A.n_bins - jb0);
+    const int t0 = tg * TPG;
+
+    float2 X[JT][TQ];
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj)
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) X[jj][q] = make_float2(0.f, 0.f);
+
+    for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+        __syncthreads();
+        if (tid < SCH) {
+            const int s = s0 + tid;
+            float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
+            if (s < it.s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
+            s_sc[tid] = v;
+        }
+        __syncthreads();
+        Geo g[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float4 v = s_sc[sh * 8 + k];
+            g[k] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+            if (!active) g[k].E = make_float2(0.f, 0.f);
+        }
+        for (int jj = 0; jj < nb; ++jj) {
+            const int jb = jb0 + jj;
+            const float jf = (float)(A.j_lo + jb);
+            const float inv_j = rcp_fast(jf);
+            // 1. Green's terms of the chunk -> LDS tile [s][n]
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                s_G[(sh * 8 + k) * GS + n] = green_next<HASY, TABLE>(A.K, g[k], jf, inv_j, s_tab, P);
+            __syncthreads();
+            // 2. transmit GEMM share: rows s = lane % 16, columns t = ct * 16 + lane % 16
+            {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const int i = lane & 15, kk = lane >> 4;
+                const int tcol = t0 + ct * 16 + i;
+                const bool tlive = tcol < A.n_tx;
+                const float2* Wrow = A.W + ((int64_t)jb * A.n_tx + (tlive ? tcol : 0)) * A.N;
+                const int nbase = kpart * KW;
+#pragma unroll 4
+                for (int k4 = 0; k4 < KW; k4 += 4) {
+                    const int nn = nbase + k4 + kk;
+                    const float2 gv = s_G[i * GS + nn];
+                    float2 wv = make_float2(0.f, 0.f);
+                    if (tlive && nn < A.M) wv = Wrow[nn / A.nu];
+                    // re: Gr Wr - Gi Wi ; im: Gr Wi + Gi Wr
+                    const float b0 = out_im ? wv.y : wv.x;
+                    const float b1 = out_im ? wv.x : -wv.y;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, b0, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, b1, acc, 0, 0, 0);
+                }
+                // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s_part[wave][(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[v];
+            }
+            __syncthreads();
+            // 3. sum the shares (fixed order), scale by R_s
+            for (int idx = tid; idx < SCH * TPG; idx += NB) {
+                const int s = idx / TPG, t = idx % TPG;
+                const int c_tile = t >> 4, col = t & 15;
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int kp = 0; kp < KSPLIT; ++kp) {
+                    re += s_part[kp * NOUT + 2 * c_tile][s * 16 + col];
+                    im += s_part[kp * NOUT + 2 * c_tile + 1][s * 16 + col];
+                }
+                const float R = s_sc[s].w;
+                s_c[s][t] = make_float2(R * re, R * im);
+            }
+            __syncthreads();
+            // 4. receive contraction per element
+            if (re_live) {
+#pragma unroll 4
+                for (int s = 0; s < SCH; ++s) {
+                    float2 ge = make_float2(0.f, 0.f);
+                    for (int mu = 0; mu < A.nu; ++mu) {
+                        const float2 v = s_G[s * GS + re_e * A.nu + mu];
+                        ge.x += v.x;
+                        ge.y += v.y;
+                    }
+#pragma unroll
+                    for (int q = 0; q < TQ; ++q) X[jj][q] = cfma(ge, s_c[s][re_q * TQ + q], X[jj][q]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // per-element partials [item][JT][TPG][N]
+    if (re_live) {
+        float2* out = A.part + (int64_t)blockIdx.x * JT * TPG * A.N;
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj)
+#pragma unroll
+            for (int q = 0; q < TQ; ++q) out[((int64_t)jj * TPG + re_q * TQ + q) * A.N + re_e] = X[jj][q];
+    }
+}
+
+template <int NTP, int NQ>
+static hipError_t launch_mt_nq(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
+{
+    constexpr int TQ = 16 * NTP / NQ;
+    constexpr int JT = (32 / TQ) > 8 ? 8 : 32 / TQ;
+    if (c.jt != JT) return hipErrorInvalidValue;
+    if (c.has_y)
+        hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, true, false>), dim3(c.grid), dim3(512), 0, st, a);
+    else if (c.table)
+        hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, false, true>), dim3(c.grid), dim3(512), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, false, false>), dim3(c.grid), dim3(512), 0, st, a);
+    return hipGetLastError();
+}
+
+// MFMA path is used for n_tx >= 4 with nu N <= 256.
+bool mt_supported(int M, int N, int n_tx) { return n_tx >= 4 && M <= 256 && N <= 256; }
+
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
+{
+    SynthConfig c{};
+    c.bs = 512;
+    c.tt = n_tx > 16 ? 32 : 16;               // transmits per group
+    int np = 64;
+    while (np < N) np *= 2;                   // element slots
+    const int nq = 512 / np;
+    const int tq = c.tt / nq;
+    c.jt = std::min(8, 32 / tq);
+    c.sc = 16;
+    c.has_y = has_y;
+    c.mfma = true;
+    c.nq = nq;
+    (void)M;
+    return c;
+}
+
+hipError_t launch_synth_mt(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
+{
+    if (c.grid <= 0) return hipSuccess;
+    const int ntp = c.tt / 16;
+    if (ntp == 1) {
+        switch (c.nq) {
+        case 2: return launch_mt_nq<1, 2>(c, a, st);
+        case 4: return launch_mt_nq<1, 4>(c, a, st);
+        case 8: return launch_mt_nq<1, 8>(c, a, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (c.nq) {
+    case 2: return launch_mt_nq<2, 2>(c, a, st);
+    case 4: return launch_mt_nq<2, 4>(c, a, st);
+    case 8: return launch_mt_nq<2, 8>(c, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace simus

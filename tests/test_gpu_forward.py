@@ -188,3 +188,39 @@ def test_empty_and_degenerate(S):
     rf = S.rf(w["probe"], w["medium"], o, w["delays"], w["apod"], dx, None, dz, dR)
     torch.cuda.synchronize()
     assert torch.all(rf == 0)
+
+
+@pytest.mark.parametrize("n_tx,n_el,nu,with_y,no_mfma", [
+    (21, 32, 0, False, False), (33, 32, 0, False, False), (6, 32, 0, True, False),
+    (12, 64, 1, False, False), (5, 200, 1, False, False), (21, 32, 0, False, True)])
+def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
+    """Many steered plane waves: the transmit contraction on the matrix cores
+    (or, with the flag, on the VALU path) matches the oracle; covers two
+    transmit groups with a ragged last one, y != 0, nu = 1 and 200 elements."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.3)
+    w["probe"] = inputs.linear_probe(n_el)
+    w["options"]["nu"] = nu
+    w["delays"] = inputs.plane_wave_delays(w["probe"], np.linspace(-15, 15, n_tx))
+    w["apod"] = np.random.default_rng(n_tx).uniform(0.2, 1.0, w["delays"].shape).astype(np.float32)
+    if with_y:
+        w["phantoms"][0]["y"] = np.random.default_rng(1).uniform(
+            -1e-3, 1e-3, w["phantoms"][0]["x"].size).astype(np.float32)
+    g, rf, data = _run(S, w, flags=S.FLAG_NO_MFMA if no_mfma else 0, with_y=with_y)
+    ref = _oracle_rf(orc, w, g, data, with_y=with_y)
+    print(n_tx, "tx", n_el, "el rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
+def test_many_transmits_full_size_sampled_bins(S, orc):
+    """21 plane waves, 200,000 scatterers (the compounding workload) in the
+    benchmark's launch configuration: sampled bins against the oracle."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw128x21_s200k")
+    g, spec, data = _run(S, w, spectrum=True)
+    bins = sample_bins(g, 3)
+    x, y, z, R, off = data
+    ref = orc.spectrum(oracle_setup(orc, w), g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
+    got = spec[0][:, :, bins - g["j_lo"]]
+    print("pw128x21_s200k sampled bins rel L2", rel_l2(got, ref))
+    assert rel_l2(got, ref) <= TOL
