@@ -44,6 +44,8 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     __shared__ float s_part[8][256];
     __shared__ float2 s_c[SCH][TPG];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+    constexpr int WS = EP + 1;              // LDS row stride of the staged weights
+    __shared__ float2 s_W[TPG * WS];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -93,38 +95,53 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
             g[k] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
             if (!active) g[k].E = make_float2(0.f, 0.f);
         }
-        for (int jj = 0; jj < nb; ++jj) {
+        // GEMM operand lanes: rows s = lane % 16, columns t = ct * 16 + lane % 16
+        const int gi = lane & 15, gk = lane >> 4;
+        const int nbase = kpart * KW;
+        // The bin loop is unrolled so that the receive accumulators X[jj] stay
+        // in registers; nb is uniform, so the barriers inside are too.
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) {
+            if (jj >= nb) break;
             const int jb = jb0 + jj;
             const float jf = (float)(A.j_lo + jb);
             const float inv_j = rcp_fast(jf);
+            // 0. stage the transmit weights of this bin, W[t][e], in LDS
+            for (int idx = tid; idx < TPG * A.N; idx += NB) {
+                const int t = idx / A.N, e2 = idx - t * A.N;
+                const int tt = t0 + t;
+                s_W[t * WS + e2] = tt < A.n_tx ? A.W[((int64_t)jb * A.n_tx + tt) * A.N + e2]
+                                               : make_float2(0.f, 0.f);
+            }
             // 1. Green's terms of the chunk -> LDS tile [s][n]
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 s_G[(sh * 8 + k) * GS + n] = green_next<HASY, TABLE>(A.K, g[k], jf, inv_j, s_tab, P);
             __syncthreads();
-            // 2. transmit GEMM share: rows s = lane % 16, columns t = ct * 16 + lane % 16
+            // 2. transmit GEMM share; two accumulators keep the MFMA chain short
             {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                const int i = lane & 15, kk = lane >> 4;
-                const int tcol = t0 + ct * 16 + i;
-                const bool tlive = tcol < A.n_tx;
-                const float2* Wrow = A.W + ((int64_t)jb * A.n_tx + (tlive ? tcol : 0)) * A.N;
-                const int nbase = kpart * KW;
-#pragma unroll 4
-                for (int k4 = 0; k4 < KW; k4 += 4) {
-                    const int nn = nbase + k4 + kk;
-                    const float2 gv = s_G[i * GS + nn];
-                    float2 wv = make_float2(0.f, 0.f);
-                    if (tlive && nn < A.M) wv = Wrow[nn / A.nu];
+                floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < KW / 4; ++k) {
+                    const int nn = nbase + 4 * k + gk;
+                    const float2 gv = s_G[gi * GS + nn];
+                    const float2 wk = (nn < A.M) ? s_W[(ct * 16 + gi) * WS + nn / A.nu]
+                                                 : make_float2(0.f, 0.f);
                     // re: Gr Wr - Gi Wi ; im: Gr Wi + Gi Wr
-                    const float b0 = out_im ? wv.y : wv.x;
-                    const float b1 = out_im ? wv.x : -wv.y;
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, b0, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, b1, acc, 0, 0, 0);
+                    const float b0 = out_im ? wk.y : wk.x;
+                    const float b1 = out_im ? wk.x : -wk.y;
+                    if (k & 1) {
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, b0, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, b1, acc1, 0, 0, 0);
+                    } else {
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, b0, acc0, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, b1, acc0, 0, 0, 0);
+                    }
                 }
                 // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
 #pragma unroll
-                for (int v = 0; v < 4; ++v) s_part[wave][(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[v];
+                for (int v = 0; v < 4; ++v)
+                    s_part[wave][(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc0[v] + acc1[v];
             }
             __syncthreads();
             // 3. sum the shares (fixed order), scale by R_s
@@ -172,7 +189,7 @@ template <int NTP, int NQ>
 static hipError_t launch_mt_nq(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
 {
     constexpr int TQ = 16 * NTP / NQ;
-    constexpr int JT = (32 / TQ) > 8 ? 8 : 32 / TQ;
+    constexpr int JT = (16 / TQ) > 8 ? 8 : 16 / TQ;
     if (c.jt != JT) return hipErrorInvalidValue;
     if (c.has_y)
         hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, true, false>), dim3(c.grid), dim3(512), 0, st, a);
@@ -195,7 +212,7 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
     while (np < N) np *= 2;                   // element slots
     const int nq = 512 / np;
     const int tq = c.tt / nq;
-    c.jt = std::min(8, 32 / tq);
+    c.jt = std::min(8, 16 / tq);
     c.sc = 16;
     c.has_y = has_y;
     c.mfma = true;
