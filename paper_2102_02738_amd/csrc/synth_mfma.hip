@@ -1,19 +1,20 @@
 // Synthesis for many transmits: the transmit contraction of Eq. (29),
 //   a[s][t] = sum_n G[n][s] W[n][t],
 // is a complex GEMM (16 scatterers x nu N sub-elements x up to 32 transmits
-// per group) and runs on the matrix cores with FP32 MFMA (16x16x4), while
-// the Green's terms are synthesised on the VALU (green.hpp) and the receive
-// contraction of Eqs. (32)-(33),
-//   X[e][t] += sum_s (sum_{mu in e} G[mu][s]) R_s a[s][t],
-// accumulates per element in registers across all scatterers of the item.
+// per group), and so is the receive contraction of Eqs. (32)-(33),
+//   X[e][t] += sum_s (sum_{mu in e} G[mu][s]) R_s a[s][t]
+// (elements x 16 scatterers x transmits).  Both run on the matrix cores with
+// FP32 MFMA (16x16x4); the Green's terms are synthesised on the VALU
+// (green.hpp).  X accumulates in MFMA registers across all scatterers of the
+// item.
 //
 // Block: 512 threads (8 waves).  Synthesis: thread = (sub-element n, half of
 // the 16-scatterer chunk), 8 pairs stepped across the item's bin tile.
 // Transmit GEMM: a complex product is four real MFMA products; the 2 * NTP
 // output tiles (re/im of each 16-transmit tile) are spread over the 8 waves,
 // each wave covering a share of the sub-elements, and the shares are summed
-// in LDS in a fixed order.  Receive: thread = (element e, quarter of the
-// transmits).
+// in LDS in a fixed order.  Receive GEMM: wave w owns elements 16 w .. 16 w + 15
+// and all output tiles of the group.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +37,6 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     constexpr int NOUT = 2 * NTP;           // output tiles (re, im per column tile)
     constexpr int KSPLIT = 8 / NOUT;        // waves per output tile
     constexpr int KW = MS / KSPLIT;         // sub-elements per wave
-    constexpr int TQ = TPG / NQ;            // transmits per receive thread
     constexpr int EP = NB / NQ;             // element slots
 
     __shared__ float4 s_sc[SCH];
@@ -53,9 +53,9 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     const int n = tid & (MS - 1), sh = tid / MS;
     const bool active = n < A.M;
     const SubFrame fr = load_frame(A.sub, active ? n : 0);
-    // receive role
-    const int re_e = tid % EP, re_q = tid / EP;
-    const bool re_live = re_e < A.N;
+    // receive role: element tile of this wave
+    const int mt_e = wave * 16;
+    const bool re_live = mt_e < A.N;
     // GEMM role
     const int otile = wave % NOUT, kpart = wave / NOUT;
     const int ct = otile >> 1;              // column tile
@@ -73,11 +73,12 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     const int nb = min(JT, A.n_bins - jb0);
     const int t0 = tg * TPG;
 
-    float2 X[JT][TQ];
+    // receive accumulators: [bin][column tile][re, im]
+    floatx4 X[JT][NTP][2];
 #pragma unroll
     for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
-        for (int q = 0; q < TQ; ++q) X[jj][q] = make_float2(0.f, 0.f);
+        for (int c = 0; c < NTP; ++c) X[jj][c][0] = X[jj][c][1] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
         __syncthreads();
@@ -107,11 +108,15 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
             const float jf = (float)(A.j_lo + jb);
             const float inv_j = rcp_fast(jf);
             // 0. stage the transmit weights of this bin, W[t][e], in LDS
-            for (int idx = tid; idx < TPG * A.N; idx += NB) {
-                const int t = idx / A.N, e2 = idx - t * A.N;
-                const int tt = t0 + t;
-                s_W[t * WS + e2] = tt < A.n_tx ? A.W[((int64_t)jb * A.n_tx + tt) * A.N + e2]
-                                               : make_float2(0.f, 0.f);
+            {
+                const int e2 = tid % EP;
+#pragma unroll
+                for (int t = tid / EP; t < TPG; t += NQ) {
+                    const int tt = t0 + t;
+                    if (e2 < A.N)
+                        s_W[t * WS + e2] = tt < A.n_tx ? A.W[((int64_t)jb * A.n_tx + tt) * A.N + e2]
+                                                       : make_float2(0.f, 0.f);
+                }
             }
             // 1. Green's terms of the chunk -> LDS tile [s][n]
 #pragma unroll
@@ -158,38 +163,55 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 s_c[s][t] = make_float2(R * re, R * im);
             }
             __syncthreads();
-            // 4. receive contraction per element
+            // 4. receive GEMM: X[e][t] += sum_s Ge[e][s] c[s][t], rows e = mt_e + lane % 16
             if (re_live) {
-#pragma unroll 4
-                for (int s = 0; s < SCH; ++s) {
-                    float2 ge = make_float2(0.f, 0.f);
-                    for (int mu = 0; mu < A.nu; ++mu) {
-                        const float2 v = s_G[s * GS + re_e * A.nu + mu];
-                        ge.x += v.x;
-                        ge.y += v.y;
-                    }
+                const int e = mt_e + gi;
 #pragma unroll
-                    for (int q = 0; q < TQ; ++q) X[jj][q] = cfma(ge, s_c[s][re_q * TQ + q], X[jj][q]);
+                for (int k = 0; k < SCH / 4; ++k) {
+                    const int s = 4 * k + gk;
+                    float2 ge = make_float2(0.f, 0.f);
+                    if (e < A.N)
+                        for (int mu = 0; mu < A.nu; ++mu) {
+                            const float2 v = s_G[s * GS + e * A.nu + mu];
+                            ge.x += v.x;
+                            ge.y += v.y;
+                        }
+#pragma unroll
+                    for (int c = 0; c < NTP; ++c) {
+                        const float2 cv = s_c[s][c * 16 + gi];
+                        // re: Ger cr - Gei ci ; im: Ger ci + Gei cr
+                        X[jj][c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.x, cv.x, X[jj][c][0], 0, 0, 0);
+                        X[jj][c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.y, -cv.y, X[jj][c][0], 0, 0, 0);
+                        X[jj][c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.x, cv.y, X[jj][c][1], 0, 0, 0);
+                        X[jj][c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.y, cv.x, X[jj][c][1], 0, 0, 0);
+                    }
                 }
             }
             __syncthreads();
         }
     }
-    // per-element partials [item][JT][TPG][N]
+    // per-element partials [item][JT][TPG][N]; D[row][col]: row = element
+    // mt_e + 4 (lane / 16) + v, col = transmit c * 16 + lane % 16
     if (re_live) {
         float2* out = A.part + (int64_t)blockIdx.x * JT * TPG * A.N;
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
-            for (int q = 0; q < TQ; ++q) out[((int64_t)jj * TPG + re_q * TQ + q) * A.N + re_e] = X[jj][q];
+            for (int c = 0; c < NTP; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int e = mt_e + 4 * (lane >> 4) + v;
+                    const int t = c * 16 + (lane & 15);
+                    if (e < A.N)
+                        out[((int64_t)jj * TPG + t) * A.N + e] = make_float2(X[jj][c][0][v], X[jj][c][1][v]);
+                }
     }
 }
 
 template <int NTP, int NQ>
 static hipError_t launch_mt_nq(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
 {
-    constexpr int TQ = 16 * NTP / NQ;
-    constexpr int JT = (16 / TQ) > 8 ? 8 : 16 / TQ;
+    constexpr int JT = NTP == 1 ? 4 : 2;   // receive accumulators: 16 JT NTP floats
     if (c.jt != JT) return hipErrorInvalidValue;
     if (c.has_y)
         hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, true, false>), dim3(c.grid), dim3(512), 0, st, a);
@@ -201,7 +223,7 @@ static hipError_t launch_mt_nq(const SynthConfig& c, const SynthArgs& a, hipStre
 }
 
 // MFMA path is used for n_tx >= 4 with nu N <= 256.
-bool mt_supported(int M, int N, int n_tx) { return n_tx >= 4 && M <= 256 && N <= 256; }
+bool mt_supported(int M, int N, int n_tx) { return n_tx >= 4 && M <= 256 && N <= 128; }
 
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
 {
@@ -211,8 +233,7 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
     int np = 64;
     while (np < N) np *= 2;                   // element slots
     const int nq = 512 / np;
-    const int tq = c.tt / nq;
-    c.jt = std::min(8, 16 / tq);
+    c.jt = c.tt == 16 ? 4 : 2;
     c.sc = 16;
     c.has_y = has_y;
     c.mfma = true;
