@@ -194,6 +194,46 @@ int simus_pfield(const simus_probe* probe, const simus_medium* medium,
                  int64_t n_pts, const float* X, const float* Y, const float* Z,
                  float* p_rms, void* hip_stream);
 
+/* Forward plan: simus_rf for a fixed probe, medium, options, transmit
+ * sequence (delays, apod) and partition into phantoms, so that repeated
+ * syntheses of changing scatterers (Eqs. 29-34 and Eq. 1) pay the host work
+ * once.  simus_rf_plan_create validates the arguments as simus_rf does,
+ * builds the frequency band, the launch configuration and the work items of
+ * the (possibly uneven) phantoms, allocates the plan's own device workspace
+ * and uploads its tables on hip_stream, then waits for that upload.
+ * has_y: nonzero if executions pass y (y != NULL), zero if y = 0.
+ * options->flags apply to every execution (SIMUS_FLAG_PERSISTENT gives one
+ * persistent work-queue launch of the synthesis).  *plan is set only on
+ * success.  The workspace is the plan's: executions of one plan must be
+ * ordered (e.g. one stream); different plans may run concurrently. */
+typedef struct simus_rf_plan_s* simus_rf_plan;
+int simus_rf_plan_create(const simus_probe* probe, const simus_medium* medium,
+                         const simus_options* options, int32_t n_tx,
+                         const double* delays, const float* apod,
+                         int32_t n_phantoms, const int64_t* scat_offsets,
+                         int32_t has_y, void* hip_stream, simus_rf_plan* plan);
+
+/* Enqueues one forward synthesis of the plan on hip_stream: x, y, z, refl
+ * (device, scat_offsets[n_phantoms] each; y NULL iff the plan was created
+ * without y) -> rf (device [n_phantoms][n_tx][N][n_t]).  Kernel launches
+ * only: no allocation, copy or host wait, so the call may be captured into
+ * a HIP graph by the caller. */
+int simus_rf_plan_execute(simus_rf_plan plan, const float* x, const float* y,
+                          const float* z, const float* refl, float* rf, void* hip_stream);
+
+/* As simus_rf_plan_execute, through a HIP graph owned by the plan: the first
+ * call for a set of pointers (x, y, z, refl, rf) captures the plan's kernels
+ * into a graph (on a stream of the plan's own) and instantiates it; every
+ * call then launches that graph on hip_stream.  A call with other pointers
+ * captures again.  Results equal simus_rf_plan_execute's bit for bit. */
+int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* y,
+                               const float* z, const float* refl, float* rf,
+                               void* hip_stream);
+
+/* Waits for the device, then frees the plan's graph, stream and workspace.
+ * NULL is ignored. */
+void simus_rf_plan_destroy(simus_rf_plan plan);
+
 /* Frees every cached workspace (all devices, all streams).  Must not run
  * concurrently with other calls. */
 void simus_release_workspace(void);
@@ -202,7 +242,7 @@ void simus_release_workspace(void);
  * library is bracketed by a pair of HIP events recorded on the launch's
  * stream.  simus_profile_read() waits for the recorded events of one kernel
  * ("synth", "wtable", "finalize", "idft", "dft", "adjoint", "adjoint_reduce",
- * "pfield") and returns their summed duration [ms] and launch count since
+ * "pfield", or "graph" for a whole plan graph launch) and returns their summed duration [ms] and launch count since
  * the last reset.  Returns SIMUS_EINVAL for an unknown name. */
 int simus_profile_enable(int on);
 int simus_profile_read(const char* kernel, double* total_ms, int64_t* launches);

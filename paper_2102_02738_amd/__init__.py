@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import SimusError, FLAG_NO_MFMA, FLAG_PERSISTENT, FLAG_NO_DELTA_TABLE  # noqa: F401
 
 __all__ = ["grid", "rf", "rf_spectrum", "spectrum_to_rf", "rf_backward", "pfield", "pfield_nf",
-           "SimusRF", "simus_rf_autograd", "release_workspace", "SimusError"]
+           "RFPlan", "rf_plan", "SimusRF", "simus_rf_autograd", "release_workspace", "SimusError"]
 
 
 def _opts_with_grid(options: dict, g: dict) -> dict:
@@ -107,6 +107,27 @@ def pfield(probe, medium, options, n_f, delays, apod, X, Y, Z, stream=None):
     out = torch.empty_like(X)
     _lib.pfield_into(out, probe, medium, options, n_f, delays, apod, X, Y, Z, stream)
     return out
+
+
+class RFPlan(_lib.RFPlan):
+    """Forward plan (see rf_plan)."""
+
+    def rf(self, x, y, z, refl, n_t, graph=False, stream=None):
+        """RF [n_phantoms, n_tx, N, n_t] of the plan for device scatterers; with
+        graph=True through the plan's captured HIP graph."""
+        import torch
+        out = torch.empty((self.n_phantoms, self.n_tx, self.n_elements, n_t), dtype=torch.float32,
+                          device=x.device)
+        (self.graph_launch_into if graph else self.execute_into)(out, x, y, z, refl, stream)
+        return out
+
+
+def rf_plan(probe, medium, options, delays, apod, n_scat=None, offsets=None, has_y=False,
+            stream=None) -> RFPlan:
+    """Plans simus_rf once for a fixed probe, transmit sequence and phantom
+    partition (offsets, or one phantom of n_scat scatterers); options['nfft']
+    must be set (use grid())."""
+    return RFPlan(probe, medium, options, delays, apod, n_scat, offsets, has_y, stream)
 
 
 def release_workspace():

@@ -23,8 +23,9 @@ FLAG_NO_DELTA_TABLE = 4
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",
            "simus_spectrum_to_rf", "simus_rf_backward", "simus_pfield_nf", "simus_pfield",
-           "simus_release_workspace", "simus_profile_enable", "simus_profile_read",
-           "simus_profile_reset"]
+           "simus_rf_plan_create", "simus_rf_plan_execute", "simus_rf_plan_graph_launch",
+           "simus_rf_plan_destroy", "simus_release_workspace", "simus_profile_enable",
+           "simus_profile_read", "simus_profile_reset"]
 
 
 class SimusError(RuntimeError):
@@ -84,6 +85,11 @@ def lib():
                                             vp, vp, vp, vp, vp]),
             "simus_pfield_nf": (C.c_int, [pP, pM, pO, pd, i64, pf, pf, pf, pi32]),
             "simus_pfield": (C.c_int, [pP, pM, pO, i32, pd, pf, i64, vp, vp, vp, vp, vp]),
+            "simus_rf_plan_create": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, i32, vp,
+                                               P(C.c_void_p)]),
+            "simus_rf_plan_execute": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "simus_rf_plan_graph_launch": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "simus_rf_plan_destroy": (None, [vp]),
             "simus_release_workspace": (None, []),
             "simus_profile_enable": (C.c_int, [C.c_int]),
             "simus_profile_read": (C.c_int, [C.c_char_p, pd, pi64]),
@@ -236,6 +242,50 @@ def pfield_into(p_rms, probe, medium, options, n_f, delays, apod, X, Y, Z, strea
                              C.byref(make_options(options)), int(n_f), _p(d, C.c_double),
                              _p(a, C.c_float), X.numel(), _dev(X), _dev(Y), _dev(Z), _dev(p_rms),
                              _stream(stream)))
+
+
+class RFPlan:
+    """simus_rf_plan: the host work of simus_rf done once for a probe, medium,
+    options, transmit sequence and partition into phantoms.  Executions take
+    device scatterer tensors and write rf [n_phantoms, n_tx, N, n_t]."""
+
+    def __init__(self, probe, medium, options, delays, apod, n_scat=None, offsets=None,
+                 has_y=False, stream=None):
+        d, a, n_tx = _tx(probe, delays, apod)
+        if offsets is None and n_scat is None:
+            raise SimusError(-1, "n_scat or offsets is required")
+        o, n_ph = _offsets(offsets, n_scat)
+        h = C.c_void_p()
+        check(lib().simus_rf_plan_create(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                                         C.byref(make_options(options)), n_tx, _p(d, C.c_double),
+                                         _p(a, C.c_float), n_ph, _p(o, C.c_int64),
+                                         1 if has_y else 0, _stream(stream), C.byref(h)))
+        self._h = h
+        self.n_phantoms, self.n_tx, self.n_elements = n_ph, n_tx, int(probe["n_elements"])
+
+    def execute_into(self, rf, x, y, z, refl, stream=None):
+        check(lib().simus_rf_plan_execute(self._handle(), _dev(x), _dev(y), _dev(z), _dev(refl),
+                                          _dev(rf), _stream(stream)))
+
+    def graph_launch_into(self, rf, x, y, z, refl, stream=None):
+        check(lib().simus_rf_plan_graph_launch(self._handle(), _dev(x), _dev(y), _dev(z),
+                                               _dev(refl), _dev(rf), _stream(stream)))
+
+    def _handle(self):
+        if not self._h:
+            raise SimusError(-1, "plan is closed")
+        return self._h
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _lib is not None:
+            _lib.simus_rf_plan_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_workspace():

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -44,9 +45,13 @@ bool log_enabled()
 }
 
 // ---------------------------------------------------------------- kernel timing
-enum Kind { K_SYNTH, K_WTABLE, K_FINALIZE, K_IDFT, K_DFT, K_ADJ, K_ADJRED, K_PFIELD, K_COUNT };
-const char* const kKindNames[K_COUNT] = {"synth", "wtable", "finalize", "idft",
-                                         "dft", "adjoint", "adjoint_reduce", "pfield"};
+enum Kind { K_SYNTH, K_WTABLE, K_FINALIZE, K_IDFT, K_DFT, K_ADJ, K_ADJRED, K_PFIELD, K_GRAPH, K_COUNT };
+const char* const kKindNames[K_COUNT] = {"synth",   "wtable",         "finalize", "idft", "dft",
+                                         "adjoint", "adjoint_reduce", "pfield",   "graph"};
+
+// Set while this thread captures a graph: launches are then not bracketed by
+// timing events.
+thread_local bool t_capturing = false;
 
 struct Profiler {
     std::mutex mu;
@@ -94,6 +99,7 @@ Profiler g_prof;
 template <class F>
 hipError_t timed(Kind k, hipStream_t st, F&& launch)
 {
+    if (t_capturing) return launch();
     {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (!g_prof.on) return launch();
@@ -261,8 +267,7 @@ struct Common {
 
 Common make_common(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
                    int32_t n_tx, const double* delays, const float* apod, int32_t n_ph,
-                   const int64_t* offs, const float* x, const float* y, const float* z,
-                   const float* refl)
+                   const int64_t* offs, bool has_y)
 {
     Common C;
     C.P = make_probe(probe, medium, opt);
@@ -270,13 +275,29 @@ Common make_common(const simus_probe* probe, const simus_medium* medium, const s
     C.ph = check_phantoms(n_ph, offs);
     if (opt->nfft <= 0) throw Error{SIMUS_EINVAL, "options.nfft must be > 0 (see simus_rf_grid)"};
     if (opt->n_t > opt->nfft) throw Error{SIMUS_EINVAL, "options.n_t must be <= nfft"};
-    if (C.ph.total > 0 && (!x || !z || !refl)) throw Error{SIMUS_EINVAL, "x, z and refl must be non-NULL"};
     C.B = make_band(C.P, opt->nfft, opt->n_t);
     C.S = sub_elements(C.P);
     C.K = model_constants(C.P, C.B);
     C.n_tx = n_tx;
-    C.has_y = y != nullptr;
+    C.has_y = has_y;
     C.table = !C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
+    return C;
+}
+
+void check_scatterers(const Common& C, const float* x, const float* y, const float* z, const float* refl)
+{
+    if (C.ph.total > 0 && (!x || !z || !refl)) throw Error{SIMUS_EINVAL, "x, z and refl must be non-NULL"};
+    if (C.ph.total > 0 && C.has_y && !y) throw Error{SIMUS_EINVAL, "y must be non-NULL for this plan"};
+    if (!C.has_y && y) throw Error{SIMUS_EINVAL, "y must be NULL for this plan (created without y)"};
+}
+
+Common make_common(const simus_probe* probe, const simus_medium* medium, const simus_options* opt,
+                   int32_t n_tx, const double* delays, const float* apod, int32_t n_ph,
+                   const int64_t* offs, const float* x, const float* y, const float* z,
+                   const float* refl)
+{
+    Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, y != nullptr);
+    check_scatterers(C, x, y, z, refl);
     return C;
 }
 
@@ -355,127 +376,156 @@ void launch_common(char* d, const CommonLayout& L, const Common& C, const float*
 }
 
 // ---------------------------------------------------------------- forward spectra
-// Plans and enqueues the spectra into spec_out (device [P][T][N][n_bins]
-// float2), or into a workspace buffer followed by the inverse transform
-// into rf_out.
-void forward_spectra(const simus_probe* probe, const simus_medium* medium,
-                     const simus_options* opt, int32_t n_tx, const double* delays,
-                     const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
-                     const float* y, const float* z, const float* refl, float* spec_out,
-                     float* rf_out, hipStream_t st)
+// Everything the forward path decides on the host for a probe, a transmit
+// sequence and a partition into phantoms: the launch configuration, the work
+// items and the workspace layout.  `host` holds the upload region (tables,
+// items) already filled.
+struct FwdPlan {
+    Common C;
+    SynthConfig cfg{};
+    bool use_mt = false;
+    int slots = 0;    // partial slots per (item, bin, transmit): sub-elements or elements
+    int fin_nu = 0;   // sub-elements summed by the finalisation (1 once summed per element)
+    int n_bt = 0, n_items = 0;
+    int64_t slice = 0;
+    CommonLayout L{};
+    size_t o_it = 0, o_pb = 0, o_ns = 0, o_part = 0, o_tk = 0, o_spec = 0;
+    size_t up_size = 0, dv_size = 0;
+    std::vector<char> host;
+};
+
+FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, const float* apod,
+                      bool own_spec)
 {
-    if (!spec_out && !rf_out) throw Error{SIMUS_EINVAL, "output pointer must be non-NULL"};
-    const Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl);
-    const int N = C.P.N, M = C.P.M;
-    const bool use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx);
-    SynthConfig cfg = use_mt ? mt_config(M, N, n_tx, C.has_y) : synth_config(M, n_tx, C.has_y);
-    cfg.table = C.table;
+    FwdPlan F;
+    F.C = std::move(C);
+    const Common& Cc = F.C;
+    const int N = Cc.P.N, M = Cc.P.M, n_tx = Cc.n_tx, n_ph = Cc.ph.n;
+    F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx);
+    SynthConfig& cfg = F.cfg;
+    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y) : synth_config(M, n_tx, Cc.has_y);
+    cfg.table = Cc.table;
     const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;
-    // partial slots per (item, bin, transmit): sub-elements (VALU path) or elements (MFMA path)
-    const int slots = use_mt ? N : BS;
-    const int fin_nu = use_mt ? 1 : C.P.nu;
-    const int n_bt = (C.B.n_bins + JT - 1) / JT;
+    F.slots = F.use_mt ? N : BS;
+    F.fin_nu = F.use_mt ? 1 : Cc.P.nu;
+    F.n_bt = (Cc.B.n_bins + JT - 1) / JT;
     const int n_tg = (n_tx + TT - 1) / TT;
-    if (n_bt >= 65536 || n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
-    // scatterers per item: about 6000 items over the whole call
+    if (F.n_bt >= 65536 || n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
+    // scatterers per item: about 6000 items (matrix-core path: 3000) over the whole call
     int64_t slice = opt->tile_scat;
     if (slice <= 0) {
-        const int64_t work = std::max<int64_t>(1, C.ph.total) * n_bt * n_tg;
-        slice = (work + 5999) / 6000;
-        if (use_mt) slice = (work + 2999) / 3000;
+        const int64_t work = std::max<int64_t>(1, Cc.ph.total) * F.n_bt * n_tg;
+        slice = F.use_mt ? (work + 2999) / 3000 : (work + 5999) / 6000;
     }
     slice = std::max<int64_t>(slice, 4 * SC);
     slice = (slice + SC - 1) / SC * SC;
     slice = std::min<int64_t>(slice, int64_t(1) << 30);
+    F.slice = slice;
 
     std::vector<Item> items;
     std::vector<int32_t> pbase(n_ph), nsl(n_ph);
     for (int p = 0; p < n_ph; ++p) {
-        const int64_t Sp = C.ph.off[p + 1] - C.ph.off[p];
+        const int64_t Sp = Cc.ph.off[p + 1] - Cc.ph.off[p];
         const int ns = (int)((Sp + slice - 1) / slice);
         pbase[p] = (int32_t)items.size();
         nsl[p] = ns;
         for (int tg = 0; tg < n_tg; ++tg)
-            for (int bt = 0; bt < n_bt; ++bt)
+            for (int bt = 0; bt < F.n_bt; ++bt)
                 for (int sl = 0; sl < ns; ++sl) {
-                    const int64_t s0 = C.ph.off[p] + int64_t(sl) * slice;
-                    const int64_t s1 = std::min<int64_t>(s0 + slice, C.ph.off[p + 1]);
+                    const int64_t s0 = Cc.ph.off[p] + int64_t(sl) * slice;
+                    const int64_t s1 = std::min<int64_t>(s0 + slice, Cc.ph.off[p + 1]);
                     items.push_back(Item{p, (int32_t)s0, (int32_t)s1, bt | (tg << 16)});
                 }
     }
-    const int n_items = (int)items.size();
+    F.n_items = (int)items.size();
 
     Layout up;
-    CommonLayout L;
-    layout_upload(up, L, C);
-    const size_t o_it = up.add(sizeof(Item) * std::max(n_items, 1));
-    const size_t o_pb = up.add(sizeof(int32_t) * n_ph), o_ns = up.add(sizeof(int32_t) * n_ph);
+    layout_upload(up, F.L, Cc);
+    F.o_it = up.add(sizeof(Item) * std::max(F.n_items, 1));
+    F.o_pb = up.add(sizeof(int32_t) * n_ph);
+    F.o_ns = up.add(sizeof(int32_t) * n_ph);
     Layout dv = up;
-    layout_device(dv, L, C);
-    const size_t o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * JT * TT * slots);
-    const size_t o_tk = dv.add(sizeof(int32_t) * 4);
-    const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(C.B.n_bins, 1);
-    const size_t o_spec = spec_out ? 0 : dv.add(spec_bytes);
+    layout_device(dv, F.L, Cc);
+    F.o_part = dv.add(sizeof(float2) * size_t(std::max(F.n_items, 1)) * JT * TT * F.slots);
+    F.o_tk = dv.add(sizeof(int32_t) * 4);
+    const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(Cc.B.n_bins, 1);
+    F.o_spec = own_spec ? dv.add(spec_bytes) : 0;
+    F.up_size = up.size;
+    F.dv_size = dv.size;
 
-    Arena& a = arena_for(st, dv.size, up.size);
-    char* h = a.host;
-    fill_upload(h, L, C, delays, apod);
-    if (n_items) std::memcpy(h + o_it, items.data(), sizeof(Item) * n_items);
-    std::memcpy(h + o_pb, pbase.data(), sizeof(int32_t) * n_ph);
-    std::memcpy(h + o_ns, nsl.data(), sizeof(int32_t) * n_ph);
-    upload(a, up.size, st);
+    F.host.assign(up.size, 0);
+    char* h = F.host.data();
+    fill_upload(h, F.L, Cc, delays, apod);
+    if (F.n_items) std::memcpy(h + F.o_it, items.data(), sizeof(Item) * F.n_items);
+    std::memcpy(h + F.o_pb, pbase.data(), sizeof(int32_t) * n_ph);
+    std::memcpy(h + F.o_ns, nsl.data(), sizeof(int32_t) * n_ph);
 
-    char* d = a.dev;
-    float2* spec = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(d, o_spec);
-    launch_common(d, L, C, x, y, z, st);
+    cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0 && F.n_items > 0;
+    if (cfg.persistent) {
+        hipDeviceProp_t prop;
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        // resident blocks: two of 256 threads per CU (VALU path), one of 512 (matrix-core path)
+        const int per_cu = std::max(1, 512 / BS);
+        cfg.grid = std::min(F.n_items, prop.multiProcessorCount * per_cu);
+    } else {
+        cfg.grid = F.n_items;
+    }
+    return F;
+}
+
+// Enqueues the forward kernels of a plan on st (kernel launches only: no
+// copies, allocations or host waits), with the workspace at device address d
+// holding the plan's upload region.  Spectra go to spec_out, or to the
+// workspace followed by the inverse transform into rf_out.
+void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, const float* z,
+                 const float* refl, float* spec_out, float* rf_out, hipStream_t st)
+{
+    const Common& C = F.C;
+    const SynthConfig& cfg = F.cfg;
+    const int N = C.P.N, n_tx = C.n_tx, n_ph = C.ph.n;
+    float2* spec = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(d, F.o_spec);
+    launch_common(d, F.L, C, x, y, z, st);
     SynthArgs A{};
     A.x = x;
     A.y = y;
     A.z = z;
     A.refl = refl;
-    A.sub = sub_geo(d, L);
-    A.W = at<float2>(d, L.W);
-    A.items = at<Item>(d, o_it);
-    A.n_items = n_items;
-    A.part = at<float2>(d, o_part);
-    A.M = M;
+    A.sub = sub_geo(d, F.L);
+    A.W = at<float2>(d, F.L.W);
+    A.items = at<Item>(d, F.o_it);
+    A.n_items = F.n_items;
+    A.part = at<float2>(d, F.o_part);
+    A.M = C.P.M;
     A.nu = C.P.nu;
     A.N = N;
     A.n_tx = n_tx;
     A.n_bins = C.B.n_bins;
     A.j_lo = C.B.j_lo;
     A.K = C.K;
-    A.dtab = C.table ? at<float4>(d, L.dt) : nullptr;
-    A.dpar = C.table ? at<DeltaParams>(d, L.dp) : nullptr;
+    A.dtab = C.table ? at<float4>(d, F.L.dt) : nullptr;
+    A.dpar = C.table ? at<DeltaParams>(d, F.L.dp) : nullptr;
     A.ticket = nullptr;
-    cfg.persistent = !use_mt && (opt->flags & SIMUS_FLAG_PERSISTENT) != 0;
-    if (cfg.persistent && n_items > 0) {
-        A.ticket = at<int32_t>(d, o_tk);
+    if (cfg.persistent) {
+        A.ticket = at<int32_t>(d, F.o_tk);
         hip_check(launch_zero_i32(A.ticket, 1, st), "zero launch");
-        hipDeviceProp_t prop;
-        int dev = 0;
-        hip_check(hipGetDevice(&dev), "hipGetDevice");
-        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        const int per_cu = std::max(1, 512 / BS);
-        cfg.grid = std::min(n_items, prop.multiProcessorCount * per_cu);
-    } else {
-        cfg.grid = n_items;
     }
     if (log_enabled())
         std::fprintf(stderr,
                      "[simus] N=%d nu=%d M=%d T=%d P=%d S=%lld nfft=%d n_t=%d j_lo=%d bins=%d "
                      "BS=%d TT=%d SC=%d JT=%d slice=%lld items=%d grid=%d y=%d table=%d persistent=%d mfma=%d\n",
-                     N, C.P.nu, M, n_tx, n_ph, (long long)C.ph.total, C.B.nfft, C.B.n_t, C.B.j_lo,
-                     C.B.n_bins, BS, TT, SC, JT, (long long)slice, n_items, cfg.grid, (int)C.has_y,
-                     (int)C.table, (int)cfg.persistent, (int)use_mt);
+                     N, C.P.nu, C.P.M, n_tx, n_ph, (long long)C.ph.total, C.B.nfft, C.B.n_t, C.B.j_lo,
+                     C.B.n_bins, cfg.bs, cfg.tt, cfg.sc, cfg.jt, (long long)F.slice, F.n_items, cfg.grid,
+                     (int)C.has_y, (int)C.table, (int)cfg.persistent, (int)F.use_mt);
     hip_check(timed(K_SYNTH, st, [&] {
-                  return use_mt ? launch_synth_mt(cfg, A, st) : launch_synth(cfg, A, st);
+                  return F.use_mt ? launch_synth_mt(cfg, A, st) : launch_synth(cfg, A, st);
               }),
               "synthesis launch");
     hip_check(timed(K_FINALIZE, st, [&] {
-                  return launch_finalize(spec, A.part, at<float2>(d, L.pw), at<int32_t>(d, o_pb),
-                                         at<int32_t>(d, o_ns), n_ph, n_tx, N, fin_nu, C.B.n_bins,
-                                         slots, TT, JT, n_bt, st);
+                  return launch_finalize(spec, A.part, at<float2>(d, F.L.pw), at<int32_t>(d, F.o_pb),
+                                         at<int32_t>(d, F.o_ns), n_ph, n_tx, N, F.fin_nu, C.B.n_bins,
+                                         F.slots, cfg.tt, cfg.jt, F.n_bt, st);
               }),
               "finalize launch");
     if (rf_out) {
@@ -485,6 +535,22 @@ void forward_spectra(const simus_probe* probe, const simus_medium* medium,
                   }),
                   "inverse transform launch");
     }
+}
+
+// One call: plan, upload through the stream's staging buffer, enqueue.
+void forward_spectra(const simus_probe* probe, const simus_medium* medium,
+                     const simus_options* opt, int32_t n_tx, const double* delays,
+                     const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
+                     const float* y, const float* z, const float* refl, float* spec_out,
+                     float* rf_out, hipStream_t st)
+{
+    if (!spec_out && !rf_out) throw Error{SIMUS_EINVAL, "output pointer must be non-NULL"};
+    Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl);
+    const FwdPlan F = make_fwd_plan(std::move(C), opt, delays, apod, spec_out == nullptr);
+    Arena& a = arena_for(st, F.dv_size, F.up_size);
+    std::memcpy(a.host, F.host.data(), F.up_size);
+    upload(a, F.up_size, st);
+    enqueue_fwd(F, a.dev, x, y, z, refl, spec_out, rf_out, st);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -684,6 +750,45 @@ int guarded(Fn&& fn)
 
 using namespace simus;
 
+// A forward plan: the host plan, its device workspace (upload region first)
+// and the graph captured for the last pointer set.
+struct simus_rf_plan_s {
+    FwdPlan F;
+    int device = 0;
+    char* dev = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key[5] = {};
+    std::mutex mu;
+
+    ~simus_rf_plan_s()
+    {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (dev) (void)hipFree(dev);
+        (void)hipSetDevice(cur);
+    }
+};
+
+namespace {
+
+void check_plan_call(simus_rf_plan plan, const float* x, const float* y, const float* z,
+                     const float* refl, const float* rf)
+{
+    if (!plan) throw Error{SIMUS_EINVAL, "plan must be non-NULL"};
+    if (!rf) throw Error{SIMUS_EINVAL, "rf must be non-NULL"};
+    check_scatterers(plan->F.C, x, y, z, refl);
+    int cur = 0;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != plan->device) throw Error{SIMUS_EINVAL, "plan belongs to another device"};
+}
+
+}  // namespace
+
 extern "C" {
 
 int simus_version(void) { return SIMUS_VERSION; }
@@ -784,6 +889,84 @@ int simus_pfield(const simus_probe* probe, const simus_medium* medium, const sim
                static_cast<hipStream_t>(hip_stream));
     });
 }
+
+int simus_rf_plan_create(const simus_probe* probe, const simus_medium* medium,
+                         const simus_options* opt, int32_t n_tx, const double* delays,
+                         const float* apod, int32_t n_ph, const int64_t* offs, int32_t has_y,
+                         void* hip_stream, simus_rf_plan* out)
+{
+    return guarded([&] {
+        if (!out) throw Error{SIMUS_EINVAL, "plan must be non-NULL"};
+        Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, has_y != 0);
+        std::unique_ptr<simus_rf_plan_s> pl(new simus_rf_plan_s);
+        pl->F = make_fwd_plan(std::move(C), opt, delays, apod, true);
+        hip_check(hipGetDevice(&pl->device), "hipGetDevice");
+        if (hipMalloc(&pl->dev, pl->F.dv_size) != hipSuccess) {
+            pl->dev = nullptr;
+            (void)hipGetLastError();
+            throw Error{SIMUS_ENOMEM, "plan workspace allocation failed"};
+        }
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        hip_check(hipMemcpyAsync(pl->dev, pl->F.host.data(), pl->F.up_size, hipMemcpyHostToDevice, st),
+                  "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        *out = pl.release();
+    });
+}
+
+int simus_rf_plan_execute(simus_rf_plan plan, const float* x, const float* y, const float* z,
+                          const float* refl, float* rf, void* hip_stream)
+{
+    return guarded([&] {
+        check_plan_call(plan, x, y, z, refl, rf);
+        enqueue_fwd(plan->F, plan->dev, x, y, z, refl, nullptr, rf, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* y, const float* z,
+                               const float* refl, float* rf, void* hip_stream)
+{
+    return guarded([&] {
+        check_plan_call(plan, x, y, z, refl, rf);
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        std::lock_guard<std::mutex> lk(plan->mu);
+        const void* key[5] = {x, y, z, refl, rf};
+        if (!plan->exec || !std::equal(key, key + 5, plan->key)) {
+            if (plan->exec) {
+                // an earlier launch of the old graph may still run
+                hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+                hip_check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
+                plan->exec = nullptr;
+            }
+            if (!plan->cap)
+                hip_check(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking), "hipStreamCreate");
+            hip_check(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal),
+                      "hipStreamBeginCapture");
+            hipGraph_t g = nullptr;
+            t_capturing = true;
+            try {
+                enqueue_fwd(plan->F, plan->dev, x, y, z, refl, nullptr, rf, plan->cap);
+            } catch (...) {
+                t_capturing = false;
+                (void)hipStreamEndCapture(plan->cap, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            t_capturing = false;
+            hip_check(hipStreamEndCapture(plan->cap, &g), "hipStreamEndCapture");
+            const hipError_t e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                plan->exec = nullptr;
+                hip_check(e, "hipGraphInstantiate");
+            }
+            std::copy(key, key + 5, plan->key);
+        }
+        hip_check(timed(K_GRAPH, st, [&] { return hipGraphLaunch(plan->exec, st); }), "hipGraphLaunch");
+    });
+}
+
+void simus_rf_plan_destroy(simus_rf_plan plan) { delete plan; }
 
 int simus_spectrum_to_rf(int32_t nfft, int32_t n_t, int32_t j_lo, int32_t n_bins, int64_t n_chan,
                          const float* spec, float* rf, void* hip_stream)

@@ -6,6 +6,7 @@
 // Built by paper_2102_02738_amd/build.py as diag/valu_rate.
 #include <hip/hip_runtime.h>
 #include <cstdio>
+#include <cstdlib>
 #define CH 8
 #define IT 2048
 template <int OP>
@@ -30,13 +31,20 @@ __global__ __launch_bounds__(256) void k(float* out, float seed) {
   for (int c = 0; c < CH; ++c) s += v[c];
   out[blockIdx.x * 256 + threadIdx.x] = s;
 }
+static void chk(hipError_t e) {
+  if (e != hipSuccess) { fprintf(stderr, "HIP error: %s\n", hipGetErrorString(e)); exit(1); }
+}
 template <int OP> double run(float* d, int blocks) {
-  hipEvent_t a, b; hipEventCreate(&a); hipEventCreate(&b);
+  hipEvent_t a, b;
+  chk(hipEventCreate(&a)); chk(hipEventCreate(&b));
   hipLaunchKernelGGL(k<OP>, dim3(blocks), dim3(256), 0, 0, d, 0.3f);
-  hipEventRecord(a);
+  chk(hipGetLastError());
+  chk(hipEventRecord(a));
   for (int r = 0; r < 5; ++r) hipLaunchKernelGGL(k<OP>, dim3(blocks), dim3(256), 0, 0, d, 0.3f);
-  hipEventRecord(b); hipEventSynchronize(b);
-  float ms; hipEventElapsedTime(&ms, a, b);
+  chk(hipGetLastError());
+  chk(hipEventRecord(b)); chk(hipEventSynchronize(b));
+  float ms; chk(hipEventElapsedTime(&ms, a, b));
+  chk(hipEventDestroy(a)); chk(hipEventDestroy(b));
   double ops = 5.0 * blocks * 256.0 * CH * IT * (OP == 5 ? 4 : 1);
   return ops / (ms * 1e-3);
 }
@@ -48,7 +56,7 @@ int main() {
   r[0] = run<0>(d, blocks); r[1] = run<1>(d, blocks); r[2] = run<2>(d, blocks); r[3] = run<3>(d, blocks);
   r[4] = run<4>(d, blocks); r[5] = run<5>(d, blocks); r[6] = run<6>(d, blocks);
   for (int i = 0; i < 7; ++i) printf("%-10s %.3e lane-instr/s  (%.3f of 3.93e13)\n", names[i], r[i], r[i] / 3.93216e13);
-  hipDeviceProp_t p; hipGetDeviceProperties(&p, 0);
+  hipDeviceProp_t p; chk(hipGetDeviceProperties(&p, 0));
   printf("CUs %d clock %d kHz\n", p.multiProcessorCount, p.clockRate);
   return hipDeviceSynchronize() != hipSuccess;
 }

@@ -164,6 +164,37 @@ def test_device_entry_points_validate_before_gpu(L):
     assert rc == -1
 
 
+def test_plan_entry_points_validate_before_gpu(L):
+    """Plan creation rejects invalid arguments on the host (EINVAL, no plan
+    returned); execute and graph launch reject a NULL plan; destroy ignores
+    NULL."""
+    w = _base()
+    lib = L.lib()
+    P, M = L.make_probe(w["probe"]), L.make_medium(w["medium"])
+    d = np.ascontiguousarray(w["delays"], dtype=np.float64)
+    a = np.ones_like(d, dtype=np.float32)
+    off = np.array([0, 10], dtype=np.int64)
+    pd = d.ctypes.data_as(C.POINTER(C.c_double))
+    pa = a.ctypes.data_as(C.POINTER(C.c_float))
+    po = off.ctypes.data_as(C.POINTER(C.c_int64))
+    h = C.c_void_p()
+    for O, ntx, nph in [(L.make_options(w["options"], nfft=0), 1, 1),
+                        (L.make_options(w["options"], nfft=1280), 0, 1),
+                        (L.make_options(w["options"], nfft=1280), 1, 0),
+                        (L.make_options(w["options"], nfft=1280, n_t=2000), 1, 1)]:
+        rc = lib.simus_rf_plan_create(C.byref(P), C.byref(M), C.byref(O), ntx, pd, pa, nph, po, 0,
+                                      None, C.byref(h))
+        assert rc == -1, lib.simus_last_error()
+        assert not h.value
+    O = L.make_options(w["options"], nfft=1280)
+    assert lib.simus_rf_plan_create(C.byref(P), C.byref(M), C.byref(O), 1, pd, pa, 1, po, 0, None,
+                                    None) == -1
+    fake = C.c_void_p(0x1000)
+    assert lib.simus_rf_plan_execute(None, fake, None, fake, fake, fake, None) == -1
+    assert lib.simus_rf_plan_graph_launch(None, fake, None, fake, fake, fake, None) == -1
+    lib.simus_rf_plan_destroy(None)
+
+
 def test_package_raises_without_library(monkeypatch, tmp_path):
     """The product path fails loudly when the HIP library is missing."""
     from paper_2102_02738_amd import _lib
