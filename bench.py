@@ -1,35 +1,49 @@
 #!/usr/bin/env python3
 """Benchmark of the SIMUS RF synthesis hot path on one MI355X.
 
-One step = one simus_rf call on the 128-element, 50,000-scatterer plane-wave
-workload (pw128_s50k): transmit weights, Green's-tile synthesis with both
-contractions, finalisation and the inverse transform to RF, inputs already
-resident in HBM.  Prints one JSON line.
+Main line: one step = one simus_rf call on the 128-element, 50,000-scatterer
+plane-wave workload (pw128_s50k): transmit weights, elevation table,
+Green's-tile synthesis with both contractions, finalisation and the inverse
+transform to RF, inputs already resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+Extras in the same line (skipped with --no-extras), each against the plain
+path (a per-transmit, per-phantom loop of single-transmit calls on the
+vector path, no graph):
+  batched_transmits   21 plane waves x 200,000 scatterers in one call
+                      (transmit and receive contractions on the matrix cores)
+  uneven_phantoms     16 convex-probe phantoms of 10k-500k scatterers x 11
+                      diverging waves in one persistent launch replayed as a
+                      HIP graph
+  forward_adjoint     5 plane waves x 100,000 scatterers: forward, residual
+                      against a perturbed phantom's RF, adjoint gradients
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Issue cost model of the synthesis loop (counted from the gfx950 ISA of
-# k_synth<256, 8, 16, 1, false>: instructions per Green's term, see the
-# design notes); transcendentals are weighted by their issue cost.
-SYNTH_VALU_PER_G = 84          # full-rate VALU instructions per G term
-SYNTH_TRANS_PER_G = 13         # transcendental instructions per G term
+# Issue-cost model of the synthesis kernel this workload runs,
+# k_synth<256, 8, 16, 1, false, true>: instructions per Green's term in its
+# innermost (bin) loop, counted from the gfx950 assembly with
+# paper_2102_02738_amd/diag/isa_count.py (8 terms per iteration and lane).
+SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELb1EEEvNS_9SynthArgsE"
+SYNTH_VALU_PER_G = 51.875      # full-rate VALU instructions per G term
+SYNTH_TRANS_PER_G = 1.125      # transcendental instructions per G term
 TRANS_ISSUE_COST = 4.0         # a transcendental issues at 1/4 of the FP32 rate (diag/valu_rate)
 # MI355X FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-instructions/s
-# (256 CU x 128 FP32 lanes/clk x 2.4 GHz); one VALU "op" below = one lane slot.
+# (256 CU x 128 FP32 lanes/clk x 2.4 GHz); one "slot" = one lane-instruction.
 VALU_PEAK = 256 * 128 * 2.4e9
+MFMA_FP32_PEAK = 157.3e12      # dense FP32 matrix-core FLOP/s
 
 
 def kernel_sources_digest() -> str:
@@ -77,14 +91,189 @@ def cpu_baseline(w, g, x, y, z, R, stride: int):
                        f"bins ({bins.size} bins), direct FP64 sum, {dt:.1f} s")
 
 
+def _sync_ms(fn) -> float:
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3
+
+
+def _median_ms(fn, steps: int, warmup: int = 1) -> float:
+    for _ in range(warmup):
+        _sync_ms(fn)
+    return statistics.median(_sync_ms(fn) for _ in range(steps))
+
+
+def _rel(a, b) -> float:
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b).clamp_min(1e-30))
+
+
+class Case:
+    """A workload on the device: scatterers, grid and options."""
+
+    def __init__(self, name: str):
+        import torch
+        from paper_2102_02738_amd import inputs, grid
+        self.w = w = inputs.workload(name)
+        self.name = name
+        x, y, z, R, off = inputs.concat_phantoms(w["phantoms"])
+        self.host = (x, y, z, R)
+        self.off = off
+        self.g = grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
+        self.o = dict(w["options"], nfft=self.g["nfft"], n_t=self.g["n_t"])
+        dev = torch.device("cuda:0")
+        self.x, self.z, self.R = (torch.from_numpy(a).to(dev) for a in (x, z, R))
+        self.T, self.N = w["delays"].shape
+        self.P = len(w["phantoms"])
+        self.S = x.size
+        self.n_t = self.g["n_t"]
+
+    def evals(self) -> float:
+        return float(self.S) * self.N * self.g["n_bins"] * self.T
+
+    def offsets(self):
+        return self.off if self.P > 1 else None
+
+
+def extra_batched_transmits(steps: int) -> dict:
+    """21 plane waves in one call vs 21 single-transmit calls."""
+    import torch
+    from paper_2102_02738_amd import _lib, FLAG_NO_MFMA
+    c = Case("pw128x21_s200k")
+    w = c.w
+    out = torch.empty((1, c.T, c.N, c.n_t), device="cuda")
+    plain = torch.empty_like(out)
+
+    def batched():
+        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R)
+
+    po = dict(c.o, flags=FLAG_NO_MFMA)
+
+    def loop():
+        for t in range(c.T):
+            _lib.rf_into(plain[:, t:t + 1], w["probe"], w["medium"], po, w["delays"][t:t + 1],
+                         w["apod"][t:t + 1], c.x, None, c.z, c.R)
+
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    b_ms = _median_ms(batched, steps)
+    _lib.profile_enable(False)
+    synth_ms, n = _lib.profile_read("synth")
+    synth_ms /= max(n, 1)
+    p_ms = _median_ms(loop, 1, warmup=0)
+    # contraction flops (algorithmic, 21 transmits): Tx over nu N sub-elements
+    # and Rx over N elements, 8 real flops per complex multiply-add
+    flops = 8.0 * c.S * c.g["n_bins"] * c.T * (c.g["nu"] * c.N + c.N)
+    return dict(workload=c.name, n_tx=c.T, n_scatterers=c.S, n_bins=c.g["n_bins"],
+                batched_ms=b_ms, plain_ms=p_ms, speedup_vs_plain=p_ms / b_ms,
+                evals_per_s=c.evals() / (b_ms * 1e-3), rf_frames_per_s=c.T / (b_ms * 1e-3),
+                synth_kernel_ms=synth_ms,
+                mfma_contraction_tflops=flops / (synth_ms * 1e-3) / 1e12,
+                mfma_frac_of_fp32_peak=flops / (synth_ms * 1e-3) / MFMA_FP32_PEAK,
+                rel_l2_batched_vs_plain=_rel(out, plain))
+
+
+def extra_uneven_phantoms(steps: int) -> dict:
+    """16 uneven phantoms x 11 diverging waves: one persistent graph launch
+    vs a loop of single-phantom, single-transmit calls."""
+    import torch
+    from paper_2102_02738_amd import _lib, rf_plan, FLAG_PERSISTENT, FLAG_NO_MFMA
+    c = Case("cvx128x11_p16")
+    w = c.w
+    out = torch.empty((c.P, c.T, c.N, c.n_t), device="cuda")
+    plain = torch.empty_like(out)
+    plan = rf_plan(w["probe"], w["medium"], dict(c.o, flags=FLAG_PERSISTENT), w["delays"], w["apod"],
+                   offsets=c.off)
+
+    def graph():
+        plan.graph_launch_into(out, c.x, None, c.z, c.R)
+
+    g_ms = _median_ms(graph, steps)
+    static = torch.empty_like(out)
+    s_ms = _median_ms(lambda: _lib.rf_into(static, w["probe"], w["medium"], c.o, w["delays"],
+                                           w["apod"], c.x, None, c.z, c.R, c.off), 1)
+    po = dict(c.o, flags=FLAG_NO_MFMA)
+    off = c.off
+
+    def loop():
+        for p in range(c.P):
+            sl = slice(int(off[p]), int(off[p + 1]))
+            for t in range(c.T):
+                _lib.rf_into(plain[p:p + 1, t:t + 1], w["probe"], w["medium"], po,
+                             w["delays"][t:t + 1], w["apod"][t:t + 1], c.x[sl], None, c.z[sl],
+                             c.R[sl])
+
+    p_ms = _median_ms(loop, 1, warmup=0)
+    plan.close()
+    return dict(workload=c.name, n_phantoms=c.P, n_tx=c.T, n_scatterers=c.S,
+                scatterers_min=int(min(off[1:] - off[:-1])), scatterers_max=int(max(off[1:] - off[:-1])),
+                graph_ms=g_ms, batched_static_call_ms=s_ms, plain_ms=p_ms,
+                speedup_vs_plain=p_ms / g_ms, evals_per_s=c.evals() / (g_ms * 1e-3),
+                rf_frames_per_s=c.P * c.T / (g_ms * 1e-3),
+                rel_l2_graph_vs_plain=_rel(out, plain), graph_equals_static=bool(torch.equal(out, static)))
+
+
+def extra_forward_adjoint(steps: int) -> dict:
+    """Forward + residual + adjoint of the L2 misfit, 5 plane waves in one
+    call each vs a per-transmit loop."""
+    import torch
+    from paper_2102_02738_amd import _lib, inputs, FLAG_NO_MFMA
+    c = Case("pw128x5_s100k")
+    w = c.w
+    obs = inputs.perturbed(w["phantoms"][0])
+    ox, oz, oR = (torch.from_numpy(obs[k]).cuda() for k in ("x", "z", "R"))
+    rf_obs = torch.empty((1, c.T, c.N, c.n_t), device="cuda")
+    _lib.rf_into(rf_obs, w["probe"], w["medium"], c.o, w["delays"], w["apod"], ox, None, oz, oR)
+    out = torch.empty_like(rf_obs)
+    grads = {k: torch.empty_like(c.x) for k in ("refl", "x", "z")}
+
+    def fwd():
+        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R)
+
+    def step():
+        fwd()
+        res = out - rf_obs
+        _lib.rf_backward_into(grads, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None,
+                              c.z, c.R, res)
+
+    f_ms = _median_ms(fwd, steps)
+    s_ms = _median_ms(step, steps)
+    po = dict(c.o, flags=FLAG_NO_MFMA)
+    pg = {k: torch.zeros_like(c.x) for k in grads}
+    gt = {k: torch.empty_like(c.x) for k in grads}
+    o1 = torch.empty((1, 1, c.N, c.n_t), device="cuda")
+
+    def loop():
+        for v in pg.values():
+            v.zero_()
+        for t in range(c.T):
+            d, a = w["delays"][t:t + 1], w["apod"][t:t + 1]
+            _lib.rf_into(o1, w["probe"], w["medium"], po, d, a, c.x, None, c.z, c.R)
+            res = o1 - rf_obs[:, t:t + 1]
+            _lib.rf_backward_into(gt, w["probe"], w["medium"], po, d, a, c.x, None, c.z, c.R, res)
+            for k in pg:
+                pg[k] += gt[k]
+
+    p_ms = _median_ms(loop, 1)
+    return dict(workload=c.name, n_tx=c.T, n_scatterers=c.S, forward_ms=f_ms, forward_adjoint_ms=s_ms,
+                plain_forward_adjoint_ms=p_ms, speedup_vs_plain=p_ms / s_ms,
+                rf_frames_per_s_forward=c.T / (f_ms * 1e-3),
+                rf_frames_per_s_forward_adjoint=c.T / (s_ms * 1e-3),
+                rel_l2_grad_vs_plain={k: _rel(grads[k], pg[k]) for k in grads})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pw128_s50k")
-    ap.add_argument("--cpu-stride", type=int, default=48)
+    ap.add_argument("--cpu-stride", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extra-steps", type=int, default=2)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -94,7 +283,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -109,23 +297,15 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 3}))
         return
 
-    import paper_2102_02738_amd as S
-    from paper_2102_02738_amd import _lib, inputs
-    from tests.helpers import concat_phantoms
+    from paper_2102_02738_amd import _lib
 
-    w = inputs.workload(args.workload)
-    x, y, z, R, off = concat_phantoms(w["phantoms"])
-    g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
-    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"])
-    dev = torch.device("cuda:0")
-    dx, dz, dR = (torch.from_numpy(a).to(dev) for a in (x, z, R))
-    T, N = w["delays"].shape
-    n_ph = len(w["phantoms"])
-    offs = off if n_ph > 1 else None
-    out = torch.empty((n_ph, T, N, g["n_t"]), dtype=torch.float32, device=dev)
+    c = Case("pw128_s50k")
+    w = c.w
+    out = torch.empty((c.P, c.T, c.N, c.n_t), dtype=torch.float32, device="cuda")
 
     def step():
-        _lib.rf_into(out, w["probe"], w["medium"], o, w["delays"], w["apod"], dx, None, dz, dR, offs)
+        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R,
+                     c.offsets())
 
     for _ in range(args.warmup):
         step()
@@ -143,33 +323,39 @@ def main():
     other = {k: _lib.profile_read(k) for k in ("wtable", "finalize", "idft")}
 
     ms_per_step = wall * 1e3 / args.steps
-    S_tot = x.size
-    evals = S_tot * N * g["n_bins"] * T
-    value = evals / (ms_per_step * 1e-3)
-    g_terms = S_tot * N * g["nu"] * g["n_bins"]   # each G term serves every transmit
+    value = c.evals() / (ms_per_step * 1e-3)
+    g_terms = float(c.S) * c.N * c.g["nu"] * c.g["n_bins"]   # each G term serves every transmit
     synth_avg_ms = synth_ms / max(synth_n, 1)
-    slots = g_terms * (SYNTH_VALU_PER_G + TRANS_ISSUE_COST * SYNTH_TRANS_PER_G)
-    achieved = slots / (synth_avg_ms * 1e-3)
+    per_g = SYNTH_VALU_PER_G + TRANS_ISSUE_COST * SYNTH_TRANS_PER_G
+    achieved = g_terms * per_g / (synth_avg_ms * 1e-3)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="TOP/s",
-                frac=achieved / VALU_PEAK, traffic=measured_traffic(args.workload),
-                kernel="k_synth", kernel_ms=synth_avg_ms,
-                ops_per_unit=SYNTH_VALU_PER_G + TRANS_ISSUE_COST * SYNTH_TRANS_PER_G,
-                unit_count=g_terms, unit_def="G term (sub-element x scatterer x bin)")
+                frac=achieved / VALU_PEAK, traffic=measured_traffic(c.name),
+                kernel="k_synth<256, 8, 16, 1, false, true>", kernel_ms=synth_avg_ms,
+                ops_per_unit=per_g, valu_per_unit=SYNTH_VALU_PER_G, trans_per_unit=SYNTH_TRANS_PER_G,
+                unit_count=g_terms, unit_def="G term (sub-element x scatterer x bin)",
+                op_def="lane issue slot: full-rate VALU 1, transcendental 4")
     res = {
         "metric": "scatterer*element*freq evals/s", "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_elements": N, "n_scatterers": S_tot,
-                   "n_tx": T, "n_phantoms": n_ph, "nfft": g["nfft"], "n_bins": g["n_bins"],
-                   "n_t": g["n_t"], "nu": g["nu"]},
+        "config": {"workload": c.name, "n_elements": c.N, "n_scatterers": c.S,
+                   "n_tx": c.T, "n_phantoms": c.P, "nfft": c.g["nfft"], "n_bins": c.g["n_bins"],
+                   "n_t": c.n_t, "nu": c.g["nu"]},
         "g_terms_per_s": g_terms / (ms_per_step * 1e-3),
-        "rf_frames_per_s": n_ph * T / (ms_per_step * 1e-3),
+        "rf_frames_per_s": c.P * c.T / (ms_per_step * 1e-3),
         "kernel_ms": {"synth": synth_avg_ms, **{k: v[0] / max(v[1], 1) for k, v in other.items()}},
         "roofline": roof,
     }
+    if not args.no_extras:
+        res["extras"] = {
+            "batched_transmits": extra_batched_transmits(args.extra_steps),
+            "uneven_phantoms": extra_uneven_phantoms(args.extra_steps),
+            "forward_adjoint": extra_forward_adjoint(args.extra_steps),
+        }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, g, x, y, z, R, args.cpu_stride)
+        x, y, z, R = c.host
+        res["cpu_baseline"] = cpu_baseline(w, c.g, x, y, z, R, args.cpu_stride)
     print(json.dumps(res))
 
 

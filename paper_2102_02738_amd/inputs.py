@@ -149,6 +149,17 @@ def workload(name: str, seed: int = 0, scale: float = 1.0) -> dict:
     raise KeyError(name)
 
 
+def concat_phantoms(phs):
+    """Concatenated SoA scatterers of a list of phantoms and the offsets
+    [P + 1] of each phantom's first scatterer."""
+    x = np.concatenate([p["x"] for p in phs])
+    y = np.concatenate([p["y"] for p in phs])
+    z = np.concatenate([p["z"] for p in phs])
+    R = np.concatenate([p["R"] for p in phs])
+    off = np.cumsum([0] + [p["x"].size for p in phs]).astype(np.int64)
+    return x, y, z, R, off
+
+
 def perturbed(ph: dict, seed: int = 1, sigma_pos: float = 50e-6, sigma_R: float = 0.1) -> dict:
     """Observed phantom for the misfit: positions + N(0, 50 um), R + N(0, 0.1)."""
     rng = np.random.default_rng(seed)

@@ -4,6 +4,8 @@ import math
 
 import numpy as np
 
+from paper_2102_02738_amd.inputs import concat_phantoms  # noqa: F401
+
 ORACLE_KEYS = ["n_elements", "fc", "pitch", "width", "height", "elev_focus", "bandwidth", "radius",
                "baffle", "zeta"]
 
@@ -14,15 +16,6 @@ def oracle_setup(orc, w: dict, nu: int = 0):
     return orc.Setup(**{k: p[k] for k in ORACLE_KEYS}, c=w["medium"]["c"],
                      alpha_db=w["medium"]["alpha_db"], fs=o["fs"], n_cycles=o["n_cycles"],
                      nu=nu or o.get("nu", 0))
-
-
-def concat_phantoms(phs):
-    x = np.concatenate([p["x"] for p in phs])
-    y = np.concatenate([p["y"] for p in phs])
-    z = np.concatenate([p["z"] for p in phs])
-    R = np.concatenate([p["R"] for p in phs])
-    off = np.cumsum([0] + [p["x"].size for p in phs]).astype(np.int64)
-    return x, y, z, R, off
 
 
 def rel_l2(a, b) -> float:

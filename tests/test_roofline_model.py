@@ -1,0 +1,37 @@
+"""The issue-cost constants of bench.py's roofline are the instruction mix of
+the synthesis kernel the benchmark runs, re-counted here from the gfx950
+assembly of the current sources (hipcc cross-compiles without a GPU)."""
+import os
+import re
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc not available")
+def test_bench_cost_constants_match_isa():
+    sys.path.insert(0, ROOT)
+    import bench
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "paper_2102_02738_amd", "diag", "isa_count.py"),
+                          "kernels.hip", bench.SYNTH_KERNEL, "--terms", "8"],
+                         check=True, capture_output=True, text=True).stdout
+    valu = float(re.search(r"valu_per_term: ([0-9.]+)", out).group(1))
+    trans = float(re.search(r"trans_per_term: ([0-9.]+)", out).group(1))
+    assert valu == pytest.approx(bench.SYNTH_VALU_PER_G, abs=1e-3), out
+    assert trans == pytest.approx(bench.SYNTH_TRANS_PER_G, abs=1e-3), out
+
+
+def test_benchmark_instantiation_is_the_one_counted():
+    """pw128_s50k (128 elements, nu = 2, one transmit, y = 0) runs
+    k_synth<256, 8, 16, 1, false, true>: block 256, 8 scatterers per chunk,
+    16 bins per tile, 1 transmit, elevation table."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert "ILi256ELi8ELi16ELi1ELb0ELb1E" in bench.SYNTH_KERNEL
+    src = open(os.path.join(ROOT, "paper_2102_02738_amd", "csrc", "kernels.hip")).read()
+    assert "#define SIMUS_SC1 8" in src and "#define SIMUS_JT_MAX 16" in src
