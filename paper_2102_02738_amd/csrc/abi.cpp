@@ -403,11 +403,13 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     const int N = Cc.P.N, M = Cc.P.M, n_tx = Cc.n_tx, n_ph = Cc.ph.n;
     F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx);
     SynthConfig& cfg = F.cfg;
-    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y) : synth_config(M, n_tx, Cc.has_y);
+    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y) : synth_config(M, Cc.P.nu, n_tx, Cc.has_y);
     cfg.table = Cc.table;
     const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;
-    F.slots = F.use_mt ? N : BS;
-    F.fin_nu = F.use_mt ? 1 : Cc.P.nu;
+    // element partials (matrix-core path, or paired lanes) or sub-element partials
+    const bool per_element = F.use_mt || cfg.pair;
+    F.slots = F.use_mt ? N : cfg.pair ? BS / 2 : BS;
+    F.fin_nu = per_element ? 1 : Cc.P.nu;
     F.n_bt = (Cc.B.n_bins + JT - 1) / JT;
     const int n_tg = (n_tx + TT - 1) / TT;
     if (F.n_bt >= 65536 || n_tg >= 32768) throw Error{SIMUS_EINVAL, "problem too large for the tile index"};
@@ -466,9 +468,14 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
         int dev = 0;
         hip_check(hipGetDevice(&dev), "hipGetDevice");
         hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        // resident blocks: two of 256 threads per CU (VALU path), one of 512 (matrix-core path)
-        const int per_cu = std::max(1, 512 / BS);
-        cfg.grid = std::min(F.n_items, prop.multiProcessorCount * per_cu);
+        // as many blocks as can be resident at once
+        const SynthKernel k = F.use_mt ? synth_mt_kernel(cfg) : synth_kernel(cfg);
+        if (!k) throw Error{SIMUS_EINVAL, "no synthesis kernel for this configuration"};
+        int per_cu = 0;
+        hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
+                                                               F.use_mt ? 512 : BS, 0),
+                  "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        cfg.grid = std::min(F.n_items, prop.multiProcessorCount * std::max(per_cu, 1));
     } else {
         cfg.grid = F.n_items;
     }

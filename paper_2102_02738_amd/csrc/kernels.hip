@@ -50,12 +50,19 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 //      are summed with DPP, the pair sums go to LDS and groups of lanes
 //      reduce them (no atomics, fixed order),
 //   3. scales by the reflectivity, c[s][t] = R_s a[s][t],
-//   4. Rx contraction X_sub[n][t] += sum_s G[n][s] c[s][t], accumulated per
-//      sub-element in an LDS slot private to the thread.
+//   4. Rx contraction X[n][t] += sum_s G[n][s] c[s][t], accumulated in an
+//      LDS slot private to the thread.
 // Steps 2-3 of bin j and step 4 of bin j-1 share one barrier: the reduction
 // rows and the reduced values are double-buffered, and G of bin j-1 stays in
-// registers.  The per-sub-element partials of every item go to `part`; the
-// finaliser sums them over items and over the nu sub-elements of each element.
+// registers (two register sets, bins taken in pairs).
+//
+// PAIR (nu = 2): lanes 2e and 2e+1 hold the two sub-elements of element e,
+// whose transmit weight is the same, so both contractions only need the
+// element sum B[e][s] = G[2e][s] + G[2e+1][s] (Eqs. 29, 33), formed by one
+// DPP exchange.  The receive sum of element e is then split over its lanes:
+// the even lane accumulates Re X[e], the odd lane Im X[e], one float each.
+// Otherwise every lane accumulates its own sub-element's complex X, and the
+// finaliser sums the nu sub-elements of each element.
 // ---------------------------------------------------------------------------
 
 // Tunables of the synthesis launch (compile-time): scatterers per chunk for
@@ -75,6 +82,18 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #define SIMUS_OCCUPANCY
 #endif
 
+// Bins per tile: the receive accumulators (JT TT BS slots of 8 bytes, or
+// of 4 bytes when paired) are kept within 64 KiB (32 KiB paired, which
+// leaves room for three 256-thread blocks per CU).
+constexpr int synth_jt(int bs, int tt, bool pair)
+{
+    int jt = SIMUS_JT_MAX;
+    const int slot = pair ? 4 : 8;
+    const int budget = pair ? 32768 : 65536;
+    while (jt > 1 && jt * tt * bs * slot > budget) jt /= 2;
+    return jt;
+}
+
 // DPP lane exchanges within rows of 16 lanes (gfx9 encodings).
 enum : int {
     DPP_XOR1 = 0xB1,          // quad_perm [1,0,3,2]
@@ -83,10 +102,12 @@ enum : int {
     DPP_MIRROR = 0x140        // lane i <-> 15 - i within 16
 };
 
+// Value of v in the lane selected by CTRL (all source lanes are active
+// wherever this is used).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over an aligned group of GL lanes (GL a power of two <= 64); every
@@ -103,7 +124,7 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-template <int BS, int SC, int JT, int TT, bool HASY, bool TABLE>
+template <int BS, int SC, int JT, int TT, bool HASY, bool TABLE, bool PAIR>
 __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 {
     constexpr int NS = SC * TT;            // sums per bin
@@ -111,12 +132,15 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     constexpr int RS = HB + 4;             // LDS row stride (float2)
     constexpr int GL = (HB / NS >= 64) ? 64 : HB / NS;   // lanes per sum
     constexpr int PER = HB / GL;           // values per lane
+    constexpr int NA = PAIR ? 1 : 2;       // floats per accumulator slot
     static_assert(NS <= HB, "chunk x transmit group must not exceed half the block");
 
     __shared__ float4 s_sc[SC];
     __shared__ float2 s_red[2][NS * RS];
-    __shared__ float2 s_c[2][NS];
-    __shared__ float2 s_acc[JT * TT * BS];
+    // reduced values c (PAIR: [0] = (Re c, -Im c) for even lanes,
+    // [1] = (Im c, Re c) for odd lanes)
+    __shared__ float2 s_c[2][PAIR ? 2 : 1][NS];
+    __shared__ float s_acc[JT * TT * BS * NA];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
     const int tid = threadIdx.x;
@@ -153,21 +177,42 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
             acc.y = group_sum<GL>(acc.y);
             if (lg == 0) {
                 const float R = s_sc[sid % SC].w;
-                s_c[buf][sid] = make_float2(R * acc.x, R * acc.y);
+                const float cx = R * acc.x, cy = R * acc.y;
+                if (PAIR) {
+                    s_c[buf][0][sid] = make_float2(cx, -cy);
+                    s_c[buf][1][sid] = make_float2(cy, cx);
+                } else {
+                    s_c[buf][0][sid] = make_float2(cx, cy);
+                }
             }
         }
     };
-    // Rx accumulation of local bin jj from s_c[buf].
-    auto receive = [&](int jj, int buf, const float2* G) {
+    // Rx accumulation of local bin jj from s_c[buf] with the terms G of that
+    // bin (element sums B when paired).
+    auto receive = [&](int jj, int buf, const float2 (&G)[SC]) {
 #pragma unroll
         for (int t = 0; t < TT; ++t) {
-            float2 x = s_acc[(jj * TT + t) * BS + tid], y = make_float2(0.f, 0.f);
+            const int slot = (jj * TT + t) * BS + tid;
+            if (PAIR) {
+                const float2* cv = s_c[buf][tid & 1] + t * SC;
+                float x = s_acc[slot], y = 0.f;
 #pragma unroll
-            for (int s = 0; s < SC; s += 2) {
-                x = cfma(G[s], s_c[buf][t * SC + s], x);
-                if (s + 1 < SC) y = cfma(G[s + 1], s_c[buf][t * SC + s + 1], y);
+                for (int s = 0; s < SC; ++s) {
+                    const float2 c = cv[s];
+                    x = fmaf(G[s].x, c.x, x);
+                    y = fmaf(G[s].y, c.y, y);
+                }
+                s_acc[slot] = x + y;
+            } else {
+                float2 x = make_float2(s_acc[2 * slot], s_acc[2 * slot + 1]), y = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int s = 0; s < SC; s += 2) {
+                    x = cfma(G[s], s_c[buf][0][t * SC + s], x);
+                    if (s + 1 < SC) y = cfma(G[s + 1], s_c[buf][0][t * SC + s + 1], y);
+                }
+                s_acc[2 * slot] = x.x + y.x;
+                s_acc[2 * slot + 1] = x.y + y.y;
             }
-            s_acc[(jj * TT + t) * BS + tid] = make_float2(x.x + y.x, x.y + y.y);
         }
     };
 
@@ -187,7 +232,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
         const int nb = min(JT, A.n_bins - jb0);
         const int t0 = tg * TT;
 
-        for (int i = tid; i < JT * TT * BS; i += BS) s_acc[i] = make_float2(0.f, 0.f);
+        for (int i = tid; i < JT * TT * BS * NA; i += BS) s_acc[i] = 0.f;
 
         for (int s0 = it.s_begin; s0 < it.s_end; s0 += SC) {
             if (tid < SC) {
@@ -204,15 +249,21 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 g[s] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g[s].E = make_float2(0.f, 0.f);
             }
-            float2 Gp[SC];
-            for (int jj = 0; jj < nb; ++jj) {
+            // one bin: terms of bin jj into Gc, Tx rows, barrier, reduction of
+            // bin jj, receive of bin jj - 1 from Gp
+            auto bin = [&](int jj, float2 (&Gc)[SC], const float2 (&Gp)[SC]) {
                 const int jb = jb0 + jj;
                 const int buf = jj & 1;
                 const float jf = (float)(A.j_lo + jb);
                 const float inv_j = rcp_fast(jf);
-                float2 G[SC];
 #pragma unroll
-                for (int s = 0; s < SC; ++s) G[s] = green_next<HASY, TABLE>(A.K, g[s], jf, inv_j, s_tab, P);
+                for (int s = 0; s < SC; ++s) {
+                    Gc[s] = green_next<HASY, TABLE>(A.K, g[s], jf, inv_j, s_tab, P);
+                    if (PAIR) {
+                        Gc[s].x += dpp<DPP_XOR1>(Gc[s].x);
+                        Gc[s].y += dpp<DPP_XOR1>(Gc[s].y);
+                    }
+                }
                 float2 W[TT];
 #pragma unroll
                 for (int t = 0; t < TT; ++t) {
@@ -223,23 +274,31 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 for (int t = 0; t < TT; ++t)
 #pragma unroll
                     for (int s = 0; s < SC; ++s) {
-                        float2 p = cmul(W[t], G[s]);
-                        p.x += dpp<DPP_XOR1>(p.x);
-                        p.y += dpp<DPP_XOR1>(p.y);
+                        float2 p = cmul(W[t], Gc[s]);
+                        if (!PAIR) {
+                            p.x += dpp<DPP_XOR1>(p.x);
+                            p.y += dpp<DPP_XOR1>(p.y);
+                        }
                         if (!(tid & 1)) s_red[buf][(t * SC + s) * RS + (tid >> 1)] = p;
                     }
                 __syncthreads();
                 reduce(buf);
                 if (jj > 0) receive(jj - 1, buf ^ 1, Gp);
-#pragma unroll
-                for (int s = 0; s < SC; ++s) Gp[s] = G[s];
+            };
+            float2 G0[SC], G1[SC];
+            for (int jj = 0; jj < nb; jj += 2) {
+                bin(jj, G0, G1);
+                if (jj + 1 < nb) bin(jj + 1, G1, G0);
             }
             __syncthreads();
-            if (nb > 0) receive(nb - 1, (nb - 1) & 1, Gp);
+            if (nb > 0) {
+                if ((nb - 1) & 1) receive(nb - 1, 1, G1);
+                else receive(nb - 1, 0, G0);
+            }
             __syncthreads();
         }
-        float2* out = A.part + (int64_t)item * (JT * TT * BS);
-        for (int i = tid; i < JT * TT * BS; i += BS) out[i] = s_acc[i];
+        float* out = reinterpret_cast<float*>(A.part) + (int64_t)item * (JT * TT * BS * NA);
+        for (int i = tid; i < JT * TT * BS * NA; i += BS) out[i] = s_acc[i];
 
         if (!A.ticket) break;
         __syncthreads();
@@ -249,7 +308,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     }
 }
 
-SynthConfig synth_config(int M, int n_tx, bool has_y)
+SynthConfig synth_config(int M, int nu, int n_tx, bool has_y)
 {
     SynthConfig c{};
     int bs = 64;
@@ -258,56 +317,62 @@ SynthConfig synth_config(int M, int n_tx, bool has_y)
     c.tt = n_tx >= 8 ? 8 : n_tx >= 4 ? 4 : n_tx >= 2 ? 2 : 1;
     if (bs > 512 && c.tt > 4) c.tt = 4;     // LDS: reduction rows + accumulators
     c.sc = c.tt >= 4 ? 2 : (c.tt == 2 ? 4 : SIMUS_SC1);
-    // s_acc (JT * TT * BS float2) kept within 64 KiB
-    int jt = SIMUS_JT_MAX;
-    while (jt > 1 && jt * c.tt * bs * 8 > 65536) jt /= 2;
-    c.jt = jt;
+    c.pair = nu == 2;
+    c.jt = synth_jt(bs, c.tt, c.pair);
     c.has_y = has_y;
     return c;
 }
 
-template <int BS, int SC, int JT, int TT>
-static hipError_t launch_synth_y(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
+template <int BS, int SC, int TT, bool PAIR>
+static SynthKernel synth_kernel_y(const SynthConfig& cfg)
 {
-    if (cfg.has_y)
-        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, true, false>), dim3(cfg.grid), dim3(BS), 0, st, a);
-    else if (cfg.table)
-        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, false, true>), dim3(cfg.grid), dim3(BS), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_synth<BS, SC, JT, TT, false, false>), dim3(cfg.grid), dim3(BS), 0, st, a);
-    return hipGetLastError();
+    constexpr int JT = synth_jt(BS, TT, PAIR);
+    if (cfg.jt != JT || cfg.sc != SC) return nullptr;
+    if (cfg.has_y) return k_synth<BS, SC, JT, TT, true, false, PAIR>;
+    if (cfg.table) return k_synth<BS, SC, JT, TT, false, true, PAIR>;
+    return k_synth<BS, SC, JT, TT, false, false, PAIR>;
 }
 
-template <int BS>
-static hipError_t launch_synth_bs(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
+template <int BS, bool PAIR>
+static SynthKernel synth_kernel_bs(const SynthConfig& cfg)
 {
-    constexpr int JM = SIMUS_JT_MAX;
-    constexpr int J1 = (JM * 1 * BS * 8 <= 65536) ? JM : 65536 / (8 * BS);
-    constexpr int J2 = (JM * 2 * BS * 8 <= 65536) ? JM : 65536 / (16 * BS);
-    constexpr int J4 = (JM * 4 * BS * 8 <= 65536) ? JM : 65536 / (32 * BS);
-    constexpr int J8 = (JM * 8 * BS * 8 <= 65536) ? JM : 65536 / (64 * BS);
     switch (cfg.tt) {
-    case 1: return launch_synth_y<BS, SIMUS_SC1, J1, 1>(cfg, a, st);
-    case 2: return launch_synth_y<BS, 4, J2, 2>(cfg, a, st);
-    case 4: return launch_synth_y<BS, 2, J4, 4>(cfg, a, st);
+    case 1: return synth_kernel_y<BS, SIMUS_SC1, 1, PAIR>(cfg);
+    case 2: return synth_kernel_y<BS, 4, 2, PAIR>(cfg);
+    case 4: return synth_kernel_y<BS, 2, 4, PAIR>(cfg);
     case 8:
-        if constexpr (BS <= 512) return launch_synth_y<BS, 2, J8, 8>(cfg, a, st);
-        return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
+        if constexpr (BS <= 512) return synth_kernel_y<BS, 2, 8, PAIR>(cfg);
+        return nullptr;
+    default: return nullptr;
     }
+}
+
+template <bool PAIR>
+static SynthKernel synth_kernel_pair(const SynthConfig& cfg)
+{
+    switch (cfg.bs) {
+    case 64: return synth_kernel_bs<64, PAIR>(cfg);
+    case 128: return synth_kernel_bs<128, PAIR>(cfg);
+    case 256: return synth_kernel_bs<256, PAIR>(cfg);
+    case 512: return synth_kernel_bs<512, PAIR>(cfg);
+    case 1024: return synth_kernel_bs<1024, PAIR>(cfg);
+    default: return nullptr;
+    }
+}
+
+SynthKernel synth_kernel(const SynthConfig& cfg)
+{
+    return cfg.pair ? synth_kernel_pair<true>(cfg) : synth_kernel_pair<false>(cfg);
 }
 
 hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st)
 {
     if (cfg.grid <= 0) return hipSuccess;
-    switch (cfg.bs) {
-    case 64: return launch_synth_bs<64>(cfg, a, st);
-    case 128: return launch_synth_bs<128>(cfg, a, st);
-    case 256: return launch_synth_bs<256>(cfg, a, st);
-    case 512: return launch_synth_bs<512>(cfg, a, st);
-    case 1024: return launch_synth_bs<1024>(cfg, a, st);
-    default: return hipErrorInvalidValue;
-    }
+    const SynthKernel k = synth_kernel(cfg);
+    if (!k) return hipErrorInvalidValue;
+    SynthArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(cfg.grid), dim3(cfg.bs), args, 0, st);
 }
 
 // ---------------------------------------------------------------------------

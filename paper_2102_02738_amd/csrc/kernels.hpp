@@ -86,6 +86,7 @@ struct SynthConfig {
     bool has_y;
     bool table;  // elevation term from the table (requires !has_y)
     bool persistent;
+    bool pair;   // nu = 2: element sums of lane pairs, one float accumulator per lane
     bool mfma;   // transmit contraction on the matrix cores (synth_mfma.hip)
     int nq;      // MFMA path: transmit quarters per receive thread group
     int grid;    // blocks launched (persistent: resident blocks)
@@ -151,14 +152,20 @@ hipError_t launch_pfield(const FieldArgs& a, bool has_y, bool table, int n_range
 hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, float dw, float* out,
                                 hipStream_t st);
 
-// Picks tt/sc/jt for a block size and transmit count.
-SynthConfig synth_config(int M, int n_tx, bool has_y);
+// Picks bs/tt/sc/jt for M = nu N sub-elements and a transmit count.
+SynthConfig synth_config(int M, int nu, int n_tx, bool has_y);
 
 hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
                          int N, int j_lo, double df, hipStream_t st);
+// The synthesis kernel instance a configuration runs (nullptr if none), for
+// the launch and for occupancy queries (blocks of cfg.bs threads, or 512 on
+// the matrix-core path).
+using SynthKernel = void (*)(SynthArgs);
+SynthKernel synth_kernel(const SynthConfig& cfg);
 hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 bool mt_supported(int M, int N, int n_tx);
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y);
+SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,

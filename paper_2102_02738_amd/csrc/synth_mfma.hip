@@ -226,24 +226,19 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 }
 
 template <int NTP, int NQ, bool PERSIST>
-static hipError_t launch_mt_p(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
+static SynthKernel mt_kernel_p(const SynthConfig& c)
 {
     constexpr int JT = NTP == 1 ? 4 : 2;   // receive accumulators: 16 JT NTP floats
-    if (c.jt != JT) return hipErrorInvalidValue;
-    if (c.has_y)
-        hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, true, false, PERSIST>), dim3(c.grid), dim3(512), 0, st, a);
-    else if (c.table)
-        hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, false, true, PERSIST>), dim3(c.grid), dim3(512), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_synth_mt<NTP, NQ, JT, false, false, PERSIST>), dim3(c.grid), dim3(512), 0, st, a);
-    return hipGetLastError();
+    if (c.jt != JT) return nullptr;
+    if (c.has_y) return k_synth_mt<NTP, NQ, JT, true, false, PERSIST>;
+    if (c.table) return k_synth_mt<NTP, NQ, JT, false, true, PERSIST>;
+    return k_synth_mt<NTP, NQ, JT, false, false, PERSIST>;
 }
 
 template <int NTP, int NQ>
-static hipError_t launch_mt_nq(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
+static SynthKernel mt_kernel_nq(const SynthConfig& c)
 {
-    if (c.persistent != (a.ticket != nullptr)) return hipErrorInvalidValue;
-    return c.persistent ? launch_mt_p<NTP, NQ, true>(c, a, st) : launch_mt_p<NTP, NQ, false>(c, a, st);
+    return c.persistent ? mt_kernel_p<NTP, NQ, true>(c) : mt_kernel_p<NTP, NQ, false>(c);
 }
 
 // The matrix-core path serves n_tx >= 4 with nu N <= 256 and N <= 128.
@@ -266,22 +261,35 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
     return c;
 }
 
-hipError_t launch_synth_mt(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
+SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
-    if (c.grid <= 0) return hipSuccess;
     const int ntp = c.tt / 16;
     if (ntp == 1) {
         switch (c.nq) {
-        case 4: return launch_mt_nq<1, 4>(c, a, st);
-        case 8: return launch_mt_nq<1, 8>(c, a, st);
-        default: return hipErrorInvalidValue;
+        case 4: return mt_kernel_nq<1, 4>(c);
+        case 8: return mt_kernel_nq<1, 8>(c);
+        default: return nullptr;
         }
     }
-    switch (c.nq) {
-    case 4: return launch_mt_nq<2, 4>(c, a, st);
-    case 8: return launch_mt_nq<2, 8>(c, a, st);
-    default: return hipErrorInvalidValue;
+    if (ntp == 2) {
+        switch (c.nq) {
+        case 4: return mt_kernel_nq<2, 4>(c);
+        case 8: return mt_kernel_nq<2, 8>(c);
+        default: return nullptr;
+        }
     }
+    return nullptr;
+}
+
+hipError_t launch_synth_mt(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
+{
+    if (c.grid <= 0) return hipSuccess;
+    if (c.persistent != (a.ticket != nullptr)) return hipErrorInvalidValue;
+    const SynthKernel k = synth_mt_kernel(c);
+    if (!k) return hipErrorInvalidValue;
+    SynthArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(c.grid), dim3(512), args, 0, st);
 }
 
 }  // namespace simus
