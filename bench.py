@@ -38,8 +38,8 @@ sys.path.insert(0, ROOT)
 # counted from the gfx950 assembly with paper_2102_02738_amd/diag/isa_count.py.
 SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELb1ELb1EEEvNS_9SynthArgsE"
 SYNTH_TERMS_PER_ITER = 16
-SYNTH_VALU_PER_G = 40.3125     # full-rate VALU instructions per G term
-SYNTH_TRANS_PER_G = 1.125      # transcendental instructions per G term
+SYNTH_VALU_PER_G = 35.125      # full-rate VALU instructions per G term
+SYNTH_TRANS_PER_G = 1.0        # transcendental instructions per G term
 TRANS_ISSUE_COST = 4.0         # a transcendental issues at 1/4 of the FP32 rate (diag/valu_rate)
 # MI355X FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-instructions/s
 # (256 CU x 128 FP32 lanes/clk x 2.4 GHz); one "slot" = one lane-instruction.

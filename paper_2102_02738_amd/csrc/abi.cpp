@@ -532,7 +532,7 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     hip_check(timed(K_FINALIZE, st, [&] {
                   return launch_finalize(spec, A.part, at<float2>(d, F.L.pw), at<int32_t>(d, F.o_pb),
                                          at<int32_t>(d, F.o_ns), n_ph, n_tx, N, F.fin_nu, C.B.n_bins,
-                                         F.slots, cfg.tt, cfg.jt, F.n_bt, st);
+                                         F.slots, cfg.tt, cfg.jt, F.n_bt, C.B.j_lo, !F.use_mt, st);
               }),
               "finalize launch");
     if (rf_out) {

@@ -255,32 +255,51 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 const int jb = jb0 + jj;
                 const int buf = jj & 1;
                 const float jf = (float)(A.j_lo + jb);
-                const float inv_j = rcp_fast(jf);
+                // j G: the sinc's 1/j is applied as 1/j^2 by the finaliser
+#pragma unroll
+                for (int s = 0; s < SC; ++s) Gc[s] = green_next<HASY, TABLE>(A.K, g[s], jf, 1.f, s_tab, P);
 #pragma unroll
                 for (int s = 0; s < SC; ++s) {
-                    Gc[s] = green_next<HASY, TABLE>(A.K, g[s], jf, inv_j, s_tab, P);
                     if (PAIR) {
                         Gc[s].x += dpp<DPP_XOR1>(Gc[s].x);
                         Gc[s].y += dpp<DPP_XOR1>(Gc[s].y);
                     }
                 }
+                // branch-free loads (clamped index, then select) keep the bin in
+                // one basic block
                 float2 W[TT];
 #pragma unroll
                 for (int t = 0; t < TT; ++t) {
-                    W[t] = make_float2(0.f, 0.f);
-                    if (active && t0 + t < A.n_tx) W[t] = A.W[((int64_t)jb * A.n_tx + t0 + t) * A.N + e];
+                    const int tt = min(t0 + t, A.n_tx - 1);
+                    const float2 w = A.W[((int64_t)jb * A.n_tx + tt) * A.N + e];
+                    const bool use = active && t0 + t < A.n_tx;
+                    W[t] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
                 }
+                if (PAIR) {
+                    // W B split over the pair: the even lane stores Re, the odd
+                    // lane Im, together the float2 slot of the pair
+                    float* red = reinterpret_cast<float*>(s_red[buf]);
 #pragma unroll
-                for (int t = 0; t < TT; ++t)
+                    for (int t = 0; t < TT; ++t) {
+                        const float w1 = (tid & 1) ? W[t].y : W[t].x;
+                        const float w2 = (tid & 1) ? W[t].x : -W[t].y;
 #pragma unroll
-                    for (int s = 0; s < SC; ++s) {
-                        float2 p = cmul(W[t], Gc[s]);
-                        if (!PAIR) {
+                        for (int s = 0; s < SC; ++s)
+                            red[2 * (t * SC + s) * RS + tid] = fmaf(w1, Gc[s].x, w2 * Gc[s].y);
+                    }
+                } else {
+                    // both lanes of a pair hold the same pair sum and store it
+                    // to the same slot
+#pragma unroll
+                    for (int t = 0; t < TT; ++t)
+#pragma unroll
+                        for (int s = 0; s < SC; ++s) {
+                            float2 p = cmul(W[t], Gc[s]);
                             p.x += dpp<DPP_XOR1>(p.x);
                             p.y += dpp<DPP_XOR1>(p.y);
+                            s_red[buf][(t * SC + s) * RS + (tid >> 1)] = p;
                         }
-                        if (!(tid & 1)) s_red[buf][(t * SC + s) * RS + (tid >> 1)] = p;
-                    }
+                }
                 __syncthreads();
                 reduce(buf);
                 if (jj > 0) receive(jj - 1, buf ^ 1, Gp);
@@ -377,13 +396,14 @@ hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t 
 
 // ---------------------------------------------------------------------------
 // Finaliser: spec[p][t][e][b] = P_b sum_items sum_{mu<nu} part[item][jj][t%TT][e nu + mu]
-// (Eqs. 33-34).  Items of phantom p are ordered (tg, bt, slice); the sum
+// (Eqs. 33-34), divided by j^2, j = j_lo + b, when inv_j2 is set (partials
+// of j G terms).  Items of phantom p are ordered (tg, bt, slice); the sum
 // over slices runs in slice order, so the result is deterministic.
 // ---------------------------------------------------------------------------
 __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__ part,
                            const float2* __restrict__ pw, const int32_t* __restrict__ pbase,
                            const int32_t* __restrict__ nsl, int n_ph, int n_tx, int N, int nu,
-                           int n_bins, int bs, int tt, int jt, int n_bt)
+                           int n_bins, int bs, int tt, int jt, int n_bt, int j_lo, bool inv_j2)
 {
     const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -405,7 +425,13 @@ __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__
                 sy += src[mu].y;
             }
         }
-        const float2 w = pw[b];
+        float2 w = pw[b];
+        if (inv_j2) {
+            // partials of j G terms (two per product): divide by j^2
+            const float j = (float)(j_lo + b);
+            const float s = 1.f / (j * j);
+            w = make_float2(w.x * s, w.y * s);
+        }
         spec[(((int64_t)p * n_tx + t) * N + e) * n_bins + b] =
             make_float2(w.x * sx - w.y * sy, w.x * sy + w.y * sx);
     }
@@ -413,13 +439,14 @@ __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__
 
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
-                           int nu, int n_bins, int bs, int tt, int jt, int n_bt, hipStream_t st)
+                           int nu, int n_bins, int bs, int tt, int jt, int n_bt, int j_lo,
+                           bool inv_j2, hipStream_t st)
 {
     const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
     if (total == 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, spec, part, pw, pbase, nsl, n_ph,
-                       n_tx, N, nu, n_bins, bs, tt, jt, n_bt);
+                       n_tx, N, nu, n_bins, bs, tt, jt, n_bt, j_lo, inv_j2);
     return hipGetLastError();
 }
 

@@ -167,10 +167,12 @@ bool mt_supported(int M, int N, int n_tx);
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y);
 SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
+// inv_j2: the partials are of j G terms (vector path) and are divided by
+// j^2, j = j_lo + bin.
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
-                           int nu, int n_bins, int bs, int tt, int jt, int n_bt,
-                           hipStream_t st);
+                           int nu, int n_bins, int bs, int tt, int jt, int n_bt, int j_lo,
+                           bool inv_j2, hipStream_t st);
 hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins, int j_lo,
                        int nfft, int n_t, hipStream_t st);
 hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,
