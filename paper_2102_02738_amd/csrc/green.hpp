@@ -61,7 +61,7 @@ __device__ __forceinline__ float sinc_setup(float x)
     p = fmaf(x2, p, -1.6666666666666667e-01f);
     p = fmaf(x2, p, 1.0f);
     if (fabsf(x) < 1.f) return p;
-    return sin_turns(x * 0.15915494309189535f) / x;
+    return sin_turns(x * 0.15915494309189535f) * rcp_fast(x);
 }
 
 // State of one (sub-element, scatterer) pair at the current bin.
@@ -116,14 +116,21 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     const double dx = (double)px - f.xc;
     const double dz = (double)pz - f.zc;
     const double yy = HASY ? (double)py : 0.0;
-    const double r = sqrt(dx * dx + dz * dz + yy * yy);
+    // r in FP64 without a double-precision root: the FP32 root of the FP64
+    // square, refined by one Newton step in FP64 (relative error ~1e-14)
+    const double r2 = fma(dx, dx, fma(dz, dz, yy * yy));
     const float dxf = (float)dx, dzf = (float)dz;
     const float xl = dxf * f.tx + dzf * f.tz;
     const float zl = dxf * f.nx + dzf * f.nz;
-    const bool ok = (zl > 0.f) && (r > 1e-9);
-    const float rf = ok ? (float)r : 1.f;
+    const bool ok = (zl > 0.f) && (r2 > 1e-18);
+    const double r2s = ok ? r2 : 1.0;
+    const float r2f = (float)r2s;
+    const float inv_r0 = rsq_fast(r2f);
+    const double r0 = (double)(r2f * inv_r0);
+    const double r = fma(fma(-r0, r0, r2s), 0.5 * (double)inv_r0, r0);
+    const float rf = (float)r;
     const float rho = HASY ? sqrtf(xl * xl + zl * zl) : rf;
-    const float inv_rho = ok ? 1.f / rho : 0.f;
+    const float inv_rho = ok ? rcp_fast(rho) : 0.f;
     const float st = xl * inv_rho;
     const float ct = ok ? zl * inv_rho : 1.f;
     float obl = ct, dobl = 1.f;                            // soft baffle
@@ -131,11 +138,11 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
         obl = 1.f;
         dobl = 0.f;
     } else if (K.baffle == 2) {                            // finite impedance
-        const float den = 1.f / (ct + K.zeta);
+        const float den = rcp_fast(ct + K.zeta);
         obl = ct * den;
         dobl = K.zeta * den * den;
     }
-    const float inv_r = 1.f / rf;
+    const float inv_r = rcp_fast(rf);
     const float amp = ok ? obl * inv_r : 0.f;
     const float jf0 = (float)j0;
 
@@ -170,7 +177,7 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
         const float dxl[3] = {f.tx, 0.f, f.tz};
         const float dzl[3] = {f.nx, 0.f, f.nz};
         const float dyy[3] = {0.f, 1.f, 0.f};
-        const float inv_obl = ok ? 1.f / obl : 0.f;
+        const float inv_obl = ok ? rcp_fast(obl) : 0.f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const float drho = (xl * dxl[a] + zl * dzl[a]) * inv_rho;
@@ -184,7 +191,7 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
         }
         D->c = cos_turns(jf0 * sigma);
         D->dc = -theta * sin_turns((jf0 - 0.5f) * sigma) * sh;
-        D->inv_theta = (theta != 0.f) ? 1.f / theta : 0.f;
+        D->inv_theta = (theta != 0.f) ? rcp_fast(theta) : 0.f;
         D->r = rf;
         D->y = yf;
     }
@@ -259,7 +266,7 @@ template <bool HASY>
 __device__ __forceinline__ void elevation_grad(const Gauss4& G, float inv_rf, float k, float r,
                                                float y, float2& dl, float2& d_r, float2& d_y)
 {
-    const float inv_r = 1.f / r;
+    const float inv_r = rcp_fast(r);
     const float q = 0.5f * k * (inv_rf - inv_r);
     const float ar_i = 0.5f * k * inv_r * inv_r;          // d alpha / dr = i ar_i
     dl = d_r = d_y = make_float2(0.f, 0.f);
