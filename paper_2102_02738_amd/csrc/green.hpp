@@ -258,6 +258,36 @@ __device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaPara
     return make_float2(re, im);
 }
 
+// The table lookup in two steps, so that a lookup's LDS read can be in
+// flight while earlier terms are evaluated.
+struct DeltaFetch {
+    float4 a, b;
+    float t;
+};
+
+__device__ __forceinline__ DeltaFetch delta_fetch(const float4* tab, const DeltaParams& P, float q)
+{
+    const float w = q * rcp_fast(fabsf(q) + P.L);
+    const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
+    const float kf = floorf(u);
+    const int k = (int)kf;
+    DeltaFetch f;
+    f.t = u - kf;
+    f.a = tab[2 * k];
+    f.b = tab[2 * k + 1];
+    return f;
+}
+
+__device__ __forceinline__ float2 delta_eval(const DeltaFetch& f)
+{
+    float re = fmaf(f.t, f.b.z, f.b.x), im = fmaf(f.t, f.b.w, f.b.y);
+    re = fmaf(f.t, re, f.a.z);
+    im = fmaf(f.t, im, f.a.w);
+    re = fmaf(f.t, re, f.a.x);
+    im = fmaf(f.t, im, f.a.y);
+    return make_float2(re, im);
+}
+
 // delta with its partial derivatives in r and y, evaluated directly
 // (y != 0 path of the adjoint, or without the table).  Per Gaussian,
 // T = A sqrt(pi) alpha^{-1/2} exp(phi), phi = beta^2/(4 alpha) + gamma, and
@@ -383,6 +413,18 @@ __device__ __forceinline__ float2 green_grad_next(const ModelConst& K, Geo& g, G
     D.dc = fmaf(g.lam, D.c, D.dc);
     D.c += D.dc;
     return Gv;
+}
+
+// j G at bin j from a fetched table interval (y = 0): the sinc's 1/j is left
+// to the caller.  Advances the pair to bin j + 1.
+__device__ __forceinline__ float2 green_next_fetched(Geo& g, const DeltaFetch& f)
+{
+    const float2 A = make_float2(g.E.x * g.s, g.E.y * g.s);
+    const float2 d = delta_eval(f);
+    g.E = cmul(g.E, g.dE);
+    g.d = fmaf(g.lam, g.s, g.d);
+    g.s += g.d;
+    return cmul(A, d);
 }
 
 // Green's term at absolute bin j (jf = j, inv_j = 1/j); advances the pair to

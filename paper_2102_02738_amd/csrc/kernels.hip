@@ -256,8 +256,21 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 const int buf = jj & 1;
                 const float jf = (float)(A.j_lo + jb);
                 // j G: the sinc's 1/j is applied as 1/j^2 by the finaliser
+                if constexpr (TABLE) {
+                    // each term's table read is issued while the previous term
+                    // is evaluated (one read ahead keeps three blocks per CU)
+                    DeltaFetch fch[2];
+                    fch[0] = delta_fetch(s_tab, P, jf * g[0].kap);
 #pragma unroll
-                for (int s = 0; s < SC; ++s) Gc[s] = green_next<HASY, TABLE>(A.K, g[s], jf, 1.f, s_tab, P);
+                    for (int s = 0; s < SC; ++s) {
+                        if (s + 1 < SC) fch[(s + 1) & 1] = delta_fetch(s_tab, P, jf * g[s + 1].kap);
+                        __builtin_amdgcn_sched_barrier(0);
+                        Gc[s] = green_next_fetched(g[s], fch[s & 1]);
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < SC; ++s) Gc[s] = green_next<HASY, TABLE>(A.K, g[s], jf, 1.f, s_tab, P);
+                }
 #pragma unroll
                 for (int s = 0; s < SC; ++s) {
                     if (PAIR) {
