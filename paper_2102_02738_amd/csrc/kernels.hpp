@@ -88,7 +88,6 @@ struct SynthConfig {
     bool persistent;
     bool pair;   // nu = 2: element sums of lane pairs, one float accumulator per lane
     bool mfma;   // transmit contraction on the matrix cores (synth_mfma.hip)
-    int nq;      // MFMA path: transmit quarters per receive thread group
     int grid;    // blocks launched (persistent: resident blocks)
 };
 
@@ -167,8 +166,8 @@ bool mt_supported(int M, int N, int n_tx);
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y);
 SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
-// inv_j2: the partials are of j G terms (vector path) and are divided by
-// j^2, j = j_lo + bin.
+// inv_j2: the partials are of j G terms (both synthesis paths) and are
+// divided by j^2, j = j_lo + bin.
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
                            int nu, int n_bins, int bs, int tt, int jt, int n_bt, int j_lo,

@@ -1,20 +1,30 @@
-// Synthesis for many transmits: the transmit contraction of Eq. (29),
-//   a[s][t] = sum_n G[n][s] W[n][t],
-// is a complex GEMM (16 scatterers x nu N sub-elements x up to 32 transmits
-// per group), and so is the receive contraction of Eqs. (32)-(33),
-//   X[e][t] += sum_s (sum_{mu in e} G[mu][s]) R_s a[s][t]
-// (elements x 16 scatterers x transmits).  Both run on the matrix cores with
-// FP32 MFMA (16x16x4); the Green's terms are synthesised on the VALU
-// (green.hpp).  X accumulates in MFMA registers across all scatterers of the
-// item.
+// Synthesis for many transmits on the matrix cores.  Per chunk of 16
+// scatterers and per bin, the transmit contraction of Eq. (29),
+//   a[s][t] = sum_n G[s][n] W[n][t]      (16 x nu N x 16-32 transmits),
+// and the receive contraction of Eqs. (32)-(33),
+//   X[e][t] += sum_s B[e][s] R_s a[s][t], B[e][s] = sum_{mu in e} G[s][mu]
+//                                        (elements x 16 x transmits),
+// are complex GEMMs run with FP32 MFMA (16x16x4).  Each complex product
+// takes three real products (Karatsuba): with P1 = Re Re, P2 = Im Im and
+// P3 = (Re + Im)(Re + Im) summed over k, the product is (P1 - P2, P3 - P1 - P2).
+// The Green's terms are synthesised on the VALU (green.hpp) and stepped
+// across the item's bins; X accumulates in registers across the item's
+// scatterers, as the three sums, and is combined once at the end.
 //
-// Block: 512 threads (8 waves).  Synthesis: thread = (sub-element n, half of
-// the 16-scatterer chunk), 8 pairs stepped across the item's bin tile.
-// Transmit GEMM: a complex product is four real MFMA products; the 2 * NTP
-// output tiles (re/im of each 16-transmit tile) are spread over the 8 waves,
-// each wave covering a share of the sub-elements, and the shares are summed
-// in LDS in a fixed order.  Receive GEMM: wave w owns elements 16 w .. 16 w + 15
-// and all output tiles of the group.
+// Block: 512 threads (8 waves), nu in {1, 2} at compile time.
+//   Synthesis: thread = (sub-element n, group of PPT scatterers).  Writes the
+//     G tile, and for nu = 2 the element sums B (one DPP exchange between the
+//     two sub-elements of an element, which are neighbouring lanes).
+//   Transmit GEMM: wave = (column tile ct of 16 transmits, share kp of the
+//     sub-elements); its three product tiles go to LDS and are summed over the
+//     shares in a fixed order, scaled by R_s, into c[s][t].
+//   Receive GEMM: wave w owns elements 16 w .. 16 w + 15 and all column tiles.
+// Barriers per bin: after synthesis, after the transmit GEMM, after the
+// reduction.  With nu = 2 the element sums are double-buffered, so the next
+// bin's synthesis may start while other waves still run this bin's receive
+// GEMM.  Partial spectra of every item, per element, go to `part`
+// ([item][JT][TPG][N]); like the vector path the terms are j G, and the
+// finaliser divides by j^2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,40 +36,51 @@ namespace simus {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int NTP, int NQ, int JT, bool HASY, bool TABLE, bool PERSIST>
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int NTP, int JT, int NUV, bool HASY, bool TABLE, bool PERSIST>
 __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 {
     constexpr int NB = 512;
-    constexpr int MS = 256;                 // sub-element slots
+    constexpr int NE = 128;                 // element slots
+    constexpr int MS = NE * NUV;            // sub-element slots
     constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
-    constexpr int GS = MS + 4;              // LDS row stride of the G tile (float2)
+    constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
+    constexpr int NSG = NB / MS;            // scatterer groups
+    constexpr int GS = MS + 4;              // row stride of the G tile (float2)
+    constexpr int BST = NE + 4;             // row stride of the element sums
     constexpr int TPG = 16 * NTP;           // transmit columns of the group
-    constexpr int NOUT = 2 * NTP;           // output tiles (re, im per column tile)
-    constexpr int KSPLIT = 8 / NOUT;        // waves per output tile
-    constexpr int KW = MS / KSPLIT;         // sub-elements per wave
-    constexpr int EP = NB / NQ;             // element slots
+    constexpr int KP = 8 / NTP;             // sub-element shares per column tile
+    constexpr int KW = MS / KP;             // sub-elements per wave
+    constexpr int KS = KW / 4;              // transmit-GEMM k-steps per wave
+    constexpr int WS = NE + 1;              // row stride of the staged weights
+    constexpr int NBB = NUV == 2 ? 2 : 1;   // element-sum buffers
+    static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(PPT * NSG == SCH, "synthesis threads must cover the chunk");
 
     __shared__ float4 s_sc[SCH];
     __shared__ float2 s_G[SCH * GS];
-    __shared__ float s_part[8][256];
+    __shared__ float2 s_B[NUV == 2 ? NBB * SCH * BST : 1];
+    __shared__ float2 s_W[TPG * WS];
+    __shared__ float s_part[8][3][256];
     __shared__ float2 s_c[SCH][TPG];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
-    constexpr int WS = EP + 1;              // LDS row stride of the staged weights
-    __shared__ float2 s_W[TPG * WS];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int gi = lane & 15, gk = lane >> 4;      // MFMA operand lane roles
     // synthesis role
-    const int n = tid & (MS - 1), sh = tid / MS;
+    const int n = tid % MS, sh = tid / MS;
     const bool active = n < A.M;
     const SubFrame fr = load_frame(A.sub, active ? n : 0);
-    // receive role: element tile of this wave
+    // transmit-GEMM role
+    const int ct = wave % NTP, kp = wave / NTP;
+    // receive-GEMM role
     const int mt_e = wave * 16;
     const bool re_live = mt_e < A.N;
-    // GEMM role
-    const int otile = wave % NOUT, kpart = wave / NOUT;
-    const int ct = otile >> 1;              // column tile
-    const bool out_im = otile & 1;
 
     DeltaParams P{};
     if (TABLE) {
@@ -83,15 +104,16 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
         const int nb = min(JT, A.n_bins - jb0);
         const int t0 = tg * TPG;
 
-        // receive accumulators: [bin][column tile][re, im]
-        floatx4 X[JT][NTP][2];
+        // receive sums [bin][column tile][P1, P2, P3]
+        floatx4 X[JT][NTP][3];
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
-            for (int c = 0; c < NTP; ++c) X[jj][c][0] = X[jj][c][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < NTP; ++c)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) X[jj][c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
         for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
-            __syncthreads();
             if (tid < SCH) {
                 const int s = s0 + tid;
                 float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
@@ -99,109 +121,130 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 s_sc[tid] = v;
             }
             __syncthreads();
-            Geo g[8];
+            Geo g[PPT];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float4 v = s_sc[sh * 8 + k];
+            for (int k = 0; k < PPT; ++k) {
+                const float4 v = s_sc[sh * PPT + k];
                 g[k] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g[k].E = make_float2(0.f, 0.f);
             }
-            // GEMM operand lanes: rows s = lane % 16, columns t = ct * 16 + lane % 16
-            const int gi = lane & 15, gk = lane >> 4;
-            const int nbase = kpart * KW;
-            // The bin loop is unrolled so that the receive accumulators X[jj] stay
-            // in registers; nb is uniform, so the barriers inside are too.
+            // The bin loop is unrolled so that the receive sums X[jj] stay in
+            // registers; nb is uniform, so the barriers inside are too.
 #pragma unroll
             for (int jj = 0; jj < JT; ++jj) {
                 if (jj >= nb) break;
                 const int jb = jb0 + jj;
                 const float jf = (float)(A.j_lo + jb);
-                const float inv_j = rcp_fast(jf);
-                // 0. stage the transmit weights of this bin, W[t][e], in LDS
-                {
-                    const int e2 = tid % EP;
+                float2* sB = s_B + (jj & (NBB - 1)) * (SCH * BST);
+                // 0. transmit weights of this bin, W[t][e], zero outside N x n_tx
+                for (int idx = tid; idx < TPG * NE; idx += NB) {
+                    const int t = idx / NE, e = idx % NE;
+                    const int tt = min(t0 + t, A.n_tx - 1), ee = min(e, A.N - 1);
+                    const float2 w = A.W[((int64_t)jb * A.n_tx + tt) * A.N + ee];
+                    const bool use = e < A.N && t0 + t < A.n_tx;
+                    s_W[t * WS + e] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
+                }
+                // 1. j G of the chunk -> G tile [s][n]; element sums for nu = 2
+                float2 G[PPT];
+                if constexpr (TABLE) {
+                    // each term's table read is issued while the previous term
+                    // is evaluated
+                    DeltaFetch fch[2];
+                    fch[0] = delta_fetch(s_tab, P, jf * g[0].kap);
 #pragma unroll
-                    for (int t = tid / EP; t < TPG; t += NQ) {
-                        const int tt = t0 + t;
-                        if (e2 < A.N)
-                            s_W[t * WS + e2] = tt < A.n_tx ? A.W[((int64_t)jb * A.n_tx + tt) * A.N + e2]
-                                                           : make_float2(0.f, 0.f);
+                    for (int k = 0; k < PPT; ++k) {
+                        if (k + 1 < PPT) fch[(k + 1) & 1] = delta_fetch(s_tab, P, jf * g[k + 1].kap);
+                        __builtin_amdgcn_sched_barrier(0);
+                        G[k] = green_next_fetched(g[k], fch[k & 1]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) G[k] = green_next<HASY, TABLE>(A.K, g[k], jf, 1.f, s_tab, P);
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int s = sh * PPT + k;
+                    s_G[s * GS + n] = G[k];
+                    if (NUV == 2) {
+                        // both lanes of the pair store the same element sum
+                        const float bx = G[k].x + __int_as_float(__builtin_amdgcn_mov_dpp(
+                                                      __float_as_int(G[k].x), 0xB1, 0xF, 0xF, true));
+                        const float by = G[k].y + __int_as_float(__builtin_amdgcn_mov_dpp(
+                                                      __float_as_int(G[k].y), 0xB1, 0xF, 0xF, true));
+                        sB[s * BST + (n >> 1)] = make_float2(bx, by);
                     }
                 }
-                // 1. Green's terms of the chunk -> LDS tile [s][n]
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    s_G[(sh * 8 + k) * GS + n] = green_next<HASY, TABLE>(A.K, g[k], jf, inv_j, s_tab, P);
                 __syncthreads();
-                // 2. transmit GEMM share; two accumulators keep the MFMA chain short
+                // 2. transmit GEMM share: rows s = gi, columns t = ct 16 + gi,
+                //    sub-elements kp KW + 4 k + gk
                 {
-                    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                    const float2* gp = s_G + gi * GS + kp * KW + gk;
+                    const float2* wp = s_W + (ct * 16 + gi) * WS + (kp * KW + gk) / NUV;
+                    float2 ga[KS], wa[KS];
 #pragma unroll
-                    for (int k = 0; k < KW / 4; ++k) {
-                        const int nn = nbase + 4 * k + gk;
-                        const float2 gv = s_G[gi * GS + nn];
-                        const float2 wk = (nn < A.M) ? s_W[(ct * 16 + gi) * WS + nn / A.nu]
-                                                     : make_float2(0.f, 0.f);
-                        // re: Gr Wr - Gi Wi ; im: Gr Wi + Gi Wr
-                        const float b0 = out_im ? wk.y : wk.x;
-                        const float b1 = out_im ? wk.x : -wk.y;
-                        if (k & 1) {
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, b0, acc1, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, b1, acc1, 0, 0, 0);
-                        } else {
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, b0, acc0, 0, 0, 0);
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, b1, acc0, 0, 0, 0);
-                        }
+                    for (int k = 0; k < KS; ++k) {
+                        ga[k] = gp[4 * k];
+                        wa[k] = wp[4 * k / NUV];
+                    }
+                    floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        p1 = mfma4(ga[k].x, wa[k].x, p1);
+                        p2 = mfma4(ga[k].y, wa[k].y, p2);
+                        p3 = mfma4(ga[k].x + ga[k].y, wa[k].x + wa[k].y, p3);
                     }
                     // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        s_part[wave][(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc0[v] + acc1[v];
+                    for (int v = 0; v < 4; ++v) {
+                        const int d = (4 * gk + v) * 16 + gi;
+                        s_part[wave][0][d] = p1[v];
+                        s_part[wave][1][d] = p2[v];
+                        s_part[wave][2][d] = p3[v];
+                    }
                 }
                 __syncthreads();
-                // 3. sum the shares (fixed order), scale by R_s
-                for (int idx = tid; idx < SCH * TPG; idx += NB) {
-                    const int s = idx / TPG, t = idx % TPG;
-                    const int c_tile = t >> 4, col = t & 15;
-                    float re = 0.f, im = 0.f;
+                // 3. sum the shares (fixed order), combine, scale by R_s
+                if (tid < SCH * TPG) {
+                    const int s = tid / TPG, t = tid % TPG;
+                    const int c = t >> 4, d = s * 16 + (t & 15);
+                    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
 #pragma unroll
-                    for (int kp = 0; kp < KSPLIT; ++kp) {
-                        re += s_part[kp * NOUT + 2 * c_tile][s * 16 + col];
-                        im += s_part[kp * NOUT + 2 * c_tile + 1][s * 16 + col];
+                    for (int k = 0; k < KP; ++k) {
+                        q1 += s_part[k * NTP + c][0][d];
+                        q2 += s_part[k * NTP + c][1][d];
+                        q3 += s_part[k * NTP + c][2][d];
                     }
                     const float R = s_sc[s].w;
-                    s_c[s][t] = make_float2(R * re, R * im);
+                    s_c[s][t] = make_float2(R * (q1 - q2), R * (q3 - q1 - q2));
                 }
                 __syncthreads();
-                // 4. receive GEMM: X[e][t] += sum_s Ge[e][s] c[s][t], rows e = mt_e + lane % 16
+                // 4. receive GEMM: X[e][t] += sum_s B[e][s] c[s][t], rows
+                //    e = mt_e + gi, k = scatterer 4 k + gk
                 if (re_live) {
-                    const int e = mt_e + gi;
+                    float2 ba[SCH / 4], ca[SCH / 4][NTP];
 #pragma unroll
                     for (int k = 0; k < SCH / 4; ++k) {
                         const int s = 4 * k + gk;
-                        float2 ge = make_float2(0.f, 0.f);
-                        if (e < A.N)
-                            for (int mu = 0; mu < A.nu; ++mu) {
-                                const float2 v = s_G[s * GS + e * A.nu + mu];
-                                ge.x += v.x;
-                                ge.y += v.y;
-                            }
+                        ba[k] = NUV == 2 ? sB[s * BST + mt_e + gi] : s_G[s * GS + mt_e + gi];
+#pragma unroll
+                        for (int c = 0; c < NTP; ++c) ca[k][c] = s_c[s][c * 16 + gi];
+                    }
+#pragma unroll
+                    for (int k = 0; k < SCH / 4; ++k)
 #pragma unroll
                         for (int c = 0; c < NTP; ++c) {
-                            const float2 cv = s_c[s][c * 16 + gi];
-                            // re: Ger cr - Gei ci ; im: Ger ci + Gei cr
-                            X[jj][c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.x, cv.x, X[jj][c][0], 0, 0, 0);
-                            X[jj][c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.y, -cv.y, X[jj][c][0], 0, 0, 0);
-                            X[jj][c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.x, cv.y, X[jj][c][1], 0, 0, 0);
-                            X[jj][c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ge.y, cv.x, X[jj][c][1], 0, 0, 0);
+                            X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
+                            X[jj][c][1] = mfma4(ba[k].y, ca[k][c].y, X[jj][c][1]);
+                            X[jj][c][2] = mfma4(ba[k].x + ba[k].y, ca[k][c].x + ca[k][c].y, X[jj][c][2]);
                         }
-                    }
                 }
-                __syncthreads();
+                // with one element-sum buffer the G tile must not be rewritten
+                // before every wave is done with it
+                if (NBB == 1) __syncthreads();
             }
         }
         // per-element partials [item][JT][TPG][N]; D[row][col]: row = element
-        // mt_e + 4 (lane / 16) + v, col = transmit c * 16 + lane % 16
+        // mt_e + 4 (lane / 16) + v, col = transmit c 16 + lane % 16
         if (re_live) {
             float2* out = A.part + (int64_t)item * JT * TPG * A.N;
 #pragma unroll
@@ -210,10 +253,11 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 for (int c = 0; c < NTP; ++c)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int e = mt_e + 4 * (lane >> 4) + v;
-                        const int t = c * 16 + (lane & 15);
-                        if (e < A.N)
-                            out[((int64_t)jj * TPG + t) * A.N + e] = make_float2(X[jj][c][0][v], X[jj][c][1][v]);
+                        const int e = mt_e + 4 * gk + v;
+                        const int t = c * 16 + gi;
+                        const float x1 = X[jj][c][0][v], x2 = X[jj][c][1][v], x3 = X[jj][c][2][v];
+                        if (e < A.N && jj < nb)
+                            out[((int64_t)jj * TPG + t) * A.N + e] = make_float2(x1 - x2, x3 - x1 - x2);
                     }
         }
 
@@ -225,59 +269,51 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     }
 }
 
-template <int NTP, int NQ, bool PERSIST>
+// Receive sums per lane: 12 JT NTP floats (JT = 2 for 32 transmit columns,
+// 4 for 16).
+constexpr int mt_jt(int ntp) { return ntp == 1 ? 4 : 2; }
+
+template <int NTP, int NUV, bool PERSIST>
 static SynthKernel mt_kernel_p(const SynthConfig& c)
 {
-    constexpr int JT = NTP == 1 ? 4 : 2;   // receive accumulators: 16 JT NTP floats
+    constexpr int JT = mt_jt(NTP);
     if (c.jt != JT) return nullptr;
-    if (c.has_y) return k_synth_mt<NTP, NQ, JT, true, false, PERSIST>;
-    if (c.table) return k_synth_mt<NTP, NQ, JT, false, true, PERSIST>;
-    return k_synth_mt<NTP, NQ, JT, false, false, PERSIST>;
+    if (c.has_y) return k_synth_mt<NTP, JT, NUV, true, false, PERSIST>;
+    if (c.table) return k_synth_mt<NTP, JT, NUV, false, true, PERSIST>;
+    return k_synth_mt<NTP, JT, NUV, false, false, PERSIST>;
 }
 
-template <int NTP, int NQ>
-static SynthKernel mt_kernel_nq(const SynthConfig& c)
+template <int NTP, int NUV>
+static SynthKernel mt_kernel_nuv(const SynthConfig& c)
 {
-    return c.persistent ? mt_kernel_p<NTP, NQ, true>(c) : mt_kernel_p<NTP, NQ, false>(c);
+    return c.persistent ? mt_kernel_p<NTP, NUV, true>(c) : mt_kernel_p<NTP, NUV, false>(c);
 }
 
-// The matrix-core path serves n_tx >= 4 with nu N <= 256 and N <= 128.
-bool mt_supported(int M, int N, int n_tx) { return n_tx >= 4 && M <= 256 && N <= 128; }
+// The matrix-core path serves n_tx >= 4 with N <= 128 elements and nu in {1, 2}.
+bool mt_supported(int M, int N, int n_tx)
+{
+    const int nu = N > 0 ? M / N : 0;
+    return n_tx >= 4 && N >= 1 && N <= 128 && (nu == 1 || nu == 2) && M == nu * N;
+}
 
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
 {
     SynthConfig c{};
     c.bs = 512;
     c.tt = n_tx > 16 ? 32 : 16;               // transmits per group
-    int np = 64;
-    while (np < N) np *= 2;                   // element slots
-    const int nq = 512 / np;
-    c.jt = c.tt == 16 ? 4 : 2;
+    c.jt = mt_jt(c.tt / 16);
     c.sc = 16;
+    c.pair = M == 2 * N;
     c.has_y = has_y;
     c.mfma = true;
-    c.nq = nq;
-    (void)M;
     return c;
 }
 
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
     const int ntp = c.tt / 16;
-    if (ntp == 1) {
-        switch (c.nq) {
-        case 4: return mt_kernel_nq<1, 4>(c);
-        case 8: return mt_kernel_nq<1, 8>(c);
-        default: return nullptr;
-        }
-    }
-    if (ntp == 2) {
-        switch (c.nq) {
-        case 4: return mt_kernel_nq<2, 4>(c);
-        case 8: return mt_kernel_nq<2, 8>(c);
-        default: return nullptr;
-        }
-    }
+    if (ntp == 1) return c.pair ? mt_kernel_nuv<1, 2>(c) : mt_kernel_nuv<1, 1>(c);
+    if (ntp == 2) return c.pair ? mt_kernel_nuv<2, 2>(c) : mt_kernel_nuv<2, 1>(c);
     return nullptr;
 }
 
