@@ -41,7 +41,7 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int NTP, int JT, int NUV, bool HASY, bool TABLE, bool PERSIST>
+template <int NTP, int JT, int NUV, int NX, bool HASY, bool TABLE, bool PERSIST>
 __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 {
     constexpr int NB = 512;
@@ -59,6 +59,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     constexpr int WS = NE + 1;              // row stride of the staged weights
     constexpr int NBB = NUV == 2 ? 2 : 1;   // element-sum buffers
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(NX == 2 || NX == 3, "receive sums: (Re, Im) or three products");
     static_assert(PPT * NSG == SCH, "synthesis threads must cover the chunk");
 
     __shared__ float4 s_sc[SCH];
@@ -104,14 +105,14 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
         const int nb = min(JT, A.n_bins - jb0);
         const int t0 = tg * TPG;
 
-        // receive sums [bin][column tile][P1, P2, P3]
-        floatx4 X[JT][NTP][3];
+        // receive sums [bin][column tile]: (Re, Im), or the three products
+        floatx4 X[JT][NTP][NX];
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
             for (int c = 0; c < NTP; ++c)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) X[jj][c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < NX; ++q) X[jj][c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
         for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
             if (tid < SCH) {
@@ -180,18 +181,24 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 {
                     const float2* gp = s_G + gi * GS + kp * KW + gk;
                     const float2* wp = s_W + (ct * 16 + gi) * WS + (kp * KW + gk) / NUV;
-                    float2 ga[KS], wa[KS];
-#pragma unroll
-                    for (int k = 0; k < KS; ++k) {
-                        ga[k] = gp[4 * k];
-                        wa[k] = wp[4 * k / NUV];
-                    }
+                    // operands loaded in batches of KB k-steps ahead of their MFMAs
+                    constexpr int KB = KS > 8 ? 8 : KS;
                     floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
 #pragma unroll
-                    for (int k = 0; k < KS; ++k) {
-                        p1 = mfma4(ga[k].x, wa[k].x, p1);
-                        p2 = mfma4(ga[k].y, wa[k].y, p2);
-                        p3 = mfma4(ga[k].x + ga[k].y, wa[k].x + wa[k].y, p3);
+                    for (int k0 = 0; k0 < KS; k0 += KB) {
+                        float2 ga[KB], wa[KB];
+#pragma unroll
+                        for (int k = 0; k < KB; ++k) {
+                            ga[k] = gp[4 * (k0 + k)];
+                            wa[k] = wp[4 * (k0 + k) / NUV];
+                        }
+#pragma unroll
+                        for (int k = 0; k < KB; ++k) {
+                            p1 = mfma4(ga[k].x, wa[k].x, p1);
+                            p2 = mfma4(ga[k].y, wa[k].y, p2);
+                            p3 = mfma4(ga[k].x + ga[k].y, wa[k].x + wa[k].y, p3);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                     // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
 #pragma unroll
@@ -233,9 +240,18 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     for (int k = 0; k < SCH / 4; ++k)
 #pragma unroll
                         for (int c = 0; c < NTP; ++c) {
-                            X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
-                            X[jj][c][1] = mfma4(ba[k].y, ca[k][c].y, X[jj][c][1]);
-                            X[jj][c][2] = mfma4(ba[k].x + ba[k].y, ca[k][c].x + ca[k][c].y, X[jj][c][2]);
+                            if (NX == 3) {
+                                X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
+                                X[jj][c][1] = mfma4(ba[k].y, ca[k][c].y, X[jj][c][1]);
+                                X[jj][c][NX - 1] =
+                                    mfma4(ba[k].x + ba[k].y, ca[k][c].x + ca[k][c].y, X[jj][c][NX - 1]);
+                            } else {
+                                // Re += Br cr - Bi ci, Im += Br ci + Bi cr
+                                X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
+                                X[jj][c][0] = mfma4(-ba[k].y, ca[k][c].y, X[jj][c][0]);
+                                X[jj][c][1] = mfma4(ba[k].x, ca[k][c].y, X[jj][c][1]);
+                                X[jj][c][1] = mfma4(ba[k].y, ca[k][c].x, X[jj][c][1]);
+                            }
                         }
                 }
                 // with one element-sum buffer the G tile must not be rewritten
@@ -255,9 +271,9 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     for (int v = 0; v < 4; ++v) {
                         const int e = mt_e + 4 * gk + v;
                         const int t = c * 16 + gi;
-                        const float x1 = X[jj][c][0][v], x2 = X[jj][c][1][v], x3 = X[jj][c][2][v];
-                        if (e < A.N && jj < nb)
-                            out[((int64_t)jj * TPG + t) * A.N + e] = make_float2(x1 - x2, x3 - x1 - x2);
+                        const float x1 = X[jj][c][0][v], x2 = X[jj][c][1][v], x3 = X[jj][c][NX - 1][v];
+                        const float2 xv = NX == 3 ? make_float2(x1 - x2, x3 - x1 - x2) : make_float2(x1, x2);
+                        if (e < A.N && jj < nb) out[((int64_t)jj * TPG + t) * A.N + e] = xv;
                     }
         }
 
@@ -269,18 +285,20 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     }
 }
 
-// Receive sums per lane: 12 JT NTP floats (JT = 2 for 32 transmit columns,
-// 4 for 16).
-constexpr int mt_jt(int ntp) { return ntp == 1 ? 4 : 2; }
+// Bins per item and receive sums per lane (4 NX JT NTP floats): 16 transmit
+// columns take 4 bins with the three-product sums, 32 columns take 4 bins
+// with (Re, Im) sums, which fit the register file.
+constexpr int mt_jt(int ntp) { return 4; }
+constexpr int mt_nx(int ntp) { return ntp == 1 ? 3 : 2; }
 
 template <int NTP, int NUV, bool PERSIST>
 static SynthKernel mt_kernel_p(const SynthConfig& c)
 {
-    constexpr int JT = mt_jt(NTP);
+    constexpr int JT = mt_jt(NTP), NX = mt_nx(NTP);
     if (c.jt != JT) return nullptr;
-    if (c.has_y) return k_synth_mt<NTP, JT, NUV, true, false, PERSIST>;
-    if (c.table) return k_synth_mt<NTP, JT, NUV, false, true, PERSIST>;
-    return k_synth_mt<NTP, JT, NUV, false, false, PERSIST>;
+    if (c.has_y) return k_synth_mt<NTP, JT, NUV, NX, true, false, PERSIST>;
+    if (c.table) return k_synth_mt<NTP, JT, NUV, NX, false, true, PERSIST>;
+    return k_synth_mt<NTP, JT, NUV, NX, false, false, PERSIST>;
 }
 
 template <int NTP, int NUV>
