@@ -1,9 +1,10 @@
-// Synthesis for many transmits on the matrix cores.  Per chunk of 16
-// scatterers and per bin, the transmit contraction of Eq. (29),
-//   a[s][t] = sum_n G[s][n] W[n][t]      (16 x nu N x 16-32 transmits),
-// and the receive contraction of Eqs. (32)-(33),
-//   X[e][t] += sum_s B[e][s] R_s a[s][t], B[e][s] = sum_{mu in e} G[s][mu]
-//                                        (elements x 16 x transmits),
+// Synthesis for many transmits on the matrix cores.  The weight of Eq. (29)
+// is the same for the nu sub-elements of an element, so with the element
+// sums B[e][s] = sum_{mu in e} G[s][mu] both contractions run over elements:
+// per chunk of 16 scatterers and per bin, the transmit contraction
+//   a[s][t] = sum_e B[e][s] W[e][t]      (16 x N x 16-32 transmits)
+// and the receive contraction of Eqs. (32)-(33)
+//   X[e][t] += sum_s B[e][s] R_s a[s][t]  (elements x 16 x transmits)
 // are complex GEMMs run with FP32 MFMA (16x16x4).  Each complex product
 // takes three real products (Karatsuba): with P1 = Re Re, P2 = Im Im and
 // P3 = (Re + Im)(Re + Im) summed over k, the product is (P1 - P2, P3 - P1 - P2).
@@ -13,16 +14,15 @@
 //
 // Block: 512 threads (8 waves), nu in {1, 2} at compile time.
 //   Synthesis: thread = (sub-element n, group of PPT scatterers).  Writes the
-//     G tile, and for nu = 2 the element sums B (one DPP exchange between the
-//     two sub-elements of an element, which are neighbouring lanes).
+//     element sums B (for nu = 2 one DPP exchange between the two
+//     sub-elements of an element, which are neighbouring lanes).
 //   Transmit GEMM: wave = (column tile ct of 16 transmits, share kp of the
-//     sub-elements); its three product tiles go to LDS and are summed over the
+//     elements); its three product tiles go to LDS and are summed over the
 //     shares in a fixed order, scaled by R_s, into c[s][t].
 //   Receive GEMM: wave w owns elements 16 w .. 16 w + 15 and all column tiles.
 // Barriers per bin: after synthesis, after the transmit GEMM, after the
-// reduction.  With nu = 2 the element sums are double-buffered, so the next
-// bin's synthesis may start while other waves still run this bin's receive
-// GEMM.  Partial spectra of every item, per element, go to `part`
+// reduction.  The element sums are double-buffered, so the next bin's
+// synthesis may start while other waves still run this bin's receive GEMM.  Partial spectra of every item, per element, go to `part`
 // ([item][JT][TPG][N]); like the vector path the terms are j G, and the
 // finaliser divides by j^2.
 #include <hip/hip_runtime.h>
@@ -50,21 +50,18 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int NSG = NB / MS;            // scatterer groups
-    constexpr int GS = MS + 4;              // row stride of the G tile (float2)
     constexpr int BST = NE + 4;             // row stride of the element sums
     constexpr int TPG = 16 * NTP;           // transmit columns of the group
-    constexpr int KP = 8 / NTP;             // sub-element shares per column tile
-    constexpr int KW = MS / KP;             // sub-elements per wave
+    constexpr int KP = 8 / NTP;             // element shares per column tile
+    constexpr int KW = NE / KP;             // elements per wave
     constexpr int KS = KW / 4;              // transmit-GEMM k-steps per wave
     constexpr int WS = NE + 1;              // row stride of the staged weights
-    constexpr int NBB = NUV == 2 ? 2 : 1;   // element-sum buffers
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(NX == 2 || NX == 3, "receive sums: (Re, Im) or three products");
     static_assert(PPT * NSG == SCH, "synthesis threads must cover the chunk");
 
     __shared__ float4 s_sc[SCH];
-    __shared__ float2 s_G[SCH * GS];
-    __shared__ float2 s_B[NUV == 2 ? NBB * SCH * BST : 1];
+    __shared__ float2 s_B[2 * SCH * BST];   // element sums, two buffers
     __shared__ float2 s_W[TPG * WS];
     __shared__ float s_part[8][3][256];
     __shared__ float2 s_c[SCH][TPG];
@@ -136,7 +133,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 if (jj >= nb) break;
                 const int jb = jb0 + jj;
                 const float jf = (float)(A.j_lo + jb);
-                float2* sB = s_B + (jj & (NBB - 1)) * (SCH * BST);
+                float2* sB = s_B + (jj & 1) * (SCH * BST);
                 // 0. transmit weights of this bin, W[t][e], zero outside N x n_tx
                 for (int idx = tid; idx < TPG * NE; idx += NB) {
                     const int t = idx / NE, e = idx % NE;
@@ -145,7 +142,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     const bool use = e < A.N && t0 + t < A.n_tx;
                     s_W[t * WS + e] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
                 }
-                // 1. j G of the chunk -> G tile [s][n]; element sums for nu = 2
+                // 1. j G of the chunk -> element sums B[s][e]
                 float2 G[PPT];
                 if constexpr (TABLE) {
                     // each term's table read is issued while the previous term
@@ -165,7 +162,6 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const int s = sh * PPT + k;
-                    s_G[s * GS + n] = G[k];
                     if (NUV == 2) {
                         // both lanes of the pair store the same element sum
                         const float bx = G[k].x + __int_as_float(__builtin_amdgcn_mov_dpp(
@@ -173,14 +169,16 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                         const float by = G[k].y + __int_as_float(__builtin_amdgcn_mov_dpp(
                                                       __float_as_int(G[k].y), 0xB1, 0xF, 0xF, true));
                         sB[s * BST + (n >> 1)] = make_float2(bx, by);
+                    } else {
+                        sB[s * BST + n] = G[k];
                     }
                 }
                 __syncthreads();
                 // 2. transmit GEMM share: rows s = gi, columns t = ct 16 + gi,
-                //    sub-elements kp KW + 4 k + gk
+                //    elements kp KW + 4 k + gk
                 {
-                    const float2* gp = s_G + gi * GS + kp * KW + gk;
-                    const float2* wp = s_W + (ct * 16 + gi) * WS + (kp * KW + gk) / NUV;
+                    const float2* gp = sB + gi * BST + kp * KW + gk;
+                    const float2* wp = s_W + (ct * 16 + gi) * WS + kp * KW + gk;
                     // operands loaded in batches of KB k-steps ahead of their MFMAs
                     constexpr int KB = KS > 8 ? 8 : KS;
                     floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
@@ -190,7 +188,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 #pragma unroll
                         for (int k = 0; k < KB; ++k) {
                             ga[k] = gp[4 * (k0 + k)];
-                            wa[k] = wp[4 * (k0 + k) / NUV];
+                            wa[k] = wp[4 * (k0 + k)];
                         }
 #pragma unroll
                         for (int k = 0; k < KB; ++k) {
@@ -232,7 +230,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 #pragma unroll
                     for (int k = 0; k < SCH / 4; ++k) {
                         const int s = 4 * k + gk;
-                        ba[k] = NUV == 2 ? sB[s * BST + mt_e + gi] : s_G[s * GS + mt_e + gi];
+                        ba[k] = sB[s * BST + mt_e + gi];
 #pragma unroll
                         for (int c = 0; c < NTP; ++c) ca[k][c] = s_c[s][c * 16 + gi];
                     }
@@ -254,9 +252,6 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                             }
                         }
                 }
-                // with one element-sum buffer the G tile must not be rewritten
-                // before every wave is done with it
-                if (NBB == 1) __syncthreads();
             }
         }
         // per-element partials [item][JT][TPG][N]; D[row][col]: row = element
