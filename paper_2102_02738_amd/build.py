@@ -20,7 +20,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fno-gpu-rdc", "-munsafe-fp-atomics"]
 
-SOURCES = [("kernels.hip", True), ("synth_mfma.hip", True), ("tables.hip", True), ("adjoint.hip", True), ("pfield.hip", True),
+SOURCES = [("kernels.hip", True), ("synth_mfma.hip", True), ("tables.hip", True), ("adjoint.hip", True),
+           ("adjoint_mfma.hip", True), ("pfield.hip", True),
            ("abi.cpp", False), ("plan.cpp", False)]
 
 

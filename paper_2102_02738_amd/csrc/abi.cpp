@@ -573,22 +573,26 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     if (!dR && !dX && !dY && !dZ) return;
     if (C.ph.total == 0) return;
     const int N = C.P.N;
-    AdjConfig cfg = adjoint_config(n_tx, C.has_y);
+    const bool use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && adjoint_mt_supported(C.P.M, N, n_tx);
+    AdjConfig cfg = use_mt ? adjoint_mt_config(C.P.M, N, n_tx, C.has_y) : adjoint_config(n_tx, C.has_y);
     cfg.table = C.table;
-    // items: (phantom, 256 scatterers, bin range); about 3000 items
+    // items: (phantom, scatterer slice, bin range); about 3000 items (matrix-core
+    // path: 4000), bin ranges a multiple of the bin tile
+    const int slice = cfg.scatterers;
     int64_t n_sb = 0;
-    for (int p = 0; p < n_ph; ++p) n_sb += (C.ph.off[p + 1] - C.ph.off[p] + 255) / 256;
-    int64_t rb = (int64_t(std::max(C.B.n_bins, 1)) * n_sb + 2999) / 3000;
+    for (int p = 0; p < n_ph; ++p) n_sb += (C.ph.off[p + 1] - C.ph.off[p] + slice - 1) / slice;
+    const int64_t target = use_mt ? 4000 : 3000;
+    int64_t rb = (int64_t(std::max(C.B.n_bins, 1)) * n_sb + target - 1) / target;
     rb = std::max<int64_t>(rb, cfg.jt);
     rb = (rb + cfg.jt - 1) / cfg.jt * cfg.jt;
     const int range_bins = (int)std::min<int64_t>(rb, std::max(C.B.n_bins, 1));
     const int n_ranges = (std::max(C.B.n_bins, 1) + range_bins - 1) / range_bins;
     std::vector<AdjItem> items;
     for (int p = 0; p < n_ph; ++p)
-        for (int64_t s0 = C.ph.off[p]; s0 < C.ph.off[p + 1]; s0 += 256)
+        for (int64_t s0 = C.ph.off[p]; s0 < C.ph.off[p + 1]; s0 += slice)
             for (int r = 0; r < n_ranges; ++r)
                 items.push_back(AdjItem{p, (int32_t)s0,
-                                        (int32_t)std::min<int64_t>(s0 + 256, C.ph.off[p + 1]), r});
+                                        (int32_t)std::min<int64_t>(s0 + slice, C.ph.off[p + 1]), r});
     const int n_items = (int)items.size();
 
     Layout up;
@@ -635,10 +639,13 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     A.range_bins = range_bins;
     A.K = C.K;
     if (log_enabled())
-        std::fprintf(stderr, "[simus] adjoint S=%lld T=%d bins=%d TT=%d JT=%d range=%d items=%d y=%d table=%d\n",
+        std::fprintf(stderr, "[simus] adjoint S=%lld T=%d bins=%d TT=%d JT=%d range=%d items=%d y=%d table=%d mfma=%d\n",
                      (long long)C.ph.total, n_tx, C.B.n_bins, cfg.tt, cfg.jt, range_bins, n_items,
-                     (int)C.has_y, (int)C.table);
-    hip_check(timed(K_ADJ, st, [&] { return launch_adjoint(cfg, A, n_items, st); }), "adjoint launch");
+                     (int)C.has_y, (int)C.table, (int)use_mt);
+    hip_check(timed(K_ADJ, st, [&] {
+                  return use_mt ? launch_adjoint_mt(cfg, A, n_items, st) : launch_adjoint(cfg, A, n_items, st);
+              }),
+              "adjoint launch");
     hip_check(timed(K_ADJRED, st, [&] {
                   return launch_adjoint_reduce(A.part, n_ranges, C.ph.total, refl, dR, dX, dY, dZ, st);
               }),

@@ -203,6 +203,7 @@ AdjConfig adjoint_config(int n_tx, bool has_y)
     // accumulator registers: (2 + 2 NX) complex per (bin, transmit)
     const int budget = has_y ? 4 : 8;
     c.jt = std::max(1, budget / c.tt);
+    c.scatterers = 256;
     c.has_y = has_y;
     return c;
 }

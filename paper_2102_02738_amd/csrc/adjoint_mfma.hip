@@ -1,0 +1,274 @@
+// Adjoint on the matrix cores (up to 16 transmits, N <= 128, nu in {1, 2}).
+//
+// The gradients of the misfit need, per scatterer s, bin j and transmit t,
+// four sums over the sub-elements n (see adjoint.hip):
+//   a_t = sum_n W_t G,  b_t = sum_n Lam_t G,  a'_t = sum_n W_t dG,  b'_t = sum_n Lam_t dG,
+// and since W and Lam depend only on the element, all of them are sums over
+// elements of the element sums B = sum_{mu in e} G and dB = sum_{mu in e} dG.
+// Stacking the rows (scatterer, {B, dB/dx, dB/dz, dB/dy}) and the columns
+// [W_0 .. W_{TG-1} | Lam_0 .. Lam_{TG-1}] makes them one complex GEMM per
+// chunk and bin:
+//   V[(s, L)][col] = sum_e Brow[(s, L)][e] WL[e][col]    (32 x N x 16 NTC),
+// run with FP32 MFMA (16x16x4), three real products per complex product.
+// Then dL/dR_s += Re P_j sum_t a_t b_t and dL/dxi_s += Re P_j sum_t (a'_t b_t
+// + a_t b'_t) (the R_s factor of the positions is applied by the reduction
+// kernel), accumulated across the item's bins in registers.  Nothing is
+// accumulated per bin, so each (sub-element, scatterer) pair is set up once
+// per 16 bins and stepped across them (green.hpp).
+//
+// Block: 512 threads (8 waves), chunks of 8 scatterers (32 rows, two row
+// tiles); work item = (phantom, scatterer slice, bin range).
+//   Synthesis: thread = (sub-element n, group of PPT scatterers): G and its
+//     gradient, element sums by one DPP exchange (nu = 2).
+//   GEMM: wave = (row tile, share of the elements); three product tiles per
+//     column tile go to LDS and are summed over the shares in a fixed order.
+//   Gradient: lane = (scatterer, transmit); lanes of a scatterer are summed
+//     once per chunk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "green.hpp"
+#include "kernels.hpp"
+
+namespace simus {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma_a(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float dpp_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+
+template <int NTC, int NUV, bool HASY, bool TABLE>
+__global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
+{
+    constexpr int NB = 512;
+    constexpr int NE = 128;                 // element slots
+    constexpr int MS = NE * NUV;            // sub-element slots
+    constexpr int SCH = 8;                  // scatterers per chunk
+    constexpr int NL = 4;                   // rows per scatterer: B, dB/dx, dB/dz, dB/dy
+    constexpr int ROWS = SCH * NL;          // 32
+    constexpr int RT = ROWS / 16;           // row tiles
+    constexpr int KP = 8 / RT;              // element shares per row tile
+    constexpr int KW = NE / KP;             // elements per wave
+    constexpr int KS = KW / 4;              // k-steps per wave
+    constexpr int TG = 8 * NTC;             // transmits
+    constexpr int NC = 2 * TG;              // columns: W, then Lam
+    constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
+    constexpr int LST = NE + 4;             // row stride of the element sums
+    constexpr int WS = NE + 1;              // row stride of the staged columns
+    constexpr int JS = 16;                  // bins per set-up
+    constexpr int NX = HASY ? 3 : 2;        // coordinates: X, Z (, Y)
+    static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(PPT * (NB / MS) == SCH, "synthesis threads must cover the chunk");
+
+    __shared__ float4 s_sc[SCH];
+    __shared__ float2 s_L[ROWS * LST];
+    __shared__ float2 s_WL[NC * WS];
+    __shared__ float s_part[8][3][256 * NTC];
+    __shared__ float2 s_V[ROWS][NC];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int gi = lane & 15, gk = lane >> 4;
+    // synthesis role
+    const int n = tid % MS, sp = tid / MS;
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    // GEMM role
+    const int rt = wave / KP, kp = wave % KP;
+    // gradient role
+    const bool glane = tid < SCH * TG;
+    const int gs = tid / TG, gt = tid % TG;
+
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
+    if (!HASY)   // rows dB/dy stay zero
+        for (int i = tid; i < SCH * LST; i += NB) s_L[((i / LST) * NL + 3) * LST + i % LST] = make_float2(0.f, 0.f);
+
+    const AdjItem it = A.items[blockIdx.x];
+    const int b_begin = it.range * A.range_bins;
+    const int b_end = min(A.n_bins, b_begin + A.range_bins);
+    const int p = it.phantom;
+
+    for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+        if (tid < SCH) {
+            const int s = s0 + tid;
+            float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding
+            if (s < it.s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], 0.f);
+            s_sc[tid] = v;
+        }
+        __syncthreads();
+        float gR = 0.f, gX[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) gX[i] = 0.f;
+
+        for (int jb0 = b_begin; jb0 < b_end; jb0 += JS) {
+            Geo g[PPT];
+            GeoD D[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const float4 v = s_sc[sp * PPT + k];
+                g[k] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0, &D[k]);
+                if (!active) g[k].E = make_float2(0.f, 0.f);
+            }
+            const int nb = min(JS, b_end - jb0);
+            for (int jj = 0; jj < nb; ++jj) {
+                const int jb = jb0 + jj;
+                const float jf = (float)(A.j_lo + jb);
+                const float inv_j = rcp_fast(jf);
+                // 0. columns of this bin: W of the transmits, then Lam; zero
+                //    outside N x n_tx
+                for (int idx = tid; idx < NC * NE; idx += NB) {
+                    const int col = idx / NE, e = idx % NE;
+                    const int t = col < TG ? col : col - TG;
+                    const int tt = min(t, A.n_tx - 1), ee = min(e, A.N - 1);
+                    const float2 w = col < TG ? A.W[((int64_t)jb * A.n_tx + tt) * A.N + ee]
+                                              : A.lam[(((int64_t)p * A.n_bins + jb) * A.n_tx + tt) * A.N + ee];
+                    const bool use = e < A.N && t < A.n_tx;
+                    s_WL[col * WS + e] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
+                }
+                // 1. G and its gradient -> element sums, rows (s, L)
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int s = sp * PPT + k;
+                    float2 dG[NX];
+                    float2 v[NX + 1];
+                    v[0] = green_grad_next<HASY, TABLE, NX>(A.K, g[k], D[k], jf, inv_j, s_tab, P, dG);
+#pragma unroll
+                    for (int i = 0; i < NX; ++i) v[1 + i] = dG[i];
+#pragma unroll
+                    for (int L = 0; L <= NX; ++L) {
+                        float2 b = v[L];
+                        if (NUV == 2) {
+                            b.x += dpp_xor1(b.x);
+                            b.y += dpp_xor1(b.y);
+                        }
+                        s_L[(s * NL + L) * LST + (NUV == 2 ? (n >> 1) : n)] = b;
+                    }
+                }
+                __syncthreads();
+                // 2. GEMM share: rows rt 16 + gi, columns ct 16 + gi, elements
+                //    kp KW + 4 k + gk
+                {
+                    const float2* lp = s_L + (rt * 16 + gi) * LST + kp * KW + gk;
+                    float2 la[KS];
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) la[k] = lp[4 * k];
+#pragma unroll
+                    for (int ct = 0; ct < NTC; ++ct) {
+                        const float2* wp = s_WL + (ct * 16 + gi) * WS + kp * KW + gk;
+                        float2 wa[KS];
+#pragma unroll
+                        for (int k = 0; k < KS; ++k) wa[k] = wp[4 * k];
+                        floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+#pragma unroll
+                        for (int k = 0; k < KS; ++k) {
+                            p1 = mfma_a(la[k].x, wa[k].x, p1);
+                            p2 = mfma_a(la[k].y, wa[k].y, p2);
+                            p3 = mfma_a(la[k].x + la[k].y, wa[k].x + wa[k].y, p3);
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int d = ct * 256 + (4 * gk + v) * 16 + gi;
+                            s_part[wave][0][d] = p1[v];
+                            s_part[wave][1][d] = p2[v];
+                            s_part[wave][2][d] = p3[v];
+                        }
+                    }
+                }
+                __syncthreads();
+                // 3. sum the shares (fixed order), combine the three products
+                for (int idx = tid; idx < ROWS * NC; idx += NB) {
+                    const int r = idx / NC, col = idx % NC;
+                    const int d = (col >> 4) * 256 + (r & 15) * 16 + (col & 15);
+                    const int w0 = (r >> 4) * KP;
+                    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) {
+                        q1 += s_part[w0 + k][0][d];
+                        q2 += s_part[w0 + k][1][d];
+                        q3 += s_part[w0 + k][2][d];
+                    }
+                    s_V[r][col] = make_float2(q1 - q2, q3 - q1 - q2);
+                }
+                __syncthreads();
+                // 4. gradient terms of lane (scatterer gs, transmit gt)
+                if (glane) {
+                    const float2 pw = A.pw[jb];
+                    const float2 a = s_V[gs * NL][gt], b = s_V[gs * NL][TG + gt];
+                    gR += cmul(pw, cmul(a, b)).x;
+#pragma unroll
+                    for (int i = 0; i < NX; ++i) {
+                        const float2 da = s_V[gs * NL + 1 + i][gt], db = s_V[gs * NL + 1 + i][TG + gt];
+                        gX[i] += cmul(pw, cfma(da, b, cmul(a, db))).x;
+                    }
+                }
+            }
+        }
+        // sum the transmit lanes of each scatterer; layout [range][s] of
+        // (dR, dX, dY, dZ) before the R_s factor
+        if (glane) {
+#pragma unroll
+            for (int m = 1; m < TG; m <<= 1) {
+                gR += __shfl_xor(gR, m);
+#pragma unroll
+                for (int i = 0; i < NX; ++i) gX[i] += __shfl_xor(gX[i], m);
+            }
+            const int s = s0 + gs;
+            if (gt == 0 && s < it.s_end)
+                A.part[(int64_t)it.range * A.S_total + s] = make_float4(gR, gX[0], HASY ? gX[NX - 1] : 0.f, gX[1]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int NTC, int NUV>
+static hipError_t launch_adj_mt_nuv(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
+{
+    if (c.has_y)
+        hipLaunchKernelGGL((k_adjoint_mt<NTC, NUV, true, false>), dim3(n_items), dim3(512), 0, st, a);
+    else if (c.table)
+        hipLaunchKernelGGL((k_adjoint_mt<NTC, NUV, false, true>), dim3(n_items), dim3(512), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_adjoint_mt<NTC, NUV, false, false>), dim3(n_items), dim3(512), 0, st, a);
+    return hipGetLastError();
+}
+
+bool adjoint_mt_supported(int M, int N, int n_tx)
+{
+    const int nu = N > 0 ? M / N : 0;
+    return n_tx >= 1 && n_tx <= 16 && N >= 1 && N <= 128 && (nu == 1 || nu == 2) && M == nu * N;
+}
+
+AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y)
+{
+    AdjConfig c{};
+    c.mfma = true;
+    c.tt = n_tx <= 8 ? 8 : 16;
+    c.jt = 16;
+    c.scatterers = 64;        // per item, a multiple of the 8-scatterer chunk
+    c.pair = M == 2 * N;
+    c.has_y = has_y;
+    return c;
+}
+
+hipError_t launch_adjoint_mt(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (c.tt == 8) return c.pair ? launch_adj_mt_nuv<1, 2>(c, a, n_items, st) : launch_adj_mt_nuv<1, 1>(c, a, n_items, st);
+    if (c.tt == 16) return c.pair ? launch_adj_mt_nuv<2, 2>(c, a, n_items, st) : launch_adj_mt_nuv<2, 1>(c, a, n_items, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace simus

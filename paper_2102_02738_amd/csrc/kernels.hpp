@@ -119,14 +119,20 @@ struct AdjArgs {
 };
 
 struct AdjConfig {
-    int tt;      // transmits per group
-    int jt;      // bins per tile
+    int tt;          // transmits per group (matrix-core path: columns per half)
+    int jt;          // bins per tile (matrix-core path: bins per set-up)
+    int scatterers;  // scatterers per work item (256 on the vector path)
     bool has_y;
     bool table;
+    bool mfma;       // matrix-core adjoint (adjoint_mfma.hip)
+    bool pair;       // matrix-core path: nu = 2
 };
 
 AdjConfig adjoint_config(int n_tx, bool has_y);
 hipError_t launch_adjoint(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st);
+bool adjoint_mt_supported(int M, int N, int n_tx);
+AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y);
+hipError_t launch_adjoint_mt(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st);
 hipError_t launch_adjoint_reduce(const float4* part, int n_ranges, int64_t S, const float* refl,
                                  float* dR, float* dX, float* dY, float* dZ, hipStream_t st);
 hipError_t launch_dft_t(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo, int nfft,
