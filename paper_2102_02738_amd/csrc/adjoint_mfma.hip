@@ -67,6 +67,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
     constexpr int NX = HASY ? 3 : 2;        // coordinates: X, Z (, Y)
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * (NB / MS) == SCH, "synthesis threads must cover the chunk");
+    static_assert(NC * NE % NB == 0, "column staging must divide evenly");
 
     __shared__ float4 s_sc[SCH];
     __shared__ float2 s_L[ROWS * LST];
@@ -128,15 +129,20 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                 const float jf = (float)(A.j_lo + jb);
                 const float inv_j = rcp_fast(jf);
                 // 0. columns of this bin: W of the transmits, then Lam; zero
-                //    outside N x n_tx
-                for (int idx = tid; idx < NC * NE; idx += NB) {
+                //    outside N x n_tx.  Loaded here, stored to LDS after the
+                //    synthesis so that the loads' latency is hidden behind it.
+                constexpr int NW = NC * NE / NB;
+                float2 wl[NW];
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int idx = tid + q * NB;
                     const int col = idx / NE, e = idx % NE;
                     const int t = col < TG ? col : col - TG;
                     const int tt = min(t, A.n_tx - 1), ee = min(e, A.N - 1);
                     const float2 w = col < TG ? A.W[((int64_t)jb * A.n_tx + tt) * A.N + ee]
                                               : A.lam[(((int64_t)p * A.n_bins + jb) * A.n_tx + tt) * A.N + ee];
                     const bool use = e < A.N && t < A.n_tx;
-                    s_WL[col * WS + e] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
+                    wl[q] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
                 }
                 // 1. G and its gradient -> element sums, rows (s, L)
 #pragma unroll
@@ -156,6 +162,11 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                         }
                         s_L[(s * NL + L) * LST + (NUV == 2 ? (n >> 1) : n)] = b;
                     }
+                }
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int idx = tid + q * NB;
+                    s_WL[(idx / NE) * WS + idx % NE] = wl[q];
                 }
                 __syncthreads();
                 // 2. GEMM share: rows rt 16 + gi, columns ct 16 + gi, elements

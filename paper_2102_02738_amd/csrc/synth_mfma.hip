@@ -134,13 +134,25 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 const int jb = jb0 + jj;
                 const float jf = (float)(A.j_lo + jb);
                 float2* sB = s_B + (jj & 1) * (SCH * BST);
-                // 0. transmit weights of this bin, W[t][e], zero outside N x n_tx
-                for (int idx = tid; idx < TPG * NE; idx += NB) {
+                // 0. transmit weights of this bin, W[t][e], zero outside N x n_tx.
+                //    With 16 columns they are loaded here and stored to LDS after
+                //    the synthesis, which hides the loads' latency; with 32 the
+                //    registers are short and they are stored at once.
+                constexpr int NW = TPG * NE / NB;
+                constexpr bool HOIST = NTP == 1;
+                auto w_at = [&](int idx) {
                     const int t = idx / NE, e = idx % NE;
                     const int tt = min(t0 + t, A.n_tx - 1), ee = min(e, A.N - 1);
                     const float2 w = A.W[((int64_t)jb * A.n_tx + tt) * A.N + ee];
                     const bool use = e < A.N && t0 + t < A.n_tx;
-                    s_W[t * WS + e] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
+                    return make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
+                };
+                float2 wv[HOIST ? NW : 1];
+                if (HOIST) {
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) wv[q] = w_at(tid + q * NB);
+                } else {
+                    for (int idx = tid; idx < TPG * NE; idx += NB) s_W[(idx / NE) * WS + idx % NE] = w_at(idx);
                 }
                 // 1. j G of the chunk -> element sums B[s][e]
                 float2 G[PPT];
@@ -171,6 +183,13 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                         sB[s * BST + (n >> 1)] = make_float2(bx, by);
                     } else {
                         sB[s * BST + n] = G[k];
+                    }
+                }
+                if (HOIST) {
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        const int idx = tid + q * NB;
+                        s_W[(idx / NE) * WS + idx % NE] = wv[q];
                     }
                 }
                 __syncthreads();
