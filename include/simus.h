@@ -103,7 +103,8 @@ typedef struct {
 } simus_options;
 
 #define SIMUS_FLAG_NO_MFMA       1   /* never use the MFMA multi-transmit contraction */
-#define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis */
+#define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis
+                                        (always used by the matrix-core path) */
 #define SIMUS_FLAG_NO_DELTA_TABLE 4  /* evaluate the elevation term directly (no table) */
 
 /* Frequency grid of one call. */

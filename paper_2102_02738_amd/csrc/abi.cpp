@@ -463,7 +463,9 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     std::memcpy(h + F.o_pb, pbase.data(), sizeof(int32_t) * n_ph);
     std::memcpy(h + F.o_ns, nsl.data(), sizeof(int32_t) * n_ph);
 
-    cfg.persistent = (opt->flags & SIMUS_FLAG_PERSISTENT) != 0 && F.n_items > 0;
+    // the matrix-core path always draws its items from a work counter (one
+    // resident block per CU; measurably faster than a static grid)
+    cfg.persistent = ((opt->flags & SIMUS_FLAG_PERSISTENT) != 0 || F.use_mt) && F.n_items > 0;
     if (cfg.persistent) {
         hipDeviceProp_t prop;
         int dev = 0;
