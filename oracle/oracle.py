@@ -42,6 +42,7 @@ class _Setup(C.Structure):
         ("baffle", C.c_int32), ("pad0", C.c_int32), ("zeta", C.c_double),
         ("c", C.c_double), ("alpha_db", C.c_double),
         ("fs", C.c_double), ("n_cycles", C.c_double),
+        ("dim2", C.c_int32), ("pad1", C.c_int32),
     ]
 
 
@@ -63,6 +64,7 @@ class Setup:
     baffle: int = 0
     zeta: float = 1.75
     nu: int = 0          # 0: Eq. (21)
+    dim2: int = 0        # 1: 2-D acoustics (Section V)
 
     def resolved_nu(self) -> int:
         if self.nu > 0:
@@ -73,7 +75,7 @@ class Setup:
         return _Setup(self.n_elements, self.resolved_nu(), self.fc, self.pitch,
                       self.width, self.height, self.elev_focus, self.bandwidth,
                       self.radius, self.baffle, 0, self.zeta, self.c,
-                      self.alpha_db, self.fs, self.n_cycles)
+                      self.alpha_db, self.fs, self.n_cycles, int(self.dim2), 0)
 
 
 _lib = None

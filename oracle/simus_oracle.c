@@ -24,6 +24,10 @@
  *   - RF(t_q) = Re sum_j X_j exp(-i w_j t_q), t_q = q/fs, no extra scale
  *     (time convention of Eq. 1).
  *   - frequency grid and RMS-field partition: see oracle_grid/oracle_pfield.
+ *   - 2-D acoustics (Section V): G = exp(i (k + i k_a) r) / sqrt(r) D with no
+ *     elevation term (Eqs. 36-38), r in the x-z plane (the point's y is not
+ *     used), a factor 2b on the two-way spectrum (Eq. 38) and sqrt(2b) on the
+ *     one-way field (Eq. 37), b the element half-width.
  *
  * Parity pins for every function live in tests/test_oracle_*.py.
  */
@@ -54,6 +58,8 @@ typedef struct {
     double alpha_db;        /* attenuation [dB/cm/MHz] */
     double fs;              /* sampling frequency [Hz] */
     double n_cycles;        /* n_lambda, number of wavelengths of the pulse */
+    int32_t dim2;           /* 1: 2-D acoustics of Section V */
+    int32_t pad1;
 } orc_setup;
 
 /* ------------------------------------------------------------------ */
@@ -204,12 +210,14 @@ double oracle_transducer_spectrum(const orc_setup *su, double w)
     return exp(-log(2.0) * pow(2.0 * fabs(w - wc) / wb, p));
 }
 
-/* Eqs. (28) and (34): the two-way spectral weight S_P(w) S_T(w). */
+/* Eqs. (28) and (34): the two-way spectral weight S_P(w) S_T(w); in 2-D
+ * also the factor 2b of Eq. (38). */
 static cplx spectral_weight(const orc_setup *su, double w)
 {
     double sp[2];
     oracle_pulse_spectrum(su, w, sp);
-    return (sp[0] + I * sp[1]) * oracle_transducer_spectrum(su, w);
+    double f2 = su->dim2 ? su->width : 1.0;
+    return (sp[0] + I * sp[1]) * oracle_transducer_spectrum(su, w) * f2;
 }
 
 /* ------------------------------------------------------------------ */
@@ -221,6 +229,7 @@ typedef struct { double xc, zc, tx, tz, nx, nz; } subel;
 static cplx green(const orc_setup *su, const subel *se, double X, double Y, double Z,
                   double k, double ka)
 {
+    if (su->dim2) Y = 0.0;                      /* the x-z plane */
     double dx = X - se->xc, dz = Z - se->zc;
     double xl = dx * se->tx + dz * se->tz;     /* along the face */
     double zl = dx * se->nx + dz * se->nz;     /* along the normal */
@@ -229,6 +238,7 @@ static cplx green(const orc_setup *su, const subel *se, double X, double Y, doub
     double r = sqrt(dx * dx + Y * Y + dz * dz);
     double b_sub = su->width / 2.0 / su->nu;
     double D = directivity(su, xl / rho, zl / rho, k, b_sub);
+    if (su->dim2) return cexp(I * (k + I * ka) * r) / sqrt(r) * D;   /* Eqs. (36)-(38) */
     cplx d = elevation_delta(su, Y, r, k);
     return cexp(I * (k + I * ka) * r) / r * D * d;
 }
@@ -238,6 +248,7 @@ static cplx green_grad(const orc_setup *su, const subel *se, double X, double Y,
                        double k, double ka, cplx dG[3])
 {
     dG[0] = dG[1] = dG[2] = 0.0;
+    if (su->dim2) Y = 0.0;
     double dx = X - se->xc, dz = Z - se->zc;
     double xl = dx * se->tx + dz * se->tz;
     double zl = dx * se->nx + dz * se->nz;
@@ -254,22 +265,26 @@ static cplx green_grad(const orc_setup *su, const subel *se, double X, double Y,
                                 dobl_dc = su->zeta / ((c_t + su->zeta) * (c_t + su->zeta)); }
     else                      { obl = c_t; dobl_dc = 1.0; }
     double D = sn * obl;
-    cplx d = elevation_delta(su, Y, r, k);
-    cplx d_dr, d_dy;
-    elevation_delta_grad(su, Y, r, k, &d_dr, &d_dy);
-    cplx E = cexp(I * (k + I * ka) * r) / r;
+    cplx d = 1.0, d_dr = 0.0, d_dy = 0.0;
+    if (!su->dim2) {
+        d = elevation_delta(su, Y, r, k);
+        elevation_delta_grad(su, Y, r, k, &d_dr, &d_dy);
+    }
+    /* amplitude 1/r (3-D) or 1/sqrt(r) (2-D) */
+    double apow = su->dim2 ? 0.5 : 1.0;
+    cplx E = cexp(I * (k + I * ka) * r) / pow(r, apow);
     cplx G = E * D * d;
     /* partials of the local coordinates w.r.t. X, Y, Z */
     double dxl[3] = { se->tx, 0.0, se->tz };
     double dzl[3] = { se->nx, 0.0, se->nz };
-    double dY[3] = { 0.0, 1.0, 0.0 };
+    double dY[3] = { 0.0, su->dim2 ? 0.0 : 1.0, 0.0 };
     for (int a = 0; a < 3; ++a) {
         double drho = (xl * dxl[a] + zl * dzl[a]) / rho;
         double dr = (xl * dxl[a] + zl * dzl[a] + Y * dY[a]) / r;
         double ds_t = (dxl[a] * rho - xl * drho) / (rho * rho);
         double dc_t = (dzl[a] * rho - zl * drho) / (rho * rho);
         double dD = dsn * k * b_sub * ds_t * obl + sn * dobl_dc * dc_t;
-        cplx dE = E * (I * (k + I * ka) - 1.0 / r) * dr;
+        cplx dE = E * (I * (k + I * ka) - apow / r) * dr;
         cplx dd = d_dr * dr + d_dy * dY[a];
         dG[a] = dE * D * d + E * dD * d + E * D * dd;
     }
@@ -373,7 +388,8 @@ void oracle_grid(const orc_setup *su, int32_t n_t_req, int32_t nfft_req, double 
     for (int64_t s = 0; s < n_scat; ++s)
         for (int n = 0; n < M; ++n) {
             double dx = x[s] - se[n].xc, dz = z[s] - se[n].zc;
-            double r = sqrt(dx * dx + y[s] * y[s] + dz * dz);
+            double yy = su->dim2 ? 0.0 : y[s];
+            double r = sqrt(dx * dx + yy * yy + dz * dz);
             if (r > rmax) rmax = r;
         }
     free(se);
@@ -561,7 +577,8 @@ int32_t oracle_pfield_nf(const orc_setup *su, const double *delays,
     for (int64_t p = 0; p < n_pts; ++p)
         for (int n = 0; n < M; ++n) {
             double dx = X[p] - se[n].xc, dz = Z[p] - se[n].zc;
-            double r = sqrt(dx * dx + Y[p] * Y[p] + dz * dz);
+            double yy = su->dim2 ? 0.0 : Y[p];
+            double r = sqrt(dx * dx + yy * yy + dz * dz);
             double t = r / su->c + delays[n / nu];
             if (t > tmax) tmax = t;
         }
@@ -613,6 +630,7 @@ void oracle_pfield(const orc_setup *su, const double *delays, const double *apod
             double sp[2];
             oracle_pulse_spectrum(su, w, sp);
             cplx ptx = (sp[0] + I * sp[1]) * sqrt(oracle_transducer_spectrum(su, w));  /* Eq. (28) */
+            if (su->dim2) ptx *= sqrt(su->width);                                  /* Eq. (37) */
             cplx acc = 0.0;
             for (int n = 0; n < M; ++n) {
                 int e = n / nu;
