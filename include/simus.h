@@ -106,6 +106,11 @@ typedef struct {
 #define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis
                                         (always used by the matrix-core path) */
 #define SIMUS_FLAG_NO_DELTA_TABLE 4  /* evaluate the elevation term directly (no table) */
+#define SIMUS_FLAG_2D            8   /* 2-D acoustics (Section V, Eqs. 35-38): Green's term
+                                        exp(i (k + i k_a) r) / sqrt(r) D in the x-z plane, no
+                                        elevation term, factor 2b (element width) on the two-way
+                                        spectrum and sqrt(2b) on the one-way field; y (Y) must
+                                        be NULL */
 
 /* Frequency grid of one call. */
 typedef struct {

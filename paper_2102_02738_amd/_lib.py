@@ -19,6 +19,7 @@ ERRORS = {-1: "SIMUS_EINVAL", -2: "SIMUS_EDOMAIN", -3: "SIMUS_ENOMEM", -4: "SIMU
 FLAG_NO_MFMA = 1
 FLAG_PERSISTENT = 2
 FLAG_NO_DELTA_TABLE = 4
+FLAG_2D = 8
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",

@@ -215,6 +215,7 @@ ModelConst model_constants(const Probe& P, const Band& B)
     K.inv_rf = std::isinf(P.elev_focus) ? 0.f : (float)(1.0 / P.elev_focus);
     K.zeta = (float)P.zeta;
     K.baffle = P.baffle;
+    K.dim2 = P.dim2 ? 1 : 0;
     // Eq. (18): A_3 = conj(A_1), B_3 = conj(B_1), A_4 = conj(A_2), B_4 = conj(B_2).
     using eq18::Ar;
     using eq18::Ai;
@@ -280,7 +281,9 @@ Common make_common(const simus_probe* probe, const simus_medium* medium, const s
     C.K = model_constants(C.P, C.B);
     C.n_tx = n_tx;
     C.has_y = has_y;
-    C.table = !C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
+    if (C.P.dim2 && has_y) throw Error{SIMUS_EINVAL, "y must be NULL with SIMUS_FLAG_2D"};
+    // 2-D: the (unit) table path carries the absent elevation term
+    C.table = C.P.dim2 || (!C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE));
     return C;
 }
 
@@ -344,9 +347,11 @@ void fill_upload(char* h, const CommonLayout& L, const Common& C, const double* 
         at<double>(h, L.dl)[i] = delays[i];
         at<float>(h, L.ap)[i] = apod ? apod[i] : 1.f;
     }
+    // two-way spectral weight (Eqs. 28, 34); in 2-D with the factor 2b of Eq. (38)
+    const double f2 = C.P.dim2 ? C.P.width : 1.0;
     for (int b = 0; b < C.B.n_bins; ++b) {
         const double w = 2 * M_PI * (C.B.j_lo + b) * C.B.df;
-        const std::complex<double> v = pulse_spectrum(C.P, w) * transducer_spectrum(C.P, w);
+        const std::complex<double> v = pulse_spectrum(C.P, w) * transducer_spectrum(C.P, w) * f2;
         at<float2>(h, L.pw)[b] = make_float2((float)v.real(), (float)v.imag());
     }
 }
@@ -370,7 +375,8 @@ void launch_common(char* d, const CommonLayout& L, const Common& C, const float*
         hip_check(launch_rrange(at<uint32_t>(d, L.rr), x, y, z, C.ph.total, sub_geo(d, L), C.P.M, st),
                   "range launch");
         hip_check(launch_dtable(at<float4>(d, L.dt), at<DeltaParams>(d, L.dp), at<uint32_t>(d, L.rr),
-                                C.K, C.P.height, C.B.j_lo, C.B.j_lo + std::max(C.B.n_bins, 1) - 1, st),
+                                C.K, C.P.height, C.B.j_lo, C.B.j_lo + std::max(C.B.n_bins, 1) - 1,
+                                C.P.dim2, st),
                   "table launch");
     }
 }
@@ -694,7 +700,8 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     C.K = model_constants(C.P, C.B);
     C.n_tx = 1;
     C.has_y = Y != nullptr;
-    C.table = !C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE);
+    if (C.P.dim2 && C.has_y) throw Error{SIMUS_EINVAL, "Y must be NULL with SIMUS_FLAG_2D"};
+    C.table = C.P.dim2 || (!C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE));
     C.ph.n = 1;
     C.ph.total = n_pts;
     const int JT = 8;
@@ -715,9 +722,11 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     const size_t o_part = dv.add(sizeof(float) * size_t(n_ranges) * n_pts);
     Arena& a = arena_for(st, dv.size, up.size);
     fill_upload(a.host, L, C, delays, apod);
+    // one-way P_Tx = S_P sqrt(S_T) (Eq. 28); in 2-D with the factor sqrt(2b) of Eq. (37)
+    const double f1 = C.P.dim2 ? std::sqrt(C.P.width) : 1.0;
     for (int j = 1; j <= n_f; ++j) {
         const double w = 2 * M_PI * j * C.B.df;
-        const std::complex<double> v = pulse_spectrum(C.P, w) * std::sqrt(transducer_spectrum(C.P, w));
+        const std::complex<double> v = pulse_spectrum(C.P, w) * std::sqrt(transducer_spectrum(C.P, w)) * f1;
         at<float2>(a.host, o_ptx)[j - 1] = make_float2((float)v.real(), (float)v.imag());
     }
     upload(a, up.size, st);
@@ -822,6 +831,7 @@ int simus_rf_grid(const simus_probe* probe, const simus_medium* medium, const si
         check_transmits(P, n_tx, delays, nullptr);
         if (n_scat < 0) throw Error{SIMUS_EINVAL, "n_scat must be >= 0"};
         if (n_scat > 0 && (!x || !z)) throw Error{SIMUS_EINVAL, "x and z must be non-NULL"};
+        if (P.dim2 && y) throw Error{SIMUS_EINVAL, "y must be NULL with SIMUS_FLAG_2D"};
         const SubElements S = sub_elements(P);
         check_domain(P, S, n_scat, x, y, z);
         int64_t nfft = opt->nfft;
@@ -892,6 +902,7 @@ int simus_pfield_nf(const simus_probe* probe, const simus_medium* medium, const 
         const Probe P = make_probe(probe, medium, opt);
         check_transmits(P, 1, delays, nullptr);
         if (n_pts < 1 || !X || !Z) throw Error{SIMUS_EINVAL, "at least one point (X, Z non-NULL) is required"};
+        if (P.dim2 && Y) throw Error{SIMUS_EINVAL, "Y must be NULL with SIMUS_FLAG_2D"};
         const SubElements S = sub_elements(P);
         *n_f = pfield_nf_host(P, S, delays, n_pts, X, Y, Z);
     });

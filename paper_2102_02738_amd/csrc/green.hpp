@@ -143,7 +143,9 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
         dobl = K.zeta * den * den;
     }
     const float inv_r = rcp_fast(rf);
-    const float amp = ok ? obl * inv_r : 0.f;
+    // amplitude 1/r, or 1/sqrt(r) in 2-D (Eqs. 36-38)
+    const float amp = ok ? obl * (K.dim2 ? rsq_fast(rf) : inv_r) : 0.f;
+    const float apow = K.dim2 ? 0.5f : 1.f;
     const float jf0 = (float)j0;
 
     Geo g;
@@ -184,7 +186,7 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
             const float dr = (xl * dxl[a] + zl * dzl[a] + yf * dyy[a]) * inv_r;
             const float dst = (dxl[a] - st * drho) * inv_rho;
             const float dct = (dzl[a] - ct * drho) * inv_rho;
-            D->la[a] = ok ? dobl * dct * inv_obl - dr * inv_r : 0.f;
+            D->la[a] = ok ? dobl * dct * inv_obl - apow * dr * inv_r : 0.f;
             D->rd[a] = ok ? dr : 0.f;
             D->ud[a] = ok ? K.b_sub * dst : 0.f;
             D->qd[a] = ok ? 0.5f * dr * inv_r * inv_r : 0.f;

@@ -29,6 +29,7 @@ struct ModelConst {
     float inv_rf;            // 1 / R_f (0 for an unfocused element)
     float zeta;              // baffle impedance ratio
     int32_t baffle;          // 0 soft, 1 rigid, 2 zeta
+    int32_t dim2;            // 2-D acoustics: amplitude 1/sqrt(r), no elevation term
     Gauss4 g;
 };
 
@@ -189,7 +190,8 @@ hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 // of q = (pi f / c)(1/R_f - 1/r), f over the evaluated band.
 hipError_t launch_rrange(uint32_t* rr, const float* x, const float* y, const float* z, int64_t n,
                          const SubGeo& sub, int M, hipStream_t st);
+// unit: every interval holds delta = 1 (2-D acoustics, no elevation term).
 hipError_t launch_dtable(float4* tab, DeltaParams* par, const uint32_t* rr, const ModelConst& K,
-                         double height, int j_first, int j_last, hipStream_t st);
+                         double height, int j_first, int j_last, bool unit, hipStream_t st);
 
 }  // namespace simus

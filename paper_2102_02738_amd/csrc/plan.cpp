@@ -72,6 +72,7 @@ Probe make_probe(const simus_probe* p, const simus_medium* m, const simus_option
     P.fs = o->fs;
     P.n_cycles = o->n_cycles;
     P.eps = o->spectral_eps;
+    P.dim2 = (o->flags & SIMUS_FLAG_2D) != 0;
     P.nu = o->nu > 0 ? o->nu : nu_from_width(P.width, P.fc, P.bandwidth, P.c);
     P.M = P.nu * P.N;
     require(P.M <= 1024, "nu * n_elements must be <= 1024");

@@ -25,6 +25,7 @@ struct Probe {
     double radius = 0, zeta = 0;
     double c = 0, alpha_db = 0;
     double fs = 0, n_cycles = 1, eps = 0;
+    bool dim2 = false;               // 2-D acoustics (Section V)
     bool convex() const { return radius > 0; }
 };
 

@@ -92,7 +92,7 @@ __device__ void delta_q(double q, double h, double& dr, double& di, double& gr, 
 __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* par,
                                                      const uint32_t* rr, double q_per_bin,
                                                      double inv_rf, double height, int j_first,
-                                                     int j_last)
+                                                     int j_last, int unit)
 {
     double rmin = (double)__uint_as_float(rr[0]), rmax = (double)__uint_as_float(rr[1]);
     if (!(rmin <= rmax) || !(rmin > 0.0)) {   // no scatterers
@@ -130,7 +130,9 @@ __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* p
         c[1][i] = (float)m[0][i];
         c[2][i] = (float)(3.0 * (p[1][i] - p[0][i]) - 2.0 * m[0][i] - m[1][i]);
         c[3][i] = (float)(2.0 * (p[0][i] - p[1][i]) + m[0][i] + m[1][i]);
+        if (unit) c[0][i] = c[1][i] = c[2][i] = c[3][i] = 0.f;
     }
+    if (unit) c[0][0] = 1.f;
     tab[2 * k] = make_float4(c[0][0], c[0][1], c[1][0], c[1][1]);
     tab[2 * k + 1] = make_float4(c[2][0], c[2][1], c[3][0], c[3][1]);
     if (k == 0) {
@@ -144,11 +146,11 @@ __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* p
 }
 
 hipError_t launch_dtable(float4* tab, DeltaParams* par, const uint32_t* rr, const ModelConst& K,
-                         double height, int j_first, int j_last, hipStream_t st)
+                         double height, int j_first, int j_last, bool unit, hipStream_t st)
 {
     const double q_per_bin = M_PI * K.turns_per_bin_m;   // pi df / c
     hipLaunchKernelGGL(k_dtable, dim3(1), dim3(DELTA_NT), 0, st, tab, par, rr, q_per_bin,
-                       (double)K.inv_rf, height, j_first, j_last);
+                       (double)K.inv_rf, height, j_first, j_last, unit ? 1 : 0);
     return hipGetLastError();
 }
 
