@@ -16,6 +16,8 @@ vector path, no graph):
                       HIP graph
   forward_adjoint     5 plane waves x 100,000 scatterers: forward, residual
                       against a perturbed phantom's RF, adjoint gradients
+  two_d               the main workload in 2-D acoustics (Section V), with the
+                      synthesis kernel's roofline
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
 """
@@ -33,13 +35,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Issue-cost model of the synthesis kernel this workload runs,
-# k_synth<256, 8, 16, 1, false, true, true>: instructions per Green's term in
+# k_synth<256, 8, 16, 1, false, 1, true>: instructions per Green's term in
 # its innermost loop (two bins of 8 scatterers per lane and iteration),
 # counted from the gfx950 assembly with paper_2102_02738_amd/diag/isa_count.py.
-SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELb1ELb1EEEvNS_9SynthArgsE"
+SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELi1ELb1EEEvNS_9SynthArgsE"
 SYNTH_TERMS_PER_ITER = 16
 SYNTH_VALU_PER_G = 35.125      # full-rate VALU instructions per G term
 SYNTH_TRANS_PER_G = 1.0        # transcendental instructions per G term
+# The same kernel in 2-D acoustics (no elevation term), k_synth<256, 8, 16,
+# 1, false, 2, true>, counted the same way.
+SYNTH2D_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELi2ELb1EEEvNS_9SynthArgsE"
+SYNTH2D_VALU_PER_G = 17.875
+SYNTH2D_TRANS_PER_G = 0.0
 TRANS_ISSUE_COST = 4.0         # a transcendental issues at 1/4 of the FP32 rate (diag/valu_rate)
 # MI355X FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-instructions/s
 # (256 CU x 128 FP32 lanes/clk x 2.4 GHz); one "slot" = one lane-instruction.
@@ -115,10 +122,11 @@ def _rel(a, b) -> float:
 class Case:
     """A workload on the device: scatterers, grid and options."""
 
-    def __init__(self, name: str):
+    def __init__(self, name: str, flags: int = 0):
         import torch
         from paper_2102_02738_amd import inputs, grid
         self.w = w = inputs.workload(name)
+        w["options"] = dict(w["options"], flags=flags)
         self.name = name
         x, y, z, R, off = inputs.concat_phantoms(w["phantoms"])
         self.host = (x, y, z, R)
@@ -266,6 +274,34 @@ def extra_forward_adjoint(steps: int) -> dict:
                 rel_l2_grad_vs_plain={k: _rel(grads[k], pg[k]) for k in grads})
 
 
+def extra_two_d(steps: int, ms_3d: float) -> dict:
+    """The main workload in 2-D acoustics: no elevation term, 1/sqrt(r)
+    spreading (Section V)."""
+    import torch
+    from paper_2102_02738_amd import _lib, FLAG_2D
+    c = Case("pw128_s50k", flags=FLAG_2D)
+    w = c.w
+    out = torch.empty((1, c.T, c.N, c.n_t), device="cuda")
+
+    def step():
+        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R)
+
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    ms = _median_ms(step, steps * 5, warmup=2)
+    _lib.profile_enable(False)
+    synth_ms, n = _lib.profile_read("synth")
+    synth_ms /= max(n, 1)
+    g_terms = float(c.S) * c.N * c.g["nu"] * c.g["n_bins"]
+    per_g = SYNTH2D_VALU_PER_G + TRANS_ISSUE_COST * SYNTH2D_TRANS_PER_G
+    achieved = g_terms * per_g / (synth_ms * 1e-3)
+    return dict(workload=c.name + " (2-D)", ms_per_call=ms, evals_per_s=c.evals() / (ms * 1e-3),
+                speedup_vs_3d=ms_3d / ms, synth_kernel_ms=synth_ms,
+                roofline=dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12,
+                              unit="TOP/s", frac=achieved / VALU_PEAK,
+                              kernel="k_synth<256, 8, 16, 1, false, 2, true>", ops_per_unit=per_g))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +367,7 @@ def main():
     achieved = g_terms * per_g / (synth_avg_ms * 1e-3)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="TOP/s",
                 frac=achieved / VALU_PEAK, traffic=measured_traffic(c.name),
-                kernel="k_synth<256, 8, 16, 1, false, true, true>", kernel_ms=synth_avg_ms,
+                kernel="k_synth<256, 8, 16, 1, false, 1, true>", kernel_ms=synth_avg_ms,
                 ops_per_unit=per_g, valu_per_unit=SYNTH_VALU_PER_G, trans_per_unit=SYNTH_TRANS_PER_G,
                 unit_count=g_terms, unit_def="G term (sub-element x scatterer x bin)",
                 op_def="lane issue slot: full-rate VALU 1, transcendental 4")
@@ -353,6 +389,7 @@ def main():
             "batched_transmits": extra_batched_transmits(args.extra_steps),
             "uneven_phantoms": extra_uneven_phantoms(args.extra_steps),
             "forward_adjoint": extra_forward_adjoint(args.extra_steps),
+            "two_d": extra_two_d(args.extra_steps, ms_per_step),
         }
     if not args.no_cpu_baseline:
         x, y, z, R = c.host

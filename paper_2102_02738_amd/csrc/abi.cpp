@@ -411,6 +411,7 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     SynthConfig& cfg = F.cfg;
     cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y) : synth_config(M, Cc.P.nu, n_tx, Cc.has_y);
     cfg.table = Cc.table;
+    cfg.dim2 = Cc.P.dim2;   // the vector path skips the (unit) table in 2-D
     const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;
     // element partials (matrix-core path, or paired lanes) or sub-element partials
     const bool per_element = F.use_mt || cfg.pair;

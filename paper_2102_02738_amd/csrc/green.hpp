@@ -417,6 +417,17 @@ __device__ __forceinline__ float2 green_grad_next(const ModelConst& K, Geo& g, G
     return Gv;
 }
 
+// j G at bin j without an elevation term (2-D acoustics, Eqs. 36-38): the
+// sinc's 1/j is left to the caller.  Advances the pair to bin j + 1.
+__device__ __forceinline__ float2 green_next_2d(Geo& g)
+{
+    const float2 G = make_float2(g.E.x * g.s, g.E.y * g.s);
+    g.E = cmul(g.E, g.dE);
+    g.d = fmaf(g.lam, g.s, g.d);
+    g.s += g.d;
+    return G;
+}
+
 // j G at bin j from a fetched table interval (y = 0): the sinc's 1/j is left
 // to the caller.  Advances the pair to bin j + 1.
 __device__ __forceinline__ float2 green_next_fetched(Geo& g, const DeltaFetch& f)

@@ -124,7 +124,9 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-template <int BS, int SC, int JT, int TT, bool HASY, bool TABLE, bool PAIR>
+// EL: elevation term evaluated directly (0), from the table (1), or absent
+// (2, 2-D acoustics).
+template <int BS, int SC, int JT, int TT, bool HASY, int EL, bool PAIR>
 __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 {
     constexpr int NS = SC * TT;            // sums per bin
@@ -141,6 +143,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     // [1] = (Im c, Re c) for odd lanes)
     __shared__ float2 s_c[2][PAIR ? 2 : 1][NS];
     __shared__ float s_acc[JT * TT * BS * NA];
+    constexpr bool TABLE = EL == 1;
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
     const int tid = threadIdx.x;
@@ -256,7 +259,10 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 const int buf = jj & 1;
                 const float jf = (float)(A.j_lo + jb);
                 // j G: the sinc's 1/j is applied as 1/j^2 by the finaliser
-                if constexpr (TABLE) {
+                if constexpr (EL == 2) {
+#pragma unroll
+                    for (int s = 0; s < SC; ++s) Gc[s] = green_next_2d(g[s]);
+                } else if constexpr (TABLE) {
                     // each term's table read is issued while the previous term
                     // is evaluated (one read ahead keeps three blocks per CU)
                     DeltaFetch fch[2];
@@ -360,9 +366,10 @@ static SynthKernel synth_kernel_y(const SynthConfig& cfg)
 {
     constexpr int JT = synth_jt(BS, TT, PAIR);
     if (cfg.jt != JT || cfg.sc != SC) return nullptr;
-    if (cfg.has_y) return k_synth<BS, SC, JT, TT, true, false, PAIR>;
-    if (cfg.table) return k_synth<BS, SC, JT, TT, false, true, PAIR>;
-    return k_synth<BS, SC, JT, TT, false, false, PAIR>;
+    if (cfg.has_y) return k_synth<BS, SC, JT, TT, true, 0, PAIR>;
+    if (cfg.dim2) return k_synth<BS, SC, JT, TT, false, 2, PAIR>;
+    if (cfg.table) return k_synth<BS, SC, JT, TT, false, 1, PAIR>;
+    return k_synth<BS, SC, JT, TT, false, 0, PAIR>;
 }
 
 template <int BS, bool PAIR>

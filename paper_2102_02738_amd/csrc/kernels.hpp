@@ -86,6 +86,7 @@ struct SynthConfig {
     int jt;      // bins per tile
     bool has_y;
     bool table;  // elevation term from the table (requires !has_y)
+    bool dim2;   // 2-D acoustics: no elevation term (vector path skips the table)
     bool persistent;
     bool pair;   // nu = 2: element sums of lane pairs, one float accumulator per lane
     bool mfma;   // transmit contraction on the matrix cores (synth_mfma.hip)

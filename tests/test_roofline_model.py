@@ -24,14 +24,21 @@ def test_bench_cost_constants_match_isa():
     trans = float(re.search(r"trans_per_term: ([0-9.]+)", out).group(1))
     assert valu == pytest.approx(bench.SYNTH_VALU_PER_G, abs=1e-3), out
     assert trans == pytest.approx(bench.SYNTH_TRANS_PER_G, abs=1e-3), out
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "paper_2102_02738_amd", "diag", "isa_count.py"),
+                          "kernels.hip", bench.SYNTH2D_KERNEL, "--terms", str(bench.SYNTH_TERMS_PER_ITER)],
+                         check=True, capture_output=True, text=True).stdout
+    assert float(re.search(r"valu_per_term: ([0-9.]+)", out).group(1)) == pytest.approx(
+        bench.SYNTH2D_VALU_PER_G, abs=1e-3), out
+    assert float(re.search(r"trans_per_term: ([0-9.]+)", out).group(1)) == pytest.approx(
+        bench.SYNTH2D_TRANS_PER_G, abs=1e-3), out
 
 
 def test_benchmark_instantiation_is_the_one_counted():
     """pw128_s50k (128 elements, nu = 2, one transmit, y = 0) runs
-    k_synth<256, 8, 16, 1, false, true, true>: block 256, 8 scatterers per
+    k_synth<256, 8, 16, 1, false, 1, true>: block 256, 8 scatterers per
     chunk, 16 bins per tile, 1 transmit, elevation table, paired lanes."""
     sys.path.insert(0, ROOT)
     import bench
-    assert "ILi256ELi8ELi16ELi1ELb0ELb1ELb1E" in bench.SYNTH_KERNEL
+    assert "ILi256ELi8ELi16ELi1ELb0ELi1ELb1E" in bench.SYNTH_KERNEL
     src = open(os.path.join(ROOT, "paper_2102_02738_amd", "csrc", "kernels.hip")).read()
     assert "#define SIMUS_SC1 8" in src and "#define SIMUS_JT_MAX 16" in src
