@@ -18,6 +18,8 @@ vector path, no graph):
                       against a perturbed phantom's RF, adjoint gradients
   two_d               the main workload in 2-D acoustics (Section V), with the
                       synthesis kernel's roofline
+  large_t             128 focused transmits of a 64-element phased array,
+                      40,000 scatterers (the shape of Fig. 12's sequence)
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
 """
@@ -274,6 +276,33 @@ def extra_forward_adjoint(steps: int) -> dict:
                 rel_l2_grad_vs_plain={k: _rel(grads[k], pg[k]) for k in grads})
 
 
+def extra_large_t(steps: int) -> dict:
+    """128 focused transmits in one call vs 128 single-transmit calls."""
+    import torch
+    from paper_2102_02738_amd import _lib, FLAG_NO_MFMA
+    c = Case("ph64x128_s40k")
+    w = c.w
+    out = torch.empty((1, c.T, c.N, c.n_t), device="cuda")
+    plain = torch.empty_like(out)
+
+    def batched():
+        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R)
+
+    po = dict(c.o, flags=FLAG_NO_MFMA)
+
+    def loop():
+        for t in range(c.T):
+            _lib.rf_into(plain[:, t:t + 1], w["probe"], w["medium"], po, w["delays"][t:t + 1],
+                         w["apod"][t:t + 1], c.x, None, c.z, c.R)
+
+    b_ms = _median_ms(batched, steps)
+    p_ms = _median_ms(loop, 1)
+    return dict(workload=c.name, n_tx=c.T, n_elements=c.N, n_scatterers=c.S, n_bins=c.g["n_bins"],
+                batched_ms=b_ms, plain_ms=p_ms, speedup_vs_plain=p_ms / b_ms,
+                evals_per_s=c.evals() / (b_ms * 1e-3), rf_frames_per_s=c.T / (b_ms * 1e-3),
+                rel_l2_batched_vs_plain=_rel(out, plain))
+
+
 def extra_two_d(steps: int, ms_3d: float) -> dict:
     """The main workload in 2-D acoustics: no elevation term, 1/sqrt(r)
     spreading (Section V)."""
@@ -390,6 +419,7 @@ def main():
             "uneven_phantoms": extra_uneven_phantoms(args.extra_steps),
             "forward_adjoint": extra_forward_adjoint(args.extra_steps),
             "two_d": extra_two_d(args.extra_steps, ms_per_step),
+            "large_t": extra_large_t(args.extra_steps),
         }
     if not args.no_cpu_baseline:
         x, y, z, R = c.host

@@ -36,6 +36,15 @@ def convex_probe(n_elements: int = 128) -> dict:
                 baffle=0, zeta=1.75)
 
 
+def phased_probe(n_elements: int = 64) -> dict:
+    """Phased array (cardiac, cf. Figs. 9 and 12): pitch 0.3 mm, width
+    0.25 mm, height 14 mm, elevation focus 60 mm, fc 2.7 MHz, 74 %
+    bandwidth."""
+    return dict(n_elements=n_elements, fc=2.7e6, pitch=0.3 * MM, width=0.25 * MM,
+                height=14 * MM, elev_focus=60 * MM, bandwidth=0.74, radius=0.0,
+                baffle=0, zeta=1.75)
+
+
 def element_centres(probe: dict) -> np.ndarray:
     """Element centres (x, z) [N, 2]; convex: apex at the origin, centre of
     curvature at (0, -R), chord pitch."""
@@ -67,6 +76,18 @@ def diverging_wave_delays(probe: dict, xv_list, zv: float, c: float = 1540.0) ->
     for xv in np.atleast_1d(xv_list):
         d = np.hypot(ec[:, 0] - xv, ec[:, 1] - zv) / c
         out.append(d - d.min())
+    return np.asarray(out, dtype=np.float64)
+
+
+def focused_delays(probe: dict, angles_deg, depth: float, c: float = 1540.0) -> np.ndarray:
+    """Focused transmits steered to angles_deg at `depth` from the array
+    centre: delays [T, N], min delay 0."""
+    ec = element_centres(probe)
+    out = []
+    for a in np.atleast_1d(angles_deg):
+        fx, fz = depth * math.sin(math.radians(a)), depth * math.cos(math.radians(a))
+        d = np.hypot(ec[:, 0] - fx, ec[:, 1] - fz) / c
+        out.append(d.max() - d)
     return np.asarray(out, dtype=np.float64)
 
 
@@ -140,6 +161,15 @@ def workload(name: str, seed: int = 0, scale: float = 1.0) -> dict:
         dl = diverging_wave_delays(probe, np.linspace(-30 * MM, 30 * MM, 11), -60 * MM)
         n_t = depth_samples(120 * MM, 4 * probe["fc"])
         return _common(probe, dl, phs, 0.5, n_t, name)
+    if name == "ph64x128_s40k":
+        # 64-element 2.7 MHz phased array, 128 focused transmits steered over
+        # -45..45 degrees (focus 60 mm), 40,000 scatterers in a 90-degree
+        # sector to 120 mm (the shape of Fig. 12's sequence).
+        probe = phased_probe(64)
+        ph = sector_phantom(rng, S(40_000), 0.0, 120 * MM, 45.0, depth_min=5 * MM)
+        dl = focused_delays(probe, np.linspace(-45, 45, 128), 60 * MM)
+        n_t = depth_samples(120 * MM, 4 * probe["fc"])
+        return _common(probe, dl, [ph], 0.5, n_t, name)
     if name == "pw128x5_s100k":
         # 5 plane waves (-8, -4, 0, 4, 8 degrees), 100,000 scatterers.
         probe = linear_probe(128)
@@ -170,4 +200,5 @@ def perturbed(ph: dict, seed: int = 1, sigma_pos: float = 50e-6, sigma_R: float 
                 R=f(ph["R"] + rng.normal(0, sigma_R, n)))
 
 
-WORKLOADS = ["pw32_s200", "pw128_s50k", "pw128x21_s200k", "cvx128x11_p16", "pw128x5_s100k"]
+WORKLOADS = ["pw32_s200", "pw128_s50k", "pw128x21_s200k", "cvx128x11_p16", "pw128x5_s100k",
+             "ph64x128_s40k"]

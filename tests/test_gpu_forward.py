@@ -224,3 +224,28 @@ def test_many_transmits_full_size_sampled_bins(S, orc):
     got = spec[0][:, :, bins - g["j_lo"]]
     print("pw128x21_s200k sampled bins rel L2", rel_l2(got, ref))
     assert rel_l2(got, ref) <= TOL
+
+
+def test_large_t_focused_small_full_rf(S, orc):
+    """Phased array, 128 focused transmits (four transmit groups on the
+    matrix cores), 20 scatterers: full RF against the oracle."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("ph64x128_s40k", scale=0.0005)
+    g, rf, data = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    print("128 tx, 20 scatterers rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
+def test_large_t_focused_full_size_sampled_bins(S, orc):
+    """The 128-transmit, 40,000-scatterer sequence in the benchmark's launch
+    configuration: sampled bins against the oracle."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("ph64x128_s40k")
+    g, spec, data = _run(S, w, spectrum=True)
+    bins = sample_bins(g, 3)
+    x, y, z, R, off = data
+    ref = orc.spectrum(oracle_setup(orc, w), g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
+    got = spec[0][:, :, bins - g["j_lo"]]
+    print("ph64x128_s40k sampled bins rel L2", rel_l2(got, ref))
+    assert rel_l2(got, ref) <= TOL
