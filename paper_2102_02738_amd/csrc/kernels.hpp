@@ -90,6 +90,8 @@ struct SynthConfig {
     bool persistent;
     bool pair;   // nu = 2: element sums of lane pairs, one float accumulator per lane
     bool mfma;   // transmit contraction on the matrix cores (synth_mfma.hip)
+    int ne;      // matrix-core path: element slots (64 or 128)
+    int nx;      // matrix-core path: receive sums per column tile (2 or 3)
     int grid;    // blocks launched (persistent: resident blocks)
 };
 

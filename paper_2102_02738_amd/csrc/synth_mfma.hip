@@ -41,12 +41,11 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int NTP, int JT, int NUV, int NX, bool HASY, bool TABLE, bool PERSIST>
+template <int NE, int NTP, int JT, int NUV, int NX, bool HASY, bool TABLE>
 __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 {
     constexpr int NB = 512;
-    constexpr int NE = 128;                 // element slots
-    constexpr int MS = NE * NUV;            // sub-element slots
+    constexpr int MS = NE * NUV;            // sub-element slots (NE: element slots)
     constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int NSG = NB / MS;            // scatterer groups
@@ -56,6 +55,11 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     constexpr int KW = NE / KP;             // elements per wave
     constexpr int KS = KW / 4;              // transmit-GEMM k-steps per wave
     constexpr int WS = NE + 1;              // row stride of the staged weights
+    constexpr int RXE = NE / 16;            // receive element tiles
+    constexpr int CS = 8 / RXE;             // waves per element tile (column split)
+    constexpr int CPW = NTP / CS;           // receive column tiles per wave
+    static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
+    static_assert(CPW * CS == NTP && KP * NTP == 8, "waves must cover the GEMMs");
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(NX == 2 || NX == 3, "receive sums: (Re, Im) or three products");
     static_assert(PPT * NSG == SCH, "synthesis threads must cover the chunk");
@@ -76,8 +80,9 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     const SubFrame fr = load_frame(A.sub, active ? n : 0);
     // transmit-GEMM role
     const int ct = wave % NTP, kp = wave / NTP;
-    // receive-GEMM role
-    const int mt_e = wave * 16;
+    // receive-GEMM role: element tile, and the first of its CPW column tiles
+    const int mt_e = (wave % RXE) * 16;
+    const int rc0 = (wave / RXE) * CPW;
     const bool re_live = mt_e < A.N;
 
     DeltaParams P{};
@@ -86,15 +91,12 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
         P = *A.dpar;
     }
 
-    // Static launch: one item per block.  Persistent launch: blocks draw
-    // items from a work counter until it passes n_items (every block exits).
+    // Persistent launch: blocks draw items from a work counter until it passes
+    // n_items (every block exits).
     __shared__ int s_item;
-    int item = blockIdx.x;
-    if (PERSIST) {
-        if (tid == 0) s_item = atomicAdd(A.ticket, 1);
-        __syncthreads();
-        item = s_item;
-    }
+    if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+    __syncthreads();
+    int item = s_item;
     while (item < A.n_items) {
         const Item it = A.items[item];
         const int bt = it.tile & 0xffff, tg = it.tile >> 16;
@@ -102,12 +104,13 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
         const int nb = min(JT, A.n_bins - jb0);
         const int t0 = tg * TPG;
 
-        // receive sums [bin][column tile]: (Re, Im), or the three products
-        floatx4 X[JT][NTP][NX];
+        // receive sums [bin][column tile of the wave]: (Re, Im), or the three
+        // products
+        floatx4 X[JT][CPW][NX];
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
-            for (int c = 0; c < NTP; ++c)
+            for (int c = 0; c < CPW; ++c)
 #pragma unroll
                 for (int q = 0; q < NX; ++q) X[jj][c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 //    the synthesis, which hides the loads' latency; with 32 the
                 //    registers are short and they are stored at once.
                 constexpr int NW = TPG * NE / NB;
-                constexpr bool HOIST = NTP == 1;
+                constexpr bool HOIST = NW <= 4;
                 auto w_at = [&](int idx) {
                     const int t = idx / NE, e = idx % NE;
                     const int tt = min(t0 + t, A.n_tx - 1), ee = min(e, A.N - 1);
@@ -228,8 +231,8 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 }
                 __syncthreads();
                 // 3. sum the shares (fixed order), combine, scale by R_s
-                if (tid < SCH * TPG) {
-                    const int s = tid / TPG, t = tid % TPG;
+                for (int idx = tid; idx < SCH * TPG; idx += NB) {
+                    const int s = idx / TPG, t = idx % TPG;
                     const int c = t >> 4, d = s * 16 + (t & 15);
                     float q1 = 0.f, q2 = 0.f, q3 = 0.f;
 #pragma unroll
@@ -243,20 +246,20 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 }
                 __syncthreads();
                 // 4. receive GEMM: X[e][t] += sum_s B[e][s] c[s][t], rows
-                //    e = mt_e + gi, k = scatterer 4 k + gk
+                //    e = mt_e + gi, columns of tiles rc0 ..., k = scatterer 4 k + gk
                 if (re_live) {
-                    float2 ba[SCH / 4], ca[SCH / 4][NTP];
+                    float2 ba[SCH / 4], ca[SCH / 4][CPW];
 #pragma unroll
                     for (int k = 0; k < SCH / 4; ++k) {
                         const int s = 4 * k + gk;
                         ba[k] = sB[s * BST + mt_e + gi];
 #pragma unroll
-                        for (int c = 0; c < NTP; ++c) ca[k][c] = s_c[s][c * 16 + gi];
+                        for (int c = 0; c < CPW; ++c) ca[k][c] = s_c[s][(rc0 + c) * 16 + gi];
                     }
 #pragma unroll
                     for (int k = 0; k < SCH / 4; ++k)
 #pragma unroll
-                        for (int c = 0; c < NTP; ++c) {
+                        for (int c = 0; c < CPW; ++c) {
                             if (NX == 3) {
                                 X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
                                 X[jj][c][1] = mfma4(ba[k].y, ca[k][c].y, X[jj][c][1]);
@@ -274,24 +277,23 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
             }
         }
         // per-element partials [item][JT][TPG][N]; D[row][col]: row = element
-        // mt_e + 4 (lane / 16) + v, col = transmit c 16 + lane % 16
+        // mt_e + 4 (lane / 16) + v, col = transmit (rc0 + c) 16 + lane % 16
         if (re_live) {
             float2* out = A.part + (int64_t)item * JT * TPG * A.N;
 #pragma unroll
             for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
-                for (int c = 0; c < NTP; ++c)
+                for (int c = 0; c < CPW; ++c)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int e = mt_e + 4 * gk + v;
-                        const int t = c * 16 + gi;
+                        const int t = (rc0 + c) * 16 + gi;
                         const float x1 = X[jj][c][0][v], x2 = X[jj][c][1][v], x3 = X[jj][c][NX - 1][v];
                         const float2 xv = NX == 3 ? make_float2(x1 - x2, x3 - x1 - x2) : make_float2(x1, x2);
                         if (e < A.N && jj < nb) out[((int64_t)jj * TPG + t) * A.N + e] = xv;
                     }
         }
 
-        if (!PERSIST) break;
         __syncthreads();
         if (tid == 0) s_item = atomicAdd(A.ticket, 1);
         __syncthreads();
@@ -299,26 +301,36 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     }
 }
 
-// Bins per item and receive sums per lane (4 NX JT NTP floats): 16 transmit
-// columns take 4 bins with the three-product sums, 32 columns take 4 bins
-// with (Re, Im) sums, which fit the register file.
-constexpr int mt_jt(int ntp) { return 4; }
-constexpr int mt_nx(int ntp) { return ntp == 1 ? 3 : 2; }
+// Shape of a group: element slots NE (64 or 128) and 16-transmit column
+// tiles NTP; bins per item JT and receive sums NX are chosen so that the
+// receive sums (4 NX JT NTP / CS floats per lane) fit the register file.
+struct MtShape {
+    int ne, ntp, jt, nx;
+};
 
-template <int NTP, int NUV, bool PERSIST>
-static SynthKernel mt_kernel_p(const SynthConfig& c)
+static MtShape mt_shape(int N, int n_tx)
 {
-    constexpr int JT = mt_jt(NTP), NX = mt_nx(NTP);
-    if (c.jt != JT) return nullptr;
-    if (c.has_y) return k_synth_mt<NTP, JT, NUV, NX, true, false, PERSIST>;
-    if (c.table) return k_synth_mt<NTP, JT, NUV, NX, false, true, PERSIST>;
-    return k_synth_mt<NTP, JT, NUV, NX, false, false, PERSIST>;
+    if (N <= 64) {
+        if (n_tx <= 32) return {64, 2, 4, 3};
+        return {64, 4, 4, 2};
+    }
+    if (n_tx <= 16) return {128, 1, 4, 3};
+    return {128, 2, 4, 2};
 }
 
-template <int NTP, int NUV>
+template <int NE, int NTP, int JT, int NX, int NUV>
 static SynthKernel mt_kernel_nuv(const SynthConfig& c)
 {
-    return c.persistent ? mt_kernel_p<NTP, NUV, true>(c) : mt_kernel_p<NTP, NUV, false>(c);
+    if (c.has_y) return k_synth_mt<NE, NTP, JT, NUV, NX, true, false>;
+    if (c.table) return k_synth_mt<NE, NTP, JT, NUV, NX, false, true>;
+    return k_synth_mt<NE, NTP, JT, NUV, NX, false, false>;
+}
+
+template <int NE, int NTP, int JT, int NX>
+static SynthKernel mt_kernel_shape(const SynthConfig& c)
+{
+    if (c.jt != JT || c.nx != NX) return nullptr;
+    return c.pair ? mt_kernel_nuv<NE, NTP, JT, NX, 2>(c) : mt_kernel_nuv<NE, NTP, JT, NX, 1>(c);
 }
 
 // The matrix-core path serves n_tx >= 4 with N <= 128 elements and nu in {1, 2}.
@@ -330,29 +342,34 @@ bool mt_supported(int M, int N, int n_tx)
 
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
 {
+    const MtShape sh = mt_shape(N, n_tx);
     SynthConfig c{};
     c.bs = 512;
-    c.tt = n_tx > 16 ? 32 : 16;               // transmits per group
-    c.jt = mt_jt(c.tt / 16);
+    c.ne = sh.ne;
+    c.tt = 16 * sh.ntp;                       // transmits per group
+    c.jt = sh.jt;
+    c.nx = sh.nx;
     c.sc = 16;
     c.pair = M == 2 * N;
     c.has_y = has_y;
     c.mfma = true;
+    c.persistent = true;
     return c;
 }
 
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
-    const int ntp = c.tt / 16;
-    if (ntp == 1) return c.pair ? mt_kernel_nuv<1, 2>(c) : mt_kernel_nuv<1, 1>(c);
-    if (ntp == 2) return c.pair ? mt_kernel_nuv<2, 2>(c) : mt_kernel_nuv<2, 1>(c);
+    if (c.ne == 128 && c.tt == 16) return mt_kernel_shape<128, 1, 4, 3>(c);
+    if (c.ne == 128 && c.tt == 32) return mt_kernel_shape<128, 2, 4, 2>(c);
+    if (c.ne == 64 && c.tt == 32) return mt_kernel_shape<64, 2, 4, 3>(c);
+    if (c.ne == 64 && c.tt == 64) return mt_kernel_shape<64, 4, 4, 2>(c);
     return nullptr;
 }
 
 hipError_t launch_synth_mt(const SynthConfig& c, const SynthArgs& a, hipStream_t st)
 {
     if (c.grid <= 0) return hipSuccess;
-    if (c.persistent != (a.ticket != nullptr)) return hipErrorInvalidValue;
+    if (!c.persistent || !a.ticket) return hipErrorInvalidValue;
     const SynthKernel k = synth_mt_kernel(c);
     if (!k) return hipErrorInvalidValue;
     SynthArgs arg = a;
