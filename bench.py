@@ -203,6 +203,13 @@ def extra_uneven_phantoms(steps: int) -> dict:
         plan.graph_launch_into(out, c.x, None, c.z, c.R)
 
     g_ms = _median_ms(graph, steps)
+    first = out.clone()
+    t0 = time.perf_counter()
+    chosen = plan.autotune(c.x, None, c.z, c.R, c.n_t)
+    tune_s = time.perf_counter() - t0
+    gt_ms = _median_ms(graph, steps)
+    tuned = out.clone()
+    out.copy_(first)
     static = torch.empty_like(out)
     s_ms = _median_ms(lambda: _lib.rf_into(static, w["probe"], w["medium"], c.o, w["delays"],
                                            w["apod"], c.x, None, c.z, c.R, c.off), 1)
@@ -222,9 +229,31 @@ def extra_uneven_phantoms(steps: int) -> dict:
     return dict(workload=c.name, n_phantoms=c.P, n_tx=c.T, n_scatterers=c.S,
                 scatterers_min=int(min(off[1:] - off[:-1])), scatterers_max=int(max(off[1:] - off[:-1])),
                 graph_ms=g_ms, batched_static_call_ms=s_ms, plain_ms=p_ms,
-                speedup_vs_plain=p_ms / g_ms, evals_per_s=c.evals() / (g_ms * 1e-3),
-                rf_frames_per_s=c.P * c.T / (g_ms * 1e-3),
+                speedup_vs_plain=p_ms / min(g_ms, gt_ms), evals_per_s=c.evals() / (min(g_ms, gt_ms) * 1e-3),
+                rf_frames_per_s=c.P * c.T / (min(g_ms, gt_ms) * 1e-3),
+                autotune=dict(chosen=chosen, tuning_s=tune_s, graph_ms_default=g_ms,
+                              graph_ms_autotuned=gt_ms, rel_l2_autotuned_vs_plain=_rel(tuned, plain)),
                 rel_l2_graph_vs_plain=_rel(out, plain), graph_equals_static=bool(torch.equal(out, static)))
+
+
+def extra_autotune(steps: int, name: str) -> dict:
+    """A plan for the workload with the default launch shape against the
+    same plan after simus_rf_plan_autotune."""
+    import torch
+    from paper_2102_02738_amd import rf_plan
+    c = Case(name)
+    w = c.w
+    plan = rf_plan(w["probe"], w["medium"], c.o, w["delays"], w["apod"], offsets=c.off)
+    out = torch.empty((c.P, c.T, c.N, c.n_t), device="cuda")
+    d_ms = _median_ms(lambda: plan.execute_into(out, c.x, None, c.z, c.R), steps)
+    first = out.clone()
+    t0 = time.perf_counter()
+    chosen = plan.autotune(c.x, None, c.z, c.R, c.n_t)
+    tune_s = time.perf_counter() - t0
+    t_ms = _median_ms(lambda: plan.execute_into(out, c.x, None, c.z, c.R), steps)
+    plan.close()
+    return dict(workload=name, chosen=chosen, tuning_s=tune_s, default_ms=d_ms, autotuned_ms=t_ms,
+                gain=d_ms / t_ms, rel_l2_autotuned_vs_default=_rel(out, first))
 
 
 def extra_forward_adjoint(steps: int) -> dict:
@@ -415,6 +444,7 @@ def main():
     }
     if not args.no_extras:
         res["extras"] = {
+            "autotune": extra_autotune(max(args.extra_steps, 5), c.name),
             "batched_transmits": extra_batched_transmits(args.extra_steps),
             "uneven_phantoms": extra_uneven_phantoms(args.extra_steps),
             "forward_adjoint": extra_forward_adjoint(args.extra_steps),

@@ -98,8 +98,10 @@ typedef struct {
                              every other entry point requires nfft > 0 */
     int32_t n_t;          /* RF samples returned per channel; 0 = nfft; <= nfft */
     int32_t flags;        /* SIMUS_FLAG_* */
-    int32_t tile_bins;    /* 0 = autotuned; else bins per work item (1..32) */
-    int32_t tile_scat;    /* 0 = autotuned; else scatterers per work item */
+    int32_t tile_bins;    /* reserved: checked to lie in [0, 32], otherwise unused
+                             (bins per work item are fixed by the kernel shape) */
+    int32_t tile_scat;    /* scatterers per work item; 0 = a default from the
+                             problem size (simus_rf_plan_autotune measures) */
 } simus_options;
 
 #define SIMUS_FLAG_NO_MFMA       1   /* never use the MFMA multi-transmit contraction */
@@ -235,6 +237,22 @@ int simus_rf_plan_execute(simus_rf_plan plan, const float* x, const float* y,
 int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* y,
                                const float* z, const float* refl, float* rf,
                                void* hip_stream);
+
+/* Autotuner of a plan's launch shape.  Times the plan's kernels (HIP events
+ * on hip_stream) on the given scatterers, laid out as for
+ * simus_rf_plan_execute, for scatterers per work item from 0.5x to 2x the
+ * default and, on the vector path, with and without the persistent launch
+ * (a warm-up run each, then the mean of three runs, or one run when a run
+ * takes over 50 ms);
+ * keeps the fastest configuration in the plan (later executions and graph
+ * launches use it; a captured graph is dropped) and returns its
+ * options.tile_scat and options.flags in *tile_scat and *flags (either may
+ * be NULL).  Waits for hip_stream; rf is overwritten; the plan's workspace
+ * may be reallocated.  The results do not depend on the choice beyond
+ * rounding order. */
+int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y,
+                           const float* z, const float* refl, float* rf, void* hip_stream,
+                           int64_t* tile_scat, int32_t* flags);
 
 /* Waits for the device, then frees the plan's graph, stream and workspace.
  * NULL is ignored. */

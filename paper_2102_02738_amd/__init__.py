@@ -121,6 +121,14 @@ class RFPlan(_lib.RFPlan):
         (self.graph_launch_into if graph else self.execute_into)(out, x, y, z, refl, stream)
         return out
 
+    def autotune(self, x, y, z, refl, n_t, stream=None) -> dict:
+        """Times launch shapes on these scatterers and keeps the fastest in the
+        plan; returns the chosen options (tile_scat, flags)."""
+        import torch
+        out = torch.empty((self.n_phantoms, self.n_tx, self.n_elements, n_t), dtype=torch.float32,
+                          device=x.device)
+        return self.autotune_into(out, x, y, z, refl, stream)
+
 
 def rf_plan(probe, medium, options, delays, apod, n_scat=None, offsets=None, has_y=False,
             stream=None) -> RFPlan:

@@ -25,7 +25,7 @@ FLAG_2D = 8
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",
            "simus_spectrum_to_rf", "simus_rf_backward", "simus_pfield_nf", "simus_pfield",
            "simus_rf_plan_create", "simus_rf_plan_execute", "simus_rf_plan_graph_launch",
-           "simus_rf_plan_destroy", "simus_release_workspace", "simus_profile_enable",
+           "simus_rf_plan_autotune", "simus_rf_plan_destroy", "simus_release_workspace", "simus_profile_enable",
            "simus_profile_read", "simus_profile_reset"]
 
 
@@ -90,6 +90,7 @@ def lib():
                                                P(C.c_void_p)]),
             "simus_rf_plan_execute": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "simus_rf_plan_graph_launch": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "simus_rf_plan_autotune": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pi64, pi32]),
             "simus_rf_plan_destroy": (None, [vp]),
             "simus_release_workspace": (None, []),
             "simus_profile_enable": (C.c_int, [C.c_int]),
@@ -271,6 +272,15 @@ class RFPlan:
     def graph_launch_into(self, rf, x, y, z, refl, stream=None):
         check(lib().simus_rf_plan_graph_launch(self._handle(), _dev(x), _dev(y), _dev(z),
                                                _dev(refl), _dev(rf), _stream(stream)))
+
+    def autotune_into(self, rf, x, y, z, refl, stream=None) -> dict:
+        """Runs the plan's autotuner on these scatterers; returns the chosen
+        options (tile_scat, flags)."""
+        ts = C.c_int64()
+        fl = C.c_int32()
+        check(lib().simus_rf_plan_autotune(self._handle(), _dev(x), _dev(y), _dev(z), _dev(refl),
+                                           _dev(rf), _stream(stream), C.byref(ts), C.byref(fl)))
+        return dict(tile_scat=int(ts.value), flags=int(fl.value))
 
     def _handle(self):
         if not self._h:

@@ -781,8 +781,12 @@ using namespace simus;
 // and the graph captured for the last pointer set.
 struct simus_rf_plan_s {
     FwdPlan F;
+    simus_options opt{};          // as created (the autotuner changes tile_scat, flags)
+    std::vector<double> delays;   // host copies, for rebuilding the plan
+    std::vector<float> apod;
     int device = 0;
     char* dev = nullptr;
+    size_t dev_cap = 0;
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
     const void* key[5] = {};
@@ -929,12 +933,16 @@ int simus_rf_plan_create(const simus_probe* probe, const simus_medium* medium,
         Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, has_y != 0);
         std::unique_ptr<simus_rf_plan_s> pl(new simus_rf_plan_s);
         pl->F = make_fwd_plan(std::move(C), opt, delays, apod, true);
+        pl->opt = *opt;
+        pl->delays.assign(delays, delays + size_t(n_tx) * pl->F.C.P.N);
+        if (apod) pl->apod.assign(apod, apod + size_t(n_tx) * pl->F.C.P.N);
         hip_check(hipGetDevice(&pl->device), "hipGetDevice");
         if (hipMalloc(&pl->dev, pl->F.dv_size) != hipSuccess) {
             pl->dev = nullptr;
             (void)hipGetLastError();
             throw Error{SIMUS_ENOMEM, "plan workspace allocation failed"};
         }
+        pl->dev_cap = pl->F.dv_size;
         const hipStream_t st = static_cast<hipStream_t>(hip_stream);
         hip_check(hipMemcpyAsync(pl->dev, pl->F.host.data(), pl->F.up_size, hipMemcpyHostToDevice, st),
                   "hipMemcpyAsync");
@@ -992,6 +1000,95 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
             std::copy(key, key + 5, plan->key);
         }
         hip_check(timed(K_GRAPH, st, [&] { return hipGraphLaunch(plan->exec, st); }), "hipGraphLaunch");
+    });
+}
+
+int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, const float* z,
+                           const float* refl, float* rf, void* hip_stream, int64_t* tile_scat,
+                           int32_t* flags)
+{
+    return guarded([&] {
+        check_plan_call(plan, x, y, z, refl, rf);
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        std::lock_guard<std::mutex> lk(plan->mu);
+        const double* dl = plan->delays.data();
+        const float* ap = plan->apod.empty() ? nullptr : plan->apod.data();
+        // rebuilds the plan for options o, growing the workspace if needed, and
+        // uploads its tables (waits for the stream)
+        auto rebuild = [&](const simus_options& o) {
+            FwdPlan F = make_fwd_plan(Common(plan->F.C), &o, dl, ap, true);
+            if (F.dv_size > plan->dev_cap) {
+                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                hip_check(hipFree(plan->dev), "hipFree");
+                plan->dev = nullptr;
+                plan->dev_cap = 0;
+                if (hipMalloc(&plan->dev, F.dv_size) != hipSuccess) {
+                    plan->dev = nullptr;
+                    (void)hipGetLastError();
+                    throw Error{SIMUS_ENOMEM, "plan workspace allocation failed"};
+                }
+                plan->dev_cap = F.dv_size;
+            }
+            hip_check(hipMemcpyAsync(plan->dev, F.host.data(), F.up_size, hipMemcpyHostToDevice, st),
+                      "hipMemcpyAsync");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            return F;
+        };
+        // candidates: 0.5x .. 2x the default scatterers per item; on the vector
+        // path with and without the persistent launch
+        const int64_t base = plan->F.slice;
+        std::vector<simus_options> cands;
+        for (double m : {0.5, 0.75, 1.0, 1.5, 2.0}) {
+            for (int persist = 0; persist < 2; ++persist) {
+                if (plan->F.use_mt && !persist) continue;   // always persistent there
+                simus_options o = plan->opt;
+                o.tile_scat = std::max<int64_t>(1, (int64_t)std::llround(base * m));
+                o.flags = persist ? (o.flags | SIMUS_FLAG_PERSISTENT) : (o.flags & ~SIMUS_FLAG_PERSISTENT);
+                cands.push_back(o);
+            }
+        }
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        hip_check(hipEventCreate(&ev[0]), "hipEventCreate");
+        hip_check(hipEventCreate(&ev[1]), "hipEventCreate");
+        double best_ms = 0;
+        simus_options best = plan->opt;
+        try {
+            for (size_t c = 0; c < cands.size(); ++c) {
+                const FwdPlan F = rebuild(cands[c]);
+                // a warm-up run, then three timed runs (one when a run takes
+                // over 50 ms)
+                float ms = 0.f;
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int reps = pass == 0 ? 1 : ms > 50.f ? 1 : 3;
+                    hip_check(hipEventRecord(ev[0], st), "hipEventRecord");
+                    for (int r = 0; r < reps; ++r)
+                        enqueue_fwd(F, plan->dev, x, y, z, refl, nullptr, rf, st);
+                    hip_check(hipEventRecord(ev[1], st), "hipEventRecord");
+                    hip_check(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+                    hip_check(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+                    ms /= reps;
+                }
+                if (c == 0 || ms < best_ms) {
+                    best_ms = ms;
+                    best = cands[c];
+                    best.tile_scat = F.slice;
+                }
+            }
+        } catch (...) {
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            throw;
+        }
+        hip_check(hipEventDestroy(ev[0]), "hipEventDestroy");
+        hip_check(hipEventDestroy(ev[1]), "hipEventDestroy");
+        plan->F = rebuild(best);
+        plan->opt = best;
+        if (plan->exec) {
+            hip_check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
+            plan->exec = nullptr;
+        }
+        if (tile_scat) *tile_scat = best.tile_scat;
+        if (flags) *flags = best.flags;
     });
 }
 

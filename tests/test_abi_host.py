@@ -192,6 +192,7 @@ def test_plan_entry_points_validate_before_gpu(L):
     fake = C.c_void_p(0x1000)
     assert lib.simus_rf_plan_execute(None, fake, None, fake, fake, fake, None) == -1
     assert lib.simus_rf_plan_graph_launch(None, fake, None, fake, fake, fake, None) == -1
+    assert lib.simus_rf_plan_autotune(None, fake, None, fake, fake, fake, None, None, None) == -1
     lib.simus_rf_plan_destroy(None)
 
 

@@ -192,11 +192,14 @@ def test_empty_and_degenerate(S):
 
 @pytest.mark.parametrize("n_tx,n_el,nu,with_y,no_mfma", [
     (21, 32, 0, False, False), (33, 32, 0, False, False), (6, 32, 0, True, False),
-    (12, 64, 1, False, False), (5, 200, 1, False, False), (21, 32, 0, False, True)])
+    (12, 64, 1, False, False), (5, 200, 1, False, False), (21, 32, 0, False, True),
+    (11, 100, 0, False, False), (40, 128, 0, False, False), (70, 48, 1, False, False)])
 def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
     """Many steered plane waves: the transmit contraction on the matrix cores
-    (or, with the flag, on the VALU path) matches the oracle; covers two
-    transmit groups with a ragged last one, y != 0, nu = 1 and 200 elements."""
+    (or, with the flag, on the VALU path) matches the oracle; covers every
+    matrix-core shape (64 and 128 element slots, 16 to 64 transmit columns),
+    several transmit groups with a ragged last one, y != 0, nu = 1 and 200
+    elements (vector path)."""
     from paper_2102_02738_amd import inputs
     w = inputs.workload("pw32_s200", scale=0.3)
     w["probe"] = inputs.linear_probe(n_el)

@@ -130,3 +130,32 @@ def test_plan_with_y_and_argument_checks(S):
     plan.close()
     with pytest.raises(S.SimusError):
         plan.rf(dx, dy, dz, dR, g["n_t"])
+
+
+@pytest.mark.parametrize("path", ["valu", "mfma"])
+def test_autotune_keeps_results(S, path):
+    """The autotuned plan gives simus_rf's results for the options it chose,
+    bit for bit (execution and graph), and matches the default options to
+    rounding order."""
+    import torch
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw128_s50k", scale=0.1) if path == "valu" else _convex_uneven(7)
+    g, o, (dx, dy, dz, dR), (_, _, _, _, off) = _prep(S, w)
+    plan = S.rf_plan(w["probe"], w["medium"], o, w["delays"], w["apod"], offsets=off)
+    first = plan.rf(dx, None, dz, dR, g["n_t"], graph=True)
+    ch = plan.autotune(dx, None, dz, dR, g["n_t"])
+    print(path, "chosen", ch)
+    assert ch["tile_scat"] > 0
+    if path == "mfma":
+        assert ch["flags"] & S.FLAG_PERSISTENT
+    ref = S.rf(w["probe"], w["medium"], dict(o, **ch), w["delays"], w["apod"], dx, None, dz, dR,
+               offsets=off)
+    got = plan.rf(dx, None, dz, dR, g["n_t"])
+    gr = plan.rf(dx, None, dz, dR, g["n_t"], graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert torch.equal(gr, ref)
+    e = rel_l2(got.cpu().numpy(), first.cpu().numpy())
+    print(path, "rel L2 vs default shape", e)
+    assert e <= 1e-5
+    plan.close()
