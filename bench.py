@@ -354,7 +354,7 @@ def extra_two_d(steps: int, ms_3d: float) -> dict:
     per_g = SYNTH2D_VALU_PER_G + TRANS_ISSUE_COST * SYNTH2D_TRANS_PER_G
     achieved = g_terms * per_g / (synth_ms * 1e-3)
     return dict(workload=c.name + " (2-D)", ms_per_call=ms, evals_per_s=c.evals() / (ms * 1e-3),
-                speedup_vs_3d=ms_3d / ms, synth_kernel_ms=synth_ms,
+                speedup_vs_3d=ms_3d / ms if ms_3d == ms_3d else None, synth_kernel_ms=synth_ms,
                 roofline=dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12,
                               unit="TOP/s", frac=achieved / VALU_PEAK,
                               kernel="k_synth<256, 8, 16, 1, false, 2, true>", ops_per_unit=per_g))
@@ -369,6 +369,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=2)
+    ap.add_argument("--only-extra", default="",
+                    help="run only this extra measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -393,6 +395,17 @@ def main():
         return
 
     from paper_2102_02738_amd import _lib
+
+    if args.only_extra:
+        fns = {"autotune": lambda k: extra_autotune(max(k, 5), "pw128_s50k"),
+               "batched_transmits": extra_batched_transmits, "uneven_phantoms": extra_uneven_phantoms,
+               "forward_adjoint": extra_forward_adjoint, "large_t": extra_large_t,
+               "two_d": lambda k: extra_two_d(k, float("nan"))}
+        if args.only_extra not in fns:
+            print(f"unknown extra {args.only_extra!r}; one of {sorted(fns)}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({args.only_extra: fns[args.only_extra](args.extra_steps)}))
+        return
 
     c = Case("pw128_s50k")
     w = c.w
