@@ -230,8 +230,8 @@ def test_many_transmits_full_size_sampled_bins(S, orc):
 
 
 def test_large_t_focused_small_full_rf(S, orc):
-    """Phased array, 128 focused transmits (four transmit groups on the
-    matrix cores), 20 scatterers: full RF against the oracle."""
+    """Phased array, 128 focused transmits (two groups of 64 transmit
+    columns on the matrix cores), 20 scatterers: full RF against the oracle."""
     from paper_2102_02738_amd import inputs
     w = inputs.workload("ph64x128_s40k", scale=0.0005)
     g, rf, data = _run(S, w)
