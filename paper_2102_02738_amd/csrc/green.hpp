@@ -49,9 +49,8 @@ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c)
     return c;
 }
 
-// sin(x)/x for the set-up: Taylor series to x^12 for |x| < 1 (remainder
-// below 2e-10), hardware sine above.
-__device__ __forceinline__ float sinc_setup(float x)
+// sin(x)/x by its Taylor series to x^12, for |x| < 1 (remainder below 2e-10).
+__device__ __forceinline__ float sinc_taylor(float x)
 {
     const float x2 = x * x;
     float p = fmaf(x2, 1.6059043836821613e-10f, -2.5052108385441720e-08f);
@@ -59,8 +58,13 @@ __device__ __forceinline__ float sinc_setup(float x)
     p = fmaf(x2, p, -1.9841269841269841e-04f);
     p = fmaf(x2, p, 8.3333333333333333e-03f);
     p = fmaf(x2, p, -1.6666666666666667e-01f);
-    p = fmaf(x2, p, 1.0f);
-    if (fabsf(x) < 1.f) return p;
+    return fmaf(x2, p, 1.0f);
+}
+
+// sin(x)/x for the set-up: the Taylor series for |x| < 1, hardware sine above.
+__device__ __forceinline__ float sinc_setup(float x)
+{
+    if (fabsf(x) < 1.f) return sinc_taylor(x);
     return sin_turns(x * 0.15915494309189535f) * rcp_fast(x);
 }
 
@@ -129,8 +133,10 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     const double r0 = (double)(r2f * inv_r0);
     const double r = fma(fma(-r0, r0, r2s), 0.5 * (double)inv_r0, r0);
     const float rf = (float)r;
-    const float rho = HASY ? sqrtf(xl * xl + zl * zl) : rf;
-    const float inv_rho = ok ? rcp_fast(rho) : 0.f;
+    // 1/r: the FP32 reciprocal root above (about 1 ulp, as a division);
+    // 1/rho, the in-plane distance, the same without y
+    const float inv_r = inv_r0;
+    const float inv_rho = ok ? (HASY ? rsq_fast(xl * xl + zl * zl) : inv_r) : 0.f;
     const float st = xl * inv_rho;
     const float ct = ok ? zl * inv_rho : 1.f;
     float obl = ct, dobl = 1.f;                            // soft baffle
@@ -142,7 +148,6 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
         obl = ct * den;
         dobl = K.zeta * den * den;
     }
-    const float inv_r = rcp_fast(rf);
     // amplitude 1/r, or 1/sqrt(r) in 2-D (Eqs. 36-38)
     const float amp = ok ? obl * (K.dim2 ? rsq_fast(rf) : inv_r) : 0.f;
     const float apow = K.dim2 ? 0.5f : 1.f;
@@ -161,7 +166,9 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     // sinc recurrence, theta = 2 pi sigma, sigma = df b_sub sin(t) / c (turns per bin)
     const float sigma = K.sinc_per_bin * st;
     const float theta = 6.283185307179586f * sigma;
-    const float sh = sinc_setup(0.5f * theta);
+    // sinc(theta / 2): |theta / 2| <= pi sinc_per_bin, below 1 for any
+    // practical probe and grid (a uniform branch)
+    const float sh = K.sinc_per_bin < 0.3f ? sinc_taylor(0.5f * theta) : sinc_setup(0.5f * theta);
     g.s = jf0 * sinc_setup(jf0 * theta);
     g.d = cos_turns((jf0 - 0.5f) * sigma) * sh;
     g.lam = -(theta * sh) * (theta * sh);
@@ -251,7 +258,7 @@ __device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaPara
     const float kf = floorf(u);
     const float t = u - kf;
     const int k = (int)kf;
-    const float4 a = tab[2 * k], b = tab[2 * k + 1];
+    const float4 a = tab[dtab_a(k)], b = tab[dtab_b(k)];
     float re = fmaf(t, b.z, b.x), im = fmaf(t, b.w, b.y);
     re = fmaf(t, re, a.z);
     im = fmaf(t, im, a.w);
@@ -275,8 +282,8 @@ __device__ __forceinline__ DeltaFetch delta_fetch(const float4* tab, const Delta
     const int k = (int)kf;
     DeltaFetch f;
     f.t = u - kf;
-    f.a = tab[2 * k];
-    f.b = tab[2 * k + 1];
+    f.a = tab[dtab_a(k)];
+    f.b = tab[dtab_b(k)];
     return f;
 }
 
@@ -355,7 +362,7 @@ __device__ __forceinline__ float2 delta_table_d(const float4* tab, const DeltaPa
     const float kf = floorf(u);
     const float t = u - kf;
     const int k = (int)kf;
-    const float4 a = tab[2 * k], b = tab[2 * k + 1];
+    const float4 a = tab[dtab_a(k)], b = tab[dtab_b(k)];
     float re = fmaf(t, b.z, b.x), im = fmaf(t, b.w, b.y);
     // derivative in t: c1 + t (2 c2 + 3 t c3)
     float gr = fmaf(3.f * t, b.z, 2.f * b.x), gi = fmaf(3.f * t, b.w, 2.f * b.y);

@@ -133,8 +133,8 @@ __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* p
         if (unit) c[0][i] = c[1][i] = c[2][i] = c[3][i] = 0.f;
     }
     if (unit) c[0][0] = 1.f;
-    tab[2 * k] = make_float4(c[0][0], c[0][1], c[1][0], c[1][1]);
-    tab[2 * k + 1] = make_float4(c[2][0], c[2][1], c[3][0], c[3][1]);
+    tab[dtab_a(k)] = make_float4(c[0][0], c[0][1], c[1][0], c[1][1]);
+    tab[dtab_b(k)] = make_float4(c[2][0], c[2][1], c[3][0], c[3][1]);
     if (k == 0) {
         DeltaParams P;
         P.L = (float)L;
