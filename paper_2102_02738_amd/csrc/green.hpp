@@ -250,14 +250,16 @@ __device__ __forceinline__ float2 elevation(const Gauss4& G, float q, float k, f
 
 // Cubic table of delta(0, r, k) as a function of w = q / (|q| + L):
 // interval k of DELTA_NT holds (c0, c1, c2, c3) complex, delta = c0 + t (c1
-// + t (c2 + t c3)), t in [0, 1).  Stored as two float4 per interval.
+// + t (c2 + t c3)), t in [0, 1).  Stored as two float4 per interval, in two
+// arrays (dtab_a, dtab_b).
 __device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaParams& P, float q)
 {
     const float w = q * rcp_fast(fabsf(q) + P.L);
     const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
-    const float kf = floorf(u);
-    const float t = u - kf;
-    const int k = (int)kf;
+    // u >= 0 after the clamp: the conversion truncates to the interval and
+    // the hardware fraction gives the local coordinate
+    const int k = (int)u;
+    const float t = __builtin_amdgcn_fractf(u);
     const float4 a = tab[dtab_a(k)], b = tab[dtab_b(k)];
     float re = fmaf(t, b.z, b.x), im = fmaf(t, b.w, b.y);
     re = fmaf(t, re, a.z);
@@ -278,10 +280,9 @@ __device__ __forceinline__ DeltaFetch delta_fetch(const float4* tab, const Delta
 {
     const float w = q * rcp_fast(fabsf(q) + P.L);
     const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
-    const float kf = floorf(u);
-    const int k = (int)kf;
+    const int k = (int)u;                  // u >= 0: truncation is the floor
     DeltaFetch f;
-    f.t = u - kf;
+    f.t = __builtin_amdgcn_fractf(u);
     f.a = tab[dtab_a(k)];
     f.b = tab[dtab_b(k)];
     return f;
@@ -359,9 +360,10 @@ __device__ __forceinline__ float2 delta_table_d(const float4* tab, const DeltaPa
     const float den = rcp_fast(fabsf(q) + P.L);
     const float w = q * den;
     const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
-    const float kf = floorf(u);
-    const float t = u - kf;
-    const int k = (int)kf;
+    // u >= 0 after the clamp: the conversion truncates to the interval and
+    // the hardware fraction gives the local coordinate
+    const int k = (int)u;
+    const float t = __builtin_amdgcn_fractf(u);
     const float4 a = tab[dtab_a(k)], b = tab[dtab_b(k)];
     float re = fmaf(t, b.z, b.x), im = fmaf(t, b.w, b.y);
     // derivative in t: c1 + t (2 c2 + 3 t c3)

@@ -70,9 +70,6 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #ifndef SIMUS_SC1
 #define SIMUS_SC1 8
 #endif
-#ifndef SIMUS_RED_PAD
-#define SIMUS_RED_PAD 4
-#endif
 #ifndef SIMUS_JT_MAX
 #define SIMUS_JT_MAX 16
 #endif
@@ -134,7 +131,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 {
     constexpr int NS = SC * TT;            // sums per bin
     constexpr int HB = BS / 2;             // pair sums per row
-    constexpr int RS = HB + SIMUS_RED_PAD; // LDS row stride (float2)
+    constexpr int RS = HB + 4;             // LDS row stride (float2)
     constexpr int GL = (HB / NS >= 64) ? 64 : HB / NS;   // lanes per sum
     constexpr int PER = HB / GL;           // values per lane
     constexpr int NA = PAIR ? 1 : 2;       // floats per accumulator slot

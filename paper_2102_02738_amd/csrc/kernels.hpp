@@ -35,12 +35,11 @@ struct ModelConst {
 
 // Elevation-term table (y = 0): DELTA_NT cubic intervals in w = q / (|q| + L).
 constexpr int DELTA_NT = 512;
-#ifndef SIMUS_DTAB_SOA
-#define SIMUS_DTAB_SOA 0
-#endif
-// float4 index of the first and second halves of interval k's coefficients
-__host__ __device__ constexpr int dtab_a(int k) { return SIMUS_DTAB_SOA ? k : 2 * k; }
-__host__ __device__ constexpr int dtab_b(int k) { return SIMUS_DTAB_SOA ? DELTA_NT + k : 2 * k + 1; }
+// float4 index of the first and second halves of interval k's coefficients:
+// two arrays of DELTA_NT, so that lanes reading neighbouring intervals fall
+// on different LDS banks
+__host__ __device__ constexpr int dtab_a(int k) { return k; }
+__host__ __device__ constexpr int dtab_b(int k) { return DELTA_NT + k; }
 
 struct DeltaParams {
     float L;       // map scale

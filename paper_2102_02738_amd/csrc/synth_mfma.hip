@@ -34,10 +34,6 @@
 
 namespace simus {
 
-#ifndef SIMUS_MT_PAD
-#define SIMUS_MT_PAD 0
-#endif
-
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
@@ -53,15 +49,12 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int NSG = NB / MS;            // scatterer groups
-    constexpr int BST = NE + (SIMUS_MT_PAD ? 18 : 4);   // row stride of the element sums
+    constexpr int BST = NE + 4;             // row stride of the element sums
     constexpr int TPG = 16 * NTP;           // transmit columns of the group
     constexpr int KP = 8 / NTP;             // element shares per column tile
     constexpr int KW = NE / KP;             // elements per wave
     constexpr int KS = KW / 4;              // transmit-GEMM k-steps per wave
-    constexpr int WS = NE + (SIMUS_MT_PAD ? 2 : 1);     // row stride of the staged weights
-    constexpr int CST = TPG + (SIMUS_MT_PAD ? 16 : 0);  // row stride of c
-    constexpr int PST = SIMUS_MT_PAD ? 352 : 256;       // product tile size
-    auto pidx = [](int d) { return SIMUS_MT_PAD ? d + (d >> 6) * 32 : d; };
+    constexpr int WS = NE + 1;              // row stride of the staged weights
     constexpr int RXE = NE / 16;            // receive element tiles
     constexpr int CS = 8 / RXE;             // waves per element tile (column split)
     constexpr int CPW = NTP / CS;           // receive column tiles per wave
@@ -74,8 +67,8 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     __shared__ float4 s_sc[SCH];
     __shared__ float2 s_B[2 * SCH * BST];   // element sums, two buffers
     __shared__ float2 s_W[TPG * WS];
-    __shared__ float s_part[8][3][PST];
-    __shared__ float2 s_c[SCH][CST];
+    __shared__ float s_part[8][3][256];
+    __shared__ float2 s_c[SCH][TPG];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
     const int tid = threadIdx.x;
@@ -230,7 +223,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int d = pidx((4 * gk + v) * 16 + gi);
+                        const int d = (4 * gk + v) * 16 + gi;
                         s_part[wave][0][d] = p1[v];
                         s_part[wave][1][d] = p2[v];
                         s_part[wave][2][d] = p3[v];
@@ -240,7 +233,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 // 3. sum the shares (fixed order), combine, scale by R_s
                 for (int idx = tid; idx < SCH * TPG; idx += NB) {
                     const int s = idx / TPG, t = idx % TPG;
-                    const int c = t >> 4, d = pidx(s * 16 + (t & 15));
+                    const int c = t >> 4, d = s * 16 + (t & 15);
                     float q1 = 0.f, q2 = 0.f, q3 = 0.f;
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {

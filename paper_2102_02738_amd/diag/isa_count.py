@@ -11,7 +11,7 @@ issue at one lane-slot each, transcendentals (sin, cos, exp, log, rcp, rsq,
 sqrt) at four.
 
     python paper_2102_02738_amd/diag/isa_count.py kernels.hip \
-        '_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELb1EEEvNS_9SynthArgsE' --terms 8
+        '_ZN5simus7k_synthILi256ELi8ELi16ELi1ELb0ELi1ELb1EEEvNS_9SynthArgsE' --terms 16
 """
 from __future__ import annotations
 
@@ -77,40 +77,50 @@ def classify(ops: list[str]) -> collections.Counter:
     return c
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("source")
-    ap.add_argument("kernel", help="mangled kernel name")
-    ap.add_argument("--terms", type=int, default=1, help="Green's terms per loop iteration and lane")
-    ap.add_argument("--min", type=int, default=100, help="smallest loop body considered")
-    args = ap.parse_args()
-    s = assembly(args.source)
-    i = s.find(args.kernel + ":")
+def innermost(asm: str, kernel: str, min_ops: int):
+    """Instructions of the kernel's innermost loop (see the module doc)."""
+    i = asm.find(kernel + ":")
     if i < 0:
-        sys.exit(f"kernel {args.kernel} not found in {args.source}")
-    body = s[i:s.index(".Lfunc_end", i)].split("\n")
+        raise KeyError(kernel)
+    body = asm[i:asm.index(".Lfunc_end", i)].split("\n")
     best = None
     for a, b in loops(body):
         ops = [ln.strip().split()[0] for ln in body[a:b + 1]
                if ln.strip() and not ln.strip().startswith((".", ";", "/"))]
-        if len(ops) < args.min:
+        if len(ops) < min_ops:
             continue
-        if best is None or len(ops) < best[2]:
-            best = (a, b, len(ops), ops)
-    if best is None:
-        sys.exit("no loop found")
-    c = classify(best[3])
-    slots = c["valu"] + 4 * c["trans"]
-    print(f"kernel: {args.kernel}")
-    print(f"source: {args.source}")
-    print(f"innermost loop: {best[2]} instructions, {args.terms} Green's terms per iteration and lane")
-    for k in sorted(c):
-        print(f"  {k:8s} {c[k]:5d}  ({c[k] / args.terms:.2f} per term)")
-    print(f"issue slots per term (valu + 4 trans): {slots / args.terms:.2f}")
-    print(f"valu_per_term: {c['valu'] / args.terms:.3f}")
-    print(f"trans_per_term: {c['trans'] / args.terms:.3f}")
-    if c["mfma"]:
-        print(f"mfma_per_term: {c['mfma'] / args.terms:.3f}")
+        if best is None or len(ops) < len(best):
+            best = ops
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("source")
+    ap.add_argument("kernel", nargs="+", help="mangled kernel name(s)")
+    ap.add_argument("--terms", type=int, default=1, help="Green's terms per loop iteration and lane")
+    ap.add_argument("--min", type=int, default=100, help="smallest loop body considered")
+    args = ap.parse_args()
+    s = assembly(args.source)
+    for kernel in args.kernel:
+        try:
+            ops = innermost(s, kernel, args.min)
+        except KeyError:
+            sys.exit(f"kernel {kernel} not found in {args.source}")
+        if ops is None:
+            sys.exit(f"no loop found in {kernel}")
+        c = classify(ops)
+        slots = c["valu"] + 4 * c["trans"]
+        print(f"kernel: {kernel}")
+        print(f"source: {args.source}")
+        print(f"innermost loop: {len(ops)} instructions, {args.terms} Green's terms per iteration and lane")
+        for k in sorted(c):
+            print(f"  {k:8s} {c[k]:5d}  ({c[k] / args.terms:.2f} per term)")
+        print(f"issue slots per term (valu + 4 trans): {slots / args.terms:.2f}")
+        print(f"valu_per_term: {c['valu'] / args.terms:.3f}")
+        print(f"trans_per_term: {c['trans'] / args.terms:.3f}")
+        if c["mfma"]:
+            print(f"mfma_per_term: {c['mfma'] / args.terms:.3f}")
 
 
 if __name__ == "__main__":
