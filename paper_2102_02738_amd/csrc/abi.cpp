@@ -395,7 +395,7 @@ struct FwdPlan {
     int n_bt = 0, n_items = 0;
     int64_t slice = 0;
     CommonLayout L{};
-    size_t o_it = 0, o_pb = 0, o_ns = 0, o_part = 0, o_tk = 0, o_spec = 0;
+    size_t o_it = 0, o_or = 0, o_pb = 0, o_ns = 0, o_part = 0, o_tk = 0, o_spec = 0;
     size_t up_size = 0, dv_size = 0;
     std::vector<char> host;
 };
@@ -448,10 +448,20 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
                 }
     }
     F.n_items = (int)items.size();
+    // draw order: costliest items (scatterers x bins) first, so that the
+    // persistent blocks finish on small items
+    std::vector<int32_t> order(F.n_items);
+    for (int i = 0; i < F.n_items; ++i) order[i] = i;
+    auto cost = [&](int i) {
+        const Item& q = items[i];
+        return int64_t(q.s_end - q.s_begin) * std::min(JT, Cc.B.n_bins - (q.tile & 0xffff) * JT);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
 
     Layout up;
     layout_upload(up, F.L, Cc);
     F.o_it = up.add(sizeof(Item) * std::max(F.n_items, 1));
+    F.o_or = up.add(sizeof(int32_t) * std::max(F.n_items, 1));
     F.o_pb = up.add(sizeof(int32_t) * n_ph);
     F.o_ns = up.add(sizeof(int32_t) * n_ph);
     Layout dv = up;
@@ -466,7 +476,10 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     F.host.assign(up.size, 0);
     char* h = F.host.data();
     fill_upload(h, F.L, Cc, delays, apod);
-    if (F.n_items) std::memcpy(h + F.o_it, items.data(), sizeof(Item) * F.n_items);
+    if (F.n_items) {
+        std::memcpy(h + F.o_it, items.data(), sizeof(Item) * F.n_items);
+        std::memcpy(h + F.o_or, order.data(), sizeof(int32_t) * F.n_items);
+    }
     std::memcpy(h + F.o_pb, pbase.data(), sizeof(int32_t) * n_ph);
     std::memcpy(h + F.o_ns, nsl.data(), sizeof(int32_t) * n_ph);
 
@@ -512,6 +525,7 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     A.sub = sub_geo(d, F.L);
     A.W = at<float2>(d, F.L.W);
     A.items = at<Item>(d, F.o_it);
+    A.order = at<int32_t>(d, F.o_or);
     A.n_items = F.n_items;
     A.part = at<float2>(d, F.o_part);
     A.M = C.P.M;

@@ -221,6 +221,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 
     // Static launch: one item per block.  Persistent launch: blocks draw
     // items from a work counter until it passes n_items (every block exits).
+    // Items are drawn costliest first; an item's partials sit at its id.
     __shared__ int s_item;
     int item = blockIdx.x;
     if (A.ticket) {
@@ -229,7 +230,8 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
         item = s_item;
     }
     while (item < A.n_items) {
-        const Item it = A.items[item];
+        const int id = A.order[item];
+        const Item it = A.items[id];
         const int bt = it.tile & 0xffff, tg = it.tile >> 16;
         const int jb0 = bt * JT;
         const int nb = min(JT, A.n_bins - jb0);
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
             }
             __syncthreads();
         }
-        float* out = reinterpret_cast<float*>(A.part) + (int64_t)item * (JT * TT * BS * NA);
+        float* out = reinterpret_cast<float*>(A.part) + (int64_t)id * (JT * TT * BS * NA);
         for (int i = tid; i < JT * TT * BS * NA; i += BS) out[i] = s_acc[i];
 
         if (!A.ticket) break;
@@ -352,9 +354,12 @@ SynthConfig synth_config(int M, int nu, int n_tx, bool has_y)
     int bs = 64;
     while (bs < M) bs *= 2;
     c.bs = bs;
-    c.tt = n_tx >= 8 ? 8 : n_tx >= 4 ? 4 : n_tx >= 2 ? 2 : 1;
-    if (bs > 512 && c.tt > 4) c.tt = 4;     // LDS: reduction rows + accumulators
-    c.sc = c.tt >= 4 ? 2 : (c.tt == 2 ? 4 : SIMUS_SC1);
+    // Transmits per group: a pair of transmits costs 1.8x a single one here
+    // (fewer scatterers per chunk), so pairs pay for even counts and for 11
+    // or more transmits; wider groups (4, 8: 2 scatterers per chunk, 8 or 4
+    // bins per set-up) measured slower than single transmits.
+    c.tt = n_tx >= 2 && (n_tx % 2 == 0 || n_tx >= 11) ? 2 : 1;
+    c.sc = c.tt == 2 ? 4 : SIMUS_SC1;
     c.pair = nu == 2;
     c.jt = synth_jt(bs, c.tt, c.pair);
     c.has_y = has_y;
@@ -378,10 +383,6 @@ static SynthKernel synth_kernel_bs(const SynthConfig& cfg)
     switch (cfg.tt) {
     case 1: return synth_kernel_y<BS, SIMUS_SC1, 1, PAIR>(cfg);
     case 2: return synth_kernel_y<BS, 4, 2, PAIR>(cfg);
-    case 4: return synth_kernel_y<BS, 2, 4, PAIR>(cfg);
-    case 8:
-        if constexpr (BS <= 512) return synth_kernel_y<BS, 2, 8, PAIR>(cfg);
-        return nullptr;
     default: return nullptr;
     }
 }

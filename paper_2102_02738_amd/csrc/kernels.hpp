@@ -75,6 +75,7 @@ struct SynthArgs {
     SubGeo sub;
     const float2* W;    // [n_bins][n_tx][N] transmit weights W e^{i w tau}
     const Item* items;
+    const int32_t* order; // [n_items] draw order: item ids, costliest first
     int32_t n_items;
     int32_t* ticket;    // persistent launch: work counter (zeroed before launch)
     float2* part;       // [n_items][JT][TT][BS] per-sub-element partial spectra

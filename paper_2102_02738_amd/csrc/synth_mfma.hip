@@ -98,7 +98,8 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     __syncthreads();
     int item = s_item;
     while (item < A.n_items) {
-        const Item it = A.items[item];
+        const int id = A.order[item];          // costliest first
+        const Item it = A.items[id];
         const int bt = it.tile & 0xffff, tg = it.tile >> 16;
         const int jb0 = bt * JT;
         const int nb = min(JT, A.n_bins - jb0);
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
         // per-element partials [item][JT][TPG][N]; D[row][col]: row = element
         // mt_e + 4 (lane / 16) + v, col = transmit (rc0 + c) 16 + lane % 16
         if (re_live) {
-            float2* out = A.part + (int64_t)item * JT * TPG * A.N;
+            float2* out = A.part + (int64_t)id * JT * TPG * A.N;
 #pragma unroll
             for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
