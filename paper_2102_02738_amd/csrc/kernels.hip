@@ -71,7 +71,7 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #define SIMUS_SC1 8
 #endif
 #ifndef SIMUS_JT_MAX
-#define SIMUS_JT_MAX 16
+#define SIMUS_JT_MAX 18
 #endif
 #ifndef SIMUS_WAVES_PER_EU
 #define SIMUS_WAVES_PER_EU 0
@@ -83,8 +83,10 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #endif
 
 // Bins per tile: the receive accumulators (JT TT BS slots of 8 bytes, or
-// of 4 bytes when paired) are kept within 64 KiB (32 KiB paired, which
-// leaves room for three 256-thread blocks per CU).
+// of 4 bytes when paired) are kept within 64 KiB (32 KiB paired).  At most 18
+// bins: a paired 256-thread block then takes 52 KB of LDS (accumulators 18,
+// reduction rows 17, elevation table 16), which keeps three blocks per CU;
+// with 20 bins only two fit.  Longer tiles amortise each pair's set-up.
 constexpr int synth_jt(int bs, int tt, bool pair)
 {
     int jt = SIMUS_JT_MAX;
