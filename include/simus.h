@@ -105,14 +105,19 @@ typedef struct {
 } simus_options;
 
 #define SIMUS_FLAG_NO_MFMA       1   /* never use the MFMA multi-transmit contraction */
-#define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis
-                                        (always used by the matrix-core path) */
+#define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis: the
+                                        default on every path (the flag is accepted and has
+                                        no further effect) */
 #define SIMUS_FLAG_NO_DELTA_TABLE 4  /* evaluate the elevation term directly (no table) */
 #define SIMUS_FLAG_2D            8   /* 2-D acoustics (Section V, Eqs. 35-38): Green's term
                                         exp(i (k + i k_a) r) / sqrt(r) D in the x-z plane, no
                                         elevation term, factor 2b (element width) on the two-way
                                         spectrum and sqrt(2b) on the one-way field; y (Y) must
                                         be NULL */
+#define SIMUS_FLAG_STATIC       16   /* vector path: one block per work item instead of the
+                                        persistent launch (the matrix-core path is always
+                                        persistent); results are bitwise the same */
+/* Other bits of options.flags are rejected with SIMUS_EINVAL. */
 
 /* Frequency grid of one call. */
 typedef struct {
@@ -210,8 +215,8 @@ int simus_pfield(const simus_probe* probe, const simus_medium* medium,
  * the (possibly uneven) phantoms, allocates the plan's own device workspace
  * and uploads its tables on hip_stream, then waits for that upload.
  * has_y: nonzero if executions pass y (y != NULL), zero if y = 0.
- * options->flags apply to every execution (SIMUS_FLAG_PERSISTENT gives one
- * persistent work-queue launch of the synthesis).  *plan is set only on
+ * options->flags apply to every execution (the synthesis is one persistent
+ * work-queue launch unless SIMUS_FLAG_STATIC).  *plan is set only on
  * success.  The workspace is the plan's: executions of one plan must be
  * ordered (e.g. one stream); different plans may run concurrently. */
 typedef struct simus_rf_plan_s* simus_rf_plan;
@@ -241,7 +246,7 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
 /* Autotuner of a plan's launch shape.  Times the plan's kernels (HIP events
  * on hip_stream) on the given scatterers, laid out as for
  * simus_rf_plan_execute, for scatterers per work item from 0.5x to 2x the
- * default and, on the vector path, with and without the persistent launch
+ * default and, on the vector path, with and without SIMUS_FLAG_STATIC
  * (a warm-up run each, then the mean of three runs, or one run when a run
  * takes over 50 ms);
  * keeps the fastest configuration in the plan (later executions and graph

@@ -483,9 +483,10 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     std::memcpy(h + F.o_pb, pbase.data(), sizeof(int32_t) * n_ph);
     std::memcpy(h + F.o_ns, nsl.data(), sizeof(int32_t) * n_ph);
 
-    // the matrix-core path always draws its items from a work counter (one
-    // resident block per CU; measurably faster than a static grid)
-    cfg.persistent = ((opt->flags & SIMUS_FLAG_PERSISTENT) != 0 || F.use_mt) && F.n_items > 0;
+    // resident blocks draw items from a work counter (measurably faster than
+    // a static grid on both paths); SIMUS_FLAG_STATIC asks for one block per
+    // item on the vector path
+    cfg.persistent = (F.use_mt || !(opt->flags & SIMUS_FLAG_STATIC)) && F.n_items > 0;
     if (cfg.persistent) {
         hipDeviceProp_t prop;
         int dev = 0;
@@ -1057,7 +1058,7 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
                 if (plan->F.use_mt && !persist) continue;   // always persistent there
                 simus_options o = plan->opt;
                 o.tile_scat = std::max<int64_t>(1, (int64_t)std::llround(base * m));
-                o.flags = persist ? (o.flags | SIMUS_FLAG_PERSISTENT) : (o.flags & ~SIMUS_FLAG_PERSISTENT);
+                o.flags = persist ? (o.flags & ~SIMUS_FLAG_STATIC) : (o.flags | SIMUS_FLAG_STATIC);
                 cands.push_back(o);
             }
         }

@@ -144,7 +144,7 @@ def test_convex_diverging_waves_uneven_phantoms(S, orc):
     assert np.all(rf[1] == 0)
     print("convex rel L2", rel_l2(rf, ref))
     assert rel_l2(rf, ref) <= TOL
-    g2, rf2, _ = _run(S, w, flags=S.FLAG_PERSISTENT)
+    g2, rf2, _ = _run(S, w, flags=S.FLAG_STATIC)
     assert np.array_equal(rf, rf2)
 
 
@@ -153,9 +153,11 @@ def test_repeatable_and_persistent_bitwise(S):
     w = inputs.workload("pw128_s50k", scale=0.1)
     _, a, _ = _run(S, w)
     _, b, _ = _run(S, w)
-    _, c, _ = _run(S, w, flags=S.FLAG_PERSISTENT)
+    _, c, _ = _run(S, w, flags=S.FLAG_STATIC)
+    _, d, _ = _run(S, w, flags=S.FLAG_PERSISTENT)
     assert np.array_equal(a, b)
     assert np.array_equal(a, c)
+    assert np.array_equal(a, d)
 
 
 def test_inverse_transform_full_size(S, orc):

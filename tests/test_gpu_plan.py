@@ -51,7 +51,7 @@ def test_plan_and_graph_match_rf_bitwise(S, case):
         w = inputs.workload("pw128_s50k", scale=0.1)           # 1 transmit: vector path
     else:
         w = _convex_uneven(7)                                  # 7 transmits: matrix cores
-    g, o, (dx, dy, dz, dR), (x, y, z, R, off) = _prep(S, w, S.FLAG_PERSISTENT if persistent else 0)
+    g, o, (dx, dy, dz, dR), (x, y, z, R, off) = _prep(S, w, 0 if persistent else S.FLAG_STATIC)
     offs = off
     ref = S.rf(w["probe"], w["medium"], dict(o, flags=0), w["delays"], w["apod"], dx, None, dz, dR,
                offsets=offs)
@@ -147,7 +147,7 @@ def test_autotune_keeps_results(S, path):
     print(path, "chosen", ch)
     assert ch["tile_scat"] > 0
     if path == "mfma":
-        assert ch["flags"] & S.FLAG_PERSISTENT
+        assert not ch["flags"] & S.FLAG_STATIC     # the matrix-core path is always persistent
     ref = S.rf(w["probe"], w["medium"], dict(o, **ch), w["delays"], w["apod"], dx, None, dz, dR,
                offsets=off)
     got = plan.rf(dx, None, dz, dR, g["n_t"])
