@@ -409,7 +409,8 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     const int N = Cc.P.N, M = Cc.P.M, n_tx = Cc.n_tx, n_ph = Cc.ph.n;
     F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx);
     SynthConfig& cfg = F.cfg;
-    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y) : synth_config(M, Cc.P.nu, n_tx, Cc.has_y);
+    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y)
+                   : synth_config(M, Cc.P.nu, n_tx, Cc.has_y, Cc.table && !Cc.P.dim2);
     cfg.table = Cc.table;
     cfg.dim2 = Cc.P.dim2;   // the vector path skips the (unit) table in 2-D
     const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;

@@ -83,13 +83,15 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #endif
 
 // Bins per tile: the receive accumulators (JT TT BS slots of 8 bytes, or
-// of 4 bytes when paired) are kept within 64 KiB (32 KiB paired).  At most 18
-// bins: a paired 256-thread block then takes 52 KB of LDS (accumulators 18,
-// reduction rows 17, elevation table 16), which keeps three blocks per CU;
-// with 20 bins only two fit.  Longer tiles amortise each pair's set-up.
-constexpr int synth_jt(int bs, int tt, bool pair)
+// of 4 bytes when paired) are kept within 64 KiB (32 KiB paired).  With the
+// elevation table in LDS, at most 18 bins: a paired 256-thread block then
+// takes 52 KB of LDS (accumulators 18, reduction rows 17, table 16), which
+// keeps three blocks per CU; with 20 bins only two fit.  Without the table
+// (2-D, y != 0, direct evaluation) paired blocks take up to 32 bins in the
+// same space.  Longer tiles amortise each pair's set-up.
+constexpr int synth_jt(int bs, int tt, bool pair, bool table_lds)
 {
-    int jt = SIMUS_JT_MAX;
+    int jt = (pair && !table_lds) ? 32 : SIMUS_JT_MAX;
     const int slot = pair ? 4 : 8;
     const int budget = pair ? 32768 : 65536;
     while (jt > 1 && jt * tt * bs * slot > budget) jt /= 2;
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     }
 }
 
-SynthConfig synth_config(int M, int nu, int n_tx, bool has_y)
+SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds)
 {
     SynthConfig c{};
     int bs = 64;
@@ -363,7 +365,7 @@ SynthConfig synth_config(int M, int nu, int n_tx, bool has_y)
     c.tt = n_tx >= 2 && (n_tx % 2 == 0 || n_tx >= 11) ? 2 : 1;
     c.sc = c.tt == 2 ? 4 : SIMUS_SC1;
     c.pair = nu == 2;
-    c.jt = synth_jt(bs, c.tt, c.pair);
+    c.jt = synth_jt(bs, c.tt, c.pair, table_lds);
     c.has_y = has_y;
     return c;
 }
@@ -371,12 +373,15 @@ SynthConfig synth_config(int M, int nu, int n_tx, bool has_y)
 template <int BS, int SC, int TT, bool PAIR>
 static SynthKernel synth_kernel_y(const SynthConfig& cfg)
 {
-    constexpr int JT = synth_jt(BS, TT, PAIR);
-    if (cfg.jt != JT || cfg.sc != SC) return nullptr;
-    if (cfg.has_y) return k_synth<BS, SC, JT, TT, true, 0, PAIR>;
-    if (cfg.dim2) return k_synth<BS, SC, JT, TT, false, 2, PAIR>;
-    if (cfg.table) return k_synth<BS, SC, JT, TT, false, 1, PAIR>;
-    return k_synth<BS, SC, JT, TT, false, 0, PAIR>;
+    constexpr int JTT = synth_jt(BS, TT, PAIR, true);    // table in LDS
+    constexpr int JTN = synth_jt(BS, TT, PAIR, false);   // no table
+    if (cfg.sc != SC) return nullptr;
+    const bool with_table = !cfg.has_y && !cfg.dim2 && cfg.table;
+    if (cfg.jt != (with_table ? JTT : JTN)) return nullptr;
+    if (cfg.has_y) return k_synth<BS, SC, JTN, TT, true, 0, PAIR>;
+    if (cfg.dim2) return k_synth<BS, SC, JTN, TT, false, 2, PAIR>;
+    if (cfg.table) return k_synth<BS, SC, JTT, TT, false, 1, PAIR>;
+    return k_synth<BS, SC, JTN, TT, false, 0, PAIR>;
 }
 
 template <int BS, bool PAIR>

@@ -168,7 +168,9 @@ hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, 
                                 hipStream_t st);
 
 // Picks bs/tt/sc/jt for M = nu N sub-elements and a transmit count.
-SynthConfig synth_config(int M, int nu, int n_tx, bool has_y);
+// table_lds: the synthesis holds the elevation table in LDS (y = 0, 3-D,
+// table not disabled)
+SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds);
 
 hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
                          int N, int j_lo, double df, hipStream_t st);
