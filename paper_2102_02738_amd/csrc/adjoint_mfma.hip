@@ -14,7 +14,7 @@
 // + a_t b'_t) (the R_s factor of the positions is applied by the reduction
 // kernel), accumulated across the item's bins in registers.  Nothing is
 // accumulated per bin, so each (sub-element, scatterer) pair is set up once
-// per 16 bins and stepped across them (green.hpp).
+// per 32 bins and stepped across them (green.hpp).
 //
 // Block: 512 threads (8 waves), chunks of 8 scatterers (32 rows, two row
 // tiles); work item = (phantom, scatterer slice, bin range).
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int LST = NE + 4;             // row stride of the element sums
     constexpr int WS = NE + 1;              // row stride of the staged columns
-    constexpr int JS = 16;                  // bins per set-up
+    constexpr int JS = 32;                  // bins per set-up
     constexpr int NX = HASY ? 3 : 2;        // coordinates: X, Z (, Y)
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * (NB / MS) == SCH, "synthesis threads must cover the chunk");
@@ -267,7 +267,7 @@ AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y)
     AdjConfig c{};
     c.mfma = true;
     c.tt = n_tx <= 8 ? 8 : 16;
-    c.jt = 16;
+    c.jt = 32;                // bins per set-up (JS), the bin-range granule
     c.scatterers = 64;        // per item, a multiple of the 8-scatterer chunk
     c.pair = M == 2 * N;
     c.has_y = has_y;
