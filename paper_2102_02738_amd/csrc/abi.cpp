@@ -407,7 +407,8 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     F.C = std::move(C);
     const Common& Cc = F.C;
     const int N = Cc.P.N, M = Cc.P.M, n_tx = Cc.n_tx, n_ph = Cc.ph.n;
-    F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx);
+    F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx) &&
+               Cc.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
     SynthConfig& cfg = F.cfg;
     cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y)
                    : synth_config(M, Cc.P.nu, n_tx, Cc.has_y, Cc.table && !Cc.P.dim2);
@@ -598,7 +599,8 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     if (!dR && !dX && !dY && !dZ) return;
     if (C.ph.total == 0) return;
     const int N = C.P.N;
-    const bool use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && adjoint_mt_supported(C.P.M, N, n_tx);
+    const bool use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && adjoint_mt_supported(C.P.M, N, n_tx) &&
+                        C.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
     AdjConfig cfg = use_mt ? adjoint_mt_config(C.P.M, N, n_tx, C.has_y) : adjoint_config(n_tx, C.has_y);
     cfg.table = C.table;
     // items: (phantom, scatterer slice, bin range); about 3000 items (matrix-core

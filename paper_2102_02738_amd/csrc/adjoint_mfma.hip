@@ -120,7 +120,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const float4 v = s_sc[sp * PPT + k];
-                g[k] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0, &D[k]);
+                g[k] = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0, &D[k]);
                 if (!active) g[k].E = make_float2(0.f, 0.f);
             }
             const int nb = min(JS, b_end - jb0);

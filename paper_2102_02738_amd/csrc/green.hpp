@@ -113,7 +113,7 @@ struct GeoD {
 // Set-up of a pair at bin j0: distance r in FP64, azimuthal angle theta of
 // the point seen from the sub-element face (Eq. 23), obliquity of Eq. (39).
 // With D != nullptr also the derivative data of the pair.
-template <bool HASY>
+template <bool HASY, bool SMALL_SINC = false>
 __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, float px, float py,
                                         float pz, int j0, GeoD* D = nullptr)
 {
@@ -167,8 +167,9 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     const float sigma = K.sinc_per_bin * st;
     const float theta = 6.283185307179586f * sigma;
     // sinc(theta / 2): |theta / 2| <= pi sinc_per_bin, below 1 for any
-    // practical probe and grid (a uniform branch)
-    const float sh = K.sinc_per_bin < 0.3f ? sinc_taylor(0.5f * theta) : sinc_setup(0.5f * theta);
+    // practical probe and grid (a uniform branch; SMALL_SINC: known below)
+    const float sh = (SMALL_SINC || K.sinc_per_bin < SINC_TAYLOR_LIMIT) ? sinc_taylor(0.5f * theta)
+                                                                        : sinc_setup(0.5f * theta);
     g.s = jf0 * sinc_setup(jf0 * theta);
     g.d = cos_turns((jf0 - 0.5f) * sigma) * sh;
     g.lam = -(theta * sh) * (theta * sh);

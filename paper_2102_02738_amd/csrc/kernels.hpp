@@ -33,6 +33,12 @@ struct ModelConst {
     Gauss4 g;
 };
 
+// The half-angle sinc of the pair set-up, sinc(theta / 2) with |theta / 2| <=
+// pi sinc_per_bin, is its Taylor series when sinc_per_bin is below this limit
+// (argument below 1); the matrix-core kernels assume it (the host sends other
+// problems to the vector path).
+constexpr float SINC_TAYLOR_LIMIT = 0.3f;
+
 // Elevation-term table (y = 0): DELTA_NT cubic intervals in w = q / (|q| + L).
 constexpr int DELTA_NT = 512;
 // float4 index of the first and second halves of interval k's coefficients:
