@@ -254,3 +254,36 @@ def test_large_t_focused_full_size_sampled_bins(S, orc):
     got = spec[0][:, :, bins - g["j_lo"]]
     print("ph64x128_s40k sampled bins rel L2", rel_l2(got, ref))
     assert rel_l2(got, ref) <= TOL
+
+
+def test_coarse_grid_general_half_sinc(S, orc):
+    """A grid so coarse that the half-angle sinc of the pair set-up reaches
+    arguments above 1 (nu = 1, 0.9 mm elements, nfft = 10, so df b / c =
+    0.35): the set-up's general sinc branch runs, and the matrix-core path
+    declines the 5 transmits (the result equals the vector path's bit for
+    bit).  RF against the oracle."""
+    import torch
+    from paper_2102_02738_amd import inputs
+    probe = dict(inputs.linear_probe(8), pitch=1e-3, width=0.9e-3, fc=3e6)
+    rng = np.random.default_rng(21)
+    n = 40
+    x = rng.uniform(-8e-3, 8e-3, n).astype(np.float32)
+    z = rng.uniform(2e-3, 6e-3, n).astype(np.float32)
+    R = rng.standard_normal(n).astype(np.float32)
+    dl = inputs.plane_wave_delays(probe, [-10, -5, 0, 5, 10])
+    ap = np.ones(dl.shape, np.float32)
+    w = dict(probe=probe, medium=dict(c=1540.0, alpha_db=0.5),
+             options=dict(fs=12e6, n_cycles=1.0, nu=1, spectral_eps=1e-7, nfft=10, n_t=10),
+             delays=dl, apod=ap)
+    g = S.grid(probe, w["medium"], w["options"], dl, x, None, z)
+    assert g["nfft"] == 10 and g["n_t"] == 10
+    assert g["df"] * 0.45e-3 / 1540.0 > 0.3
+    dx, dz, dR = to_dev(x, z, R)
+    got = S.rf(probe, w["medium"], w["options"], dl, ap, dx, None, dz, dR)
+    vec = S.rf(probe, w["medium"], dict(w["options"], flags=S.FLAG_NO_MFMA), dl, ap, dx, None, dz, dR)
+    torch.cuda.synchronize()
+    assert torch.equal(got, vec)
+    ref = orc.rf(oracle_setup(orc, w), g, dl, ap, x, np.zeros(n), z, R)
+    e = rel_l2(got.cpu().numpy()[0], ref)
+    print("coarse grid rel L2", e)
+    assert e <= TOL
