@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 # counted from the gfx950 assembly with paper_2102_02738_amd/diag/isa_count.py.
 SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi18ELi1ELb0ELi1ELb1EEEvNS_9SynthArgsE"
 SYNTH_TERMS_PER_ITER = 16
-SYNTH_VALU_PER_G = 34.125      # full-rate VALU instructions per G term
+SYNTH_VALU_PER_G = 33.0        # full-rate VALU instructions per G term
 SYNTH_TRANS_PER_G = 1.0        # transcendental instructions per G term
 # The same kernel in 2-D acoustics (no elevation term, so 32-bin tiles fit),
 # k_synth<256, 8, 32, 1, false, 2, true>, counted the same way.

@@ -277,10 +277,13 @@ struct DeltaFetch {
     float t;
 };
 
-__device__ __forceinline__ DeltaFetch delta_fetch(const float4* tab, const DeltaParams& P, float q)
+// Argument b = q inv_dw / L (a pair's kap pre-scaled by P.kscale): the table
+// coordinate u0 + inv_dw q / (|q| + L) is u0 + b / (|b| dw + 1), one
+// multiply fewer per term than from q.
+__device__ __forceinline__ DeltaFetch delta_fetch(const float4* tab, const DeltaParams& P, float b)
 {
-    const float w = q * rcp_fast(fabsf(q) + P.L);
-    const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
+    const float r = rcp_fast(fmaf(fabsf(b), P.dw, 1.f));
+    const float u = __builtin_amdgcn_fmed3f(fmaf(b, r, P.u0), 0.f, P.umax);
     const int k = (int)u;                  // u >= 0: truncation is the floor
     DeltaFetch f;
     f.t = __builtin_amdgcn_fractf(u);

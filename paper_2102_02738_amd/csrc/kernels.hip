@@ -257,6 +257,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 const float4 v = s_sc[s];
                 g[s] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g[s].E = make_float2(0.f, 0.f);
+                if (TABLE) g[s].kap *= P.kscale;          // delta_fetch's argument
             }
             // one bin: terms of bin jj into Gc, Tx rows, barrier, reduction of
             // bin jj, receive of bin jj - 1 from Gp

@@ -52,6 +52,8 @@ struct DeltaParams {
     float u0;      // -w_lo / dw
     float inv_dw;  // 1 / dw
     float umax;    // DELTA_NT - 2^-8
+    float kscale;  // inv_dw / L: q -> b = q inv_dw / L (delta_fetch's argument)
+    float dw;      // 1 / inv_dw
 };
 
 // Sub-element frames, device arrays of length M = nu N.

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 const float4 v = s_sc[sh * PPT + k];
                 g[k] = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g[k].E = make_float2(0.f, 0.f);
+                if (TABLE) g[k].kap *= P.kscale;          // delta_fetch's argument
             }
             // The bin loop is unrolled so that the receive sums X[jj] stay in
             // registers; nb is uniform, so the barriers inside are too.

@@ -141,6 +141,8 @@ __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* p
         P.u0 = (float)(-w_lo / dw);
         P.inv_dw = (float)(1.0 / dw);
         P.umax = (float)DELTA_NT - 1.0f / 256.0f;
+        P.kscale = (float)(1.0 / (dw * L));
+        P.dw = (float)dw;
         *par = P;
     }
 }
