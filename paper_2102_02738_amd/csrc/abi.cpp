@@ -1031,25 +1031,33 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
         std::lock_guard<std::mutex> lk(plan->mu);
         const double* dl = plan->delays.data();
         const float* ap = plan->apod.empty() ? nullptr : plan->apod.data();
-        // rebuilds the plan for options o, growing the workspace if needed, and
-        // uploads its tables (waits for the stream)
-        auto rebuild = [&](const simus_options& o) {
-            FwdPlan F = make_fwd_plan(Common(plan->F.C), &o, dl, ap, true);
+        // The workspace's tables change below: a captured graph is dropped now.
+        if (plan->exec) {
+            hip_check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
+            plan->exec = nullptr;
+        }
+        // Uploads a plan's tables into the workspace, growing it first if needed
+        // (the old workspace is freed only once the new one exists); waits for
+        // the stream.
+        auto upload = [&](const FwdPlan& F) {
             if (F.dv_size > plan->dev_cap) {
-                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-                hip_check(hipFree(plan->dev), "hipFree");
-                plan->dev = nullptr;
-                plan->dev_cap = 0;
-                if (hipMalloc(&plan->dev, F.dv_size) != hipSuccess) {
-                    plan->dev = nullptr;
+                void* nd = nullptr;
+                if (hipMalloc(&nd, F.dv_size) != hipSuccess) {
                     (void)hipGetLastError();
                     throw Error{SIMUS_ENOMEM, "plan workspace allocation failed"};
                 }
+                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                (void)hipFree(plan->dev);
+                plan->dev = static_cast<char*>(nd);
                 plan->dev_cap = F.dv_size;
             }
             hip_check(hipMemcpyAsync(plan->dev, F.host.data(), F.up_size, hipMemcpyHostToDevice, st),
                       "hipMemcpyAsync");
             hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        };
+        auto rebuild = [&](const simus_options& o) {
+            FwdPlan F = make_fwd_plan(Common(plan->F.C), &o, dl, ap, true);
+            upload(F);
             return F;
         };
         // candidates: 0.5x .. 2x the default scatterers per item; on the vector
@@ -1060,7 +1068,8 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
             for (int persist = 0; persist < 2; ++persist) {
                 if (plan->F.use_mt && !persist) continue;   // always persistent there
                 simus_options o = plan->opt;
-                o.tile_scat = std::max<int64_t>(1, (int64_t)std::llround(base * m));
+                o.tile_scat = (int32_t)std::min<int64_t>(std::max<int64_t>(1, std::llround(base * m)),
+                                                         int64_t(1) << 30);
                 o.flags = persist ? (o.flags & ~SIMUS_FLAG_STATIC) : (o.flags | SIMUS_FLAG_STATIC);
                 cands.push_back(o);
             }
@@ -1095,16 +1104,28 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
         } catch (...) {
             (void)hipEventDestroy(ev[0]);
             (void)hipEventDestroy(ev[1]);
+            // the plan keeps its own configuration: put its tables back (the
+            // workspace only grew, so it still fits them)
+            try {
+                upload(plan->F);
+            } catch (...) {
+            }
             throw;
         }
         hip_check(hipEventDestroy(ev[0]), "hipEventDestroy");
         hip_check(hipEventDestroy(ev[1]), "hipEventDestroy");
-        plan->F = rebuild(best);
-        plan->opt = best;
-        if (plan->exec) {
-            hip_check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
-            plan->exec = nullptr;
+        FwdPlan F = make_fwd_plan(Common(plan->F.C), &best, dl, ap, true);
+        try {
+            upload(F);
+        } catch (...) {
+            try {
+                upload(plan->F);
+            } catch (...) {
+            }
+            throw;
         }
+        plan->F = std::move(F);
+        plan->opt = best;
         if (tile_scat) *tile_scat = best.tile_scat;
         if (flags) *flags = best.flags;
     });
