@@ -252,9 +252,11 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
  * keeps the fastest configuration in the plan (later executions and graph
  * launches use it; a captured graph is dropped) and returns its
  * options.tile_scat and options.flags in *tile_scat and *flags (either may
- * be NULL).  Waits for hip_stream; rf is overwritten; the plan's workspace
- * may be reallocated.  The results do not depend on the choice beyond
- * rounding order. */
+ * be NULL).  Waits for the device first (earlier executions of the plan on
+ * any stream) and for hip_stream at the end; rf is overwritten; the plan's
+ * workspace may be reallocated.  On failure the plan keeps its previous
+ * configuration.  The results do not depend on the choice beyond rounding
+ * order. */
 int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y,
                            const float* z, const float* refl, float* rf, void* hip_stream,
                            int64_t* tile_scat, int32_t* flags);

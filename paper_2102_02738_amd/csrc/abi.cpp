@@ -1031,7 +1031,10 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
         std::lock_guard<std::mutex> lk(plan->mu);
         const double* dl = plan->delays.data();
         const float* ap = plan->apod.empty() ? nullptr : plan->apod.data();
-        // The workspace's tables change below: a captured graph is dropped now.
+        // The workspace's tables change below: earlier executions and graph
+        // launches of the plan (on any stream) must have finished, and a
+        // captured graph is dropped now.
+        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
         if (plan->exec) {
             hip_check(hipGraphExecDestroy(plan->exec), "hipGraphExecDestroy");
             plan->exec = nullptr;
