@@ -34,7 +34,9 @@
  * - All device work is enqueued on `hip_stream` (a hipStream_t; NULL = the
  *   null stream).  No entry point synchronises the stream; outputs are
  *   ready when the stream's work completes.  Calls that share a stream are
- *   ordered; calls on different streams use different workspaces.
+ *   ordered; calls on different streams use different workspaces.  Calls
+ *   on one stream must not be made from several host threads at once
+ *   (they share that stream's workspace and staging buffer).
  * - Return value: SIMUS_OK (0) or a negative error code.  Arguments are
  *   validated on the host before any HIP call, so invalid arguments never
  *   reach the GPU.  simus_last_error() gives a message (thread-local).
