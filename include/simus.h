@@ -119,6 +119,12 @@ typedef struct {
 #define SIMUS_FLAG_STATIC       16   /* vector path: one block per work item instead of the
                                         persistent launch (the matrix-core path is always
                                         persistent); results are bitwise the same */
+#define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape: matrix-core groups of 16
+                                        transmit columns instead of 32 (more than 64
+                                        elements) or 64 instead of 32 (64 or fewer); vector
+                                        path: single transmits instead of pairs, or pairs
+                                        instead of single transmits.  The autotuner tries
+                                        it; the results agree to rounding order */
 /* Other bits of options.flags are rejected with SIMUS_EINVAL. */
 
 /* Frequency grid of one call. */
@@ -247,8 +253,10 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
 
 /* Autotuner of a plan's launch shape.  Times the plan's kernels (HIP events
  * on hip_stream) on the given scatterers, laid out as for
- * simus_rf_plan_execute, for scatterers per work item from 0.5x to 2x the
- * default and, on the vector path, with and without SIMUS_FLAG_STATIC
+ * simus_rf_plan_execute, for two tile shapes (the default rule's and,
+ * where it differs, SIMUS_FLAG_ALT_SHAPE's), scatterers per work item from
+ * 0.5x to 2x the default and, on the vector path, with and without
+ * SIMUS_FLAG_STATIC
  * (a warm-up run each, then the mean of three runs, or one run when a run
  * takes over 50 ms);
  * keeps the fastest configuration in the plan (later executions and graph

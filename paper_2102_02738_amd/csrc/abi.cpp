@@ -410,8 +410,9 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx) &&
                Cc.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
     SynthConfig& cfg = F.cfg;
-    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y)
-                   : synth_config(M, Cc.P.nu, n_tx, Cc.has_y, Cc.table && !Cc.P.dim2);
+    const bool alt = (opt->flags & SIMUS_FLAG_ALT_SHAPE) != 0;
+    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y, alt)
+                   : synth_config(M, Cc.P.nu, n_tx, Cc.has_y, Cc.table && !Cc.P.dim2, alt);
     cfg.table = Cc.table;
     cfg.dim2 = Cc.P.dim2;   // the vector path skips the (unit) table in 2-D
     const int JT = cfg.jt, TT = cfg.tt, BS = cfg.bs, SC = cfg.sc;
@@ -1063,20 +1064,33 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
             upload(F);
             return F;
         };
-        // candidates: 0.5x .. 2x the default scatterers per item; on the vector
-        // path with and without the persistent launch
+        // candidates: the tile shape of the default rule and, where it differs,
+        // the alternative one (SIMUS_FLAG_ALT_SHAPE); 0.5x .. 2x the
+        // default scatterers per item; on the vector path with and without
+        // the persistent launch
         const int64_t base = plan->F.slice;
-        std::vector<simus_options> cands;
-        for (double m : {0.5, 0.75, 1.0, 1.5, 2.0}) {
-            for (int persist = 0; persist < 2; ++persist) {
-                if (plan->F.use_mt && !persist) continue;   // always persistent there
-                simus_options o = plan->opt;
-                o.tile_scat = (int32_t)std::min<int64_t>(std::max<int64_t>(1, std::llround(base * m)),
-                                                         int64_t(1) << 30);
-                o.flags = persist ? (o.flags & ~SIMUS_FLAG_STATIC) : (o.flags | SIMUS_FLAG_STATIC);
-                cands.push_back(o);
-            }
+        std::vector<int32_t> shapes = {plan->opt.flags & ~SIMUS_FLAG_ALT_SHAPE};
+        {
+            simus_options w = plan->opt, n = plan->opt;
+            w.flags &= ~SIMUS_FLAG_ALT_SHAPE;
+            n.flags |= SIMUS_FLAG_ALT_SHAPE;
+            const FwdPlan Fw = make_fwd_plan(Common(plan->F.C), &w, dl, ap, true);
+            const FwdPlan Fn = make_fwd_plan(Common(plan->F.C), &n, dl, ap, true);
+            if (Fn.cfg.tt != Fw.cfg.tt || Fn.use_mt != Fw.use_mt) shapes.push_back(n.flags);
         }
+        std::vector<simus_options> cands;
+        for (const int32_t shape_flags : shapes)
+            for (double m : {0.5, 1.0, 1.5, 2.0}) {
+                for (int persist = 0; persist < 2; ++persist) {
+                    if (plan->F.use_mt && !persist) continue;   // always persistent there
+                    simus_options o = plan->opt;
+                    o.flags = shape_flags;
+                    o.tile_scat = (int32_t)std::min<int64_t>(
+                        std::max<int64_t>(1, std::llround(base * m)), int64_t(1) << 30);
+                    o.flags = persist ? (o.flags & ~SIMUS_FLAG_STATIC) : (o.flags | SIMUS_FLAG_STATIC);
+                    cands.push_back(o);
+                }
+            }
         hipEvent_t ev[2] = {nullptr, nullptr};
         hip_check(hipEventCreate(&ev[0]), "hipEventCreate");
         hip_check(hipEventCreate(&ev[1]), "hipEventCreate");

@@ -353,7 +353,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     }
 }
 
-SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds)
+SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds, bool alt)
 {
     SynthConfig c{};
     int bs = 64;
@@ -363,7 +363,8 @@ SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds)
     // (fewer scatterers per chunk), so pairs pay for even counts and for 11
     // or more transmits; wider groups (4, 8: 2 scatterers per chunk, 8 or 4
     // bins per set-up) measured slower than single transmits.
-    c.tt = n_tx >= 2 && (n_tx % 2 == 0 || n_tx >= 11) ? 2 : 1;
+    const bool pairs = n_tx >= 2 && (n_tx % 2 == 0 || n_tx >= 11);
+    c.tt = (alt ? !pairs && n_tx >= 2 : pairs) ? 2 : 1;
     c.sc = c.tt == 2 ? 4 : SIMUS_SC1;
     c.pair = nu == 2;
     c.jt = synth_jt(bs, c.tt, c.pair, table_lds);

@@ -178,7 +178,9 @@ hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, 
 // Picks bs/tt/sc/jt for M = nu N sub-elements and a transmit count.
 // table_lds: the synthesis holds the elevation table in LDS (y = 0, 3-D,
 // table not disabled)
-SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds);
+// alt: the other transmit-group size (single transmits instead of pairs, or
+// pairs instead of single transmits), the alternative the autotuner tries
+SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds, bool alt = false);
 
 hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
                          int N, int j_lo, double df, hipStream_t st);
@@ -189,7 +191,9 @@ using SynthKernel = void (*)(SynthArgs);
 SynthKernel synth_kernel(const SynthConfig& cfg);
 hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 bool mt_supported(int M, int N, int n_tx);
-SynthConfig mt_config(int M, int N, int n_tx, bool has_y);
+// alt: the alternative group width (16 instead of 32 transmit columns for
+// 128 element slots, 64 instead of 32 for 64), which the autotuner tries
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt = false);
 SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 // inv_j2: the partials are of j G terms (both synthesis paths) and are

@@ -57,7 +57,7 @@ Probe make_probe(const simus_probe* p, const simus_medium* m, const simus_option
     require(o->tile_bins >= 0 && o->tile_bins <= 32, "options.tile_bins must be in [0, 32]");
     require(o->tile_scat >= 0, "options.tile_scat must be >= 0");
     require((o->flags & ~(SIMUS_FLAG_NO_MFMA | SIMUS_FLAG_PERSISTENT | SIMUS_FLAG_NO_DELTA_TABLE |
-                          SIMUS_FLAG_2D | SIMUS_FLAG_STATIC)) == 0,
+                          SIMUS_FLAG_2D | SIMUS_FLAG_STATIC | SIMUS_FLAG_ALT_SHAPE)) == 0,
             "options.flags has unknown bits");
 
     P.N = p->n_elements;

@@ -310,15 +310,18 @@ struct MtShape {
     int ne, ntp, jt, nx;
 };
 
-static MtShape mt_shape(int N, int n_tx)
+static MtShape mt_shape(int N, int n_tx, bool alt)
 {
-    // 64-element shapes hold 6 bins of receive sums (8 spill; 6 is 3 %
-    // faster than 4 on the 128-transmit sequence); 128-element shapes 4
+    // 64 element slots: groups of 32 transmit columns with 6 bins per item
+    // (measured per transmit as fast as 64 columns at full groups, and finer:
+    // 96 transmits 35 vs 49 ms); alternative: 64 columns.  128 slots: 32
+    // columns above 16 transmits (21 transmits, 200k scatterers: 215 vs
+    // 258 ms with 16), 4 bins per item (5 spill); alternative: 16 columns.
     if (N <= 64) {
-        if (n_tx <= 32) return {64, 2, 6, 3};
-        return {64, 4, 6, 2};
+        if (alt && n_tx > 32) return {64, 4, 6, 2};
+        return {64, 2, 6, 3};
     }
-    if (n_tx <= 16) return {128, 1, 4, 3};
+    if (n_tx <= 16 || alt) return {128, 1, 4, 3};
     return {128, 2, 4, 2};
 }
 
@@ -344,9 +347,9 @@ bool mt_supported(int M, int N, int n_tx)
     return n_tx >= 4 && N >= 1 && N <= 128 && (nu == 1 || nu == 2) && M == nu * N;
 }
 
-SynthConfig mt_config(int M, int N, int n_tx, bool has_y)
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt)
 {
-    const MtShape sh = mt_shape(N, n_tx);
+    const MtShape sh = mt_shape(N, n_tx, alt);
     SynthConfig c{};
     c.bs = 512;
     c.ne = sh.ne;

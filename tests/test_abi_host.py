@@ -88,7 +88,7 @@ def test_invalid_probe_rejected(L, field, value, code):
 
 
 @pytest.mark.parametrize("field,value", [("fs", 1e6), ("spectral_eps", 1.5), ("nfft", 1001),
-                                         ("nu", -2), ("n_cycles", 0.0), ("flags", 32),
+                                         ("nu", -2), ("n_cycles", 0.0), ("flags", 64),
                                          ("flags", -1)])
 def test_invalid_options_rejected(L, field, value):
     w = _base()

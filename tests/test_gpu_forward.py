@@ -199,7 +199,8 @@ def test_empty_and_degenerate(S):
 def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
     """Many steered plane waves: the transmit contraction on the matrix cores
     (or, with the flag, on the VALU path) matches the oracle; covers every
-    matrix-core shape (64 and 128 element slots, 16 to 64 transmit columns),
+    default matrix-core shape (64 and 128 element slots, 16 and 32 transmit
+    columns),
     several transmit groups with a ragged last one, y != 0, nu = 1 and 200
     elements (vector path)."""
     from paper_2102_02738_amd import inputs
@@ -287,3 +288,24 @@ def test_coarse_grid_general_half_sinc(S, orc):
     e = rel_l2(got.cpu().numpy()[0], ref)
     print("coarse grid rel L2", e)
     assert e <= TOL
+
+
+@pytest.mark.parametrize("n_tx,n_el,nu", [(21, 100, 0), (40, 48, 0), (5, 200, 0), (6, 64, 3)])
+def test_alt_tile_shape(S, orc, n_tx, n_el, nu):
+    """The alternative tile shape (SIMUS_FLAG_ALT_SHAPE: matrix-core groups
+    of 16 instead of 32 transmit columns for 100 elements, of 64 instead of
+    32 for 48; on the vector path pairs instead of single transmits for 5,
+    single instead of pairs for 6) matches the oracle and the default shape
+    to rounding order."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.3)
+    w["probe"] = inputs.linear_probe(n_el)
+    w["options"]["nu"] = nu
+    w["delays"] = inputs.plane_wave_delays(w["probe"], np.linspace(-12, 12, n_tx))
+    w["apod"] = np.random.default_rng(n_tx).uniform(0.2, 1.0, w["delays"].shape).astype(np.float32)
+    g, rf, data = _run(S, w, flags=S.FLAG_ALT_SHAPE)
+    _, rf0, _ = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    print(n_tx, "tx", n_el, "el alternative shape rel L2", rel_l2(rf, ref), "vs default", rel_l2(rf, rf0))
+    assert rel_l2(rf, ref) <= TOL
+    assert rel_l2(rf, rf0) <= 1e-5
