@@ -58,7 +58,8 @@ MFMA_FP32_PEAK = 157.3e12      # dense FP32 matrix-core FLOP/s
 
 def kernel_sources_digest() -> str:
     h = hashlib.sha256()
-    for f in ["kernels.hip", "green.hpp", "kernels.hpp"]:
+    # the kernel and its launch configuration (items, tiles) decide the traffic
+    for f in ["kernels.hip", "green.hpp", "kernels.hpp", "abi.cpp"]:
         with open(os.path.join(ROOT, "paper_2102_02738_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
