@@ -257,6 +257,40 @@ def extra_autotune(steps: int, name: str) -> dict:
                 gain=d_ms / t_ms, rel_l2_autotuned_vs_default=_rel(out, first))
 
 
+def extra_pfield(steps: int) -> dict:
+    """simus_pfield on a Fig. 9-like field: 64-element 2.7 MHz phased array
+    focused at (10, 60) mm, 256 x 256 points over x in [-40, 40] mm, z in
+    [5, 100] mm."""
+    import numpy as np
+    import torch
+    from paper_2102_02738_amd import pfield, pfield_nf
+    probe = dict(n_elements=64, fc=2.7e6, pitch=0.3e-3, width=0.25e-3, height=14e-3,
+                 elev_focus=60e-3, bandwidth=0.74, radius=0.0, baffle=0, zeta=1.75)
+    xe = 0.3e-3 * (np.arange(64) - 31.5)
+    d = np.hypot(xe - 10e-3, 60e-3) / 1540.0
+    dl = d.max() - d
+    X, Z = np.meshgrid(np.linspace(-40e-3, 40e-3, 256), np.linspace(5e-3, 100e-3, 256))
+    X, Z = X.ravel().astype(np.float32), Z.ravel().astype(np.float32)
+    medium = dict(c=1540.0, alpha_db=0.5)
+    options = dict(fs=4 * probe["fc"], n_cycles=1.0, nu=0, spectral_eps=1e-7, nfft=0, n_t=0)
+    nf = pfield_nf(probe, medium, options, dl, X, None, Z)
+    dX, dZ = (torch.from_numpy(a).cuda() for a in (X, Z))
+    apod = np.ones(64, np.float32)
+    out = {}
+
+    def call():
+        out["p"] = pfield(probe, medium, options, nf, dl, apod, dX, None, dZ)
+
+    ms = _median_ms(call, max(steps, 5))
+    from paper_2102_02738_amd import grid
+    nu = grid(probe, medium, options, dl[None, :], X[:1], None, Z[:1])["nu"]
+    evals = float(X.size) * 64 * nu * (nf + 1)
+    return dict(workload="phased64 focused field 256x256", n_points=int(X.size), n_f=int(nf), nu=int(nu),
+                ms_per_call=ms, points_per_s=X.size / (ms * 1e-3),
+                point_subelement_freq_evals_per_s=evals / (ms * 1e-3),
+                finite=bool(torch.isfinite(out["p"]).all()))
+
+
 def extra_forward_adjoint(steps: int) -> dict:
     """Forward + residual + adjoint of the L2 misfit, 5 plane waves in one
     call each vs a per-transmit loop."""
@@ -401,6 +435,7 @@ def main():
         fns = {"autotune": lambda k: extra_autotune(max(k, 5), "pw128_s50k"),
                "batched_transmits": extra_batched_transmits, "uneven_phantoms": extra_uneven_phantoms,
                "forward_adjoint": extra_forward_adjoint, "large_t": extra_large_t,
+               "pfield": extra_pfield,
                "two_d": lambda k: extra_two_d(k, float("nan"))}
         if args.only_extra not in fns:
             print(f"unknown extra {args.only_extra!r}; one of {sorted(fns)}", file=sys.stderr)
@@ -464,6 +499,7 @@ def main():
             "forward_adjoint": extra_forward_adjoint(args.extra_steps),
             "two_d": extra_two_d(args.extra_steps, ms_per_step),
             "large_t": extra_large_t(args.extra_steps),
+            "pfield": extra_pfield(args.extra_steps),
         }
     if not args.no_cpu_baseline:
         x, y, z, R = c.host
