@@ -432,8 +432,10 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
         const int64_t work = std::max<int64_t>(1, Cc.ph.total) * F.n_bt * n_tg;
         slice = F.use_mt ? (work + 2999) / 3000 : (work + 5999) / 6000;
     }
-    slice = std::max<int64_t>(slice, 4 * SC);
-    slice = (slice + SC - 1) / SC * SC;
+    // a multiple of the super-chunk (groups x chunk) that the kernel steps by
+    const int SCG = SC * (F.use_mt ? 1 : std::max(cfg.groups, 1));
+    slice = std::max<int64_t>(slice, 4 * SCG);
+    slice = (slice + SCG - 1) / SCG * SCG;
     slice = std::min<int64_t>(slice, int64_t(1) << 30);
     F.slice = slice;
 
@@ -551,9 +553,9 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     if (log_enabled())
         std::fprintf(stderr,
                      "[simus] N=%d nu=%d M=%d T=%d P=%d S=%lld nfft=%d n_t=%d j_lo=%d bins=%d "
-                     "BS=%d TT=%d SC=%d JT=%d slice=%lld items=%d grid=%d y=%d table=%d persistent=%d mfma=%d\n",
+                     "BS=%d G=%d TT=%d SC=%d JT=%d slice=%lld items=%d grid=%d y=%d table=%d persistent=%d mfma=%d\n",
                      N, C.P.nu, C.P.M, n_tx, n_ph, (long long)C.ph.total, C.B.nfft, C.B.n_t, C.B.j_lo,
-                     C.B.n_bins, cfg.bs, cfg.tt, cfg.sc, cfg.jt, (long long)F.slice, F.n_items, cfg.grid,
+                     C.B.n_bins, cfg.bs, cfg.groups, cfg.tt, cfg.sc, cfg.jt, (long long)F.slice, F.n_items, cfg.grid,
                      (int)C.has_y, (int)C.table, (int)cfg.persistent, (int)F.use_mt);
     hip_check(timed(K_SYNTH, st, [&] {
                   return F.use_mt ? launch_synth_mt(cfg, A, st) : launch_synth(cfg, A, st);
@@ -562,7 +564,8 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     hip_check(timed(K_FINALIZE, st, [&] {
                   return launch_finalize(spec, A.part, at<float2>(d, F.L.pw), at<int32_t>(d, F.o_pb),
                                          at<int32_t>(d, F.o_ns), n_ph, n_tx, N, F.fin_nu, C.B.n_bins,
-                                         F.slots, cfg.tt, cfg.jt, F.n_bt, C.B.j_lo, true, st);
+                                         F.slots, F.use_mt ? 1 : cfg.groups, cfg.tt, cfg.jt, F.n_bt,
+                                         C.B.j_lo, true, st);
               }),
               "finalize launch");
     if (rf_out) {

@@ -89,9 +89,12 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 // keeps three blocks per CU; with 20 bins only two fit.  Without the table
 // (2-D, y != 0, direct evaluation) paired blocks take up to 32 bins in the
 // same space.  Longer tiles amortise each pair's set-up.
-constexpr int synth_jt(int bs, int tt, bool pair, bool table_lds)
+constexpr int synth_jt(int bs, int tt, bool pair, bool table_lds, int groups = 1)
 {
     int jt = (pair && !table_lds) ? 32 : SIMUS_JT_MAX;
+    // four paired groups' reduction rows take 1.5 KB more LDS: 16 bins keep
+    // three blocks per CU (32-element probe: 2.39 vs 2.78 ms with 18)
+    if (pair && table_lds && groups == 4) jt = 16;
     const int slot = pair ? 4 : 8;
     const int budget = pair ? 32768 : 65536;
     while (jt > 1 && jt * tt * bs * slot > budget) jt /= 2;
@@ -129,31 +132,37 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 // EL: elevation term evaluated directly (0), from the table (1), or absent
-// (2, 2-D acoustics).
-template <int BS, int SC, int JT, int TT, bool HASY, int EL, bool PAIR>
+// (2, 2-D acoustics).  NG groups of BS / NG sub-element slots share the block
+// (its LDS table and barriers); group g takes the g-th chunk of SC scatterers
+// of each super-chunk of NG SC, so small probes still fill 256-thread blocks.
+template <int BS, int SC, int JT, int TT, bool HASY, int EL, bool PAIR, int NG>
 __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 {
-    constexpr int NS = SC * TT;            // sums per bin
-    constexpr int HB = BS / 2;             // pair sums per row
+    constexpr int BG = BS / NG;            // sub-element slots per group
+    constexpr int NS = SC * TT;            // sums per bin and group
+    constexpr int NT = NS * NG;            // sums per bin
+    constexpr int HB = BG / 2;             // pair sums per row
     constexpr int RS = HB + 4;             // LDS row stride (float2)
-    constexpr int GL = (HB / NS >= 64) ? 64 : HB / NS;   // lanes per sum
+    constexpr int GL = (BS / 2 / NT >= 64) ? 64 : (BS / 2 / NT < HB ? BS / 2 / NT : HB);   // lanes per sum
     constexpr int PER = HB / GL;           // values per lane
     constexpr int NA = PAIR ? 1 : 2;       // floats per accumulator slot
-    static_assert(NS <= HB, "chunk x transmit group must not exceed half the block");
+    static_assert(NT <= BS / 2 && GL >= 1 && HB % GL == 0, "sums must fit half the block");
+    static_assert(BG >= 64 && BG % 64 == 0, "a group spans whole waves");
 
-    __shared__ float4 s_sc[SC];
-    __shared__ float2 s_red[2][NS * RS];
+    __shared__ float4 s_sc[NG * SC];
+    __shared__ float2 s_red[2][NT * RS];
     // reduced values c (PAIR: [0] = (Re c, -Im c) for even lanes,
     // [1] = (Im c, Re c) for odd lanes)
-    __shared__ float2 s_c[2][PAIR ? 2 : 1][NS];
+    __shared__ float2 s_c[2][PAIR ? 2 : 1][NT];
     __shared__ float s_acc[JT * TT * BS * NA];
     constexpr bool TABLE = EL == 1;
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
     const int tid = threadIdx.x;
-    const bool active = tid < A.M;
-    const SubFrame fr = load_frame(A.sub, active ? tid : 0);
-    const int e = active ? tid / A.nu : 0;
+    const int n = tid % BG, grp = tid / BG;    // sub-element slot, group
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    const int e = active ? n / A.nu : 0;
     DeltaParams P{};
     if (TABLE) {
         for (int i = tid; i < 2 * DELTA_NT; i += BS) s_tab[i] = A.dtab[i];
@@ -163,7 +172,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     // Tx reduction of one bin: rows s_red[buf] -> s_c[buf] (R_s applied).
     auto reduce = [&](int buf) {
         const int sid = tid / GL, lg = tid % GL;
-        if (sid < NS) {
+        if (sid < NT) {
             // two independent partial sums shorten the dependency chain
             float2 acc = make_float2(0.f, 0.f), acc2 = make_float2(0.f, 0.f);
             const float2* row = &s_red[buf][sid * RS];
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
             acc.x = group_sum<GL>(acc.x);
             acc.y = group_sum<GL>(acc.y);
             if (lg == 0) {
-                const float R = s_sc[sid % SC].w;
+                const float R = s_sc[(sid / NS) * SC + sid % SC].w;
                 const float cx = R * acc.x, cy = R * acc.y;
                 if (PAIR) {
                     s_c[buf][0][sid] = make_float2(cx, -cy);
@@ -201,7 +210,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
         for (int t = 0; t < TT; ++t) {
             const int slot = (jj * TT + t) * BS + tid;
             if (PAIR) {
-                const float2* cv = s_c[buf][tid & 1] + t * SC;
+                const float2* cv = s_c[buf][tid & 1] + grp * NS + t * SC;
                 float x = s_acc[slot], y = 0.f;
 #pragma unroll
                 for (int s = 0; s < SC; ++s) {
@@ -214,8 +223,8 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                 float2 x = make_float2(s_acc[2 * slot], s_acc[2 * slot + 1]), y = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int s = 0; s < SC; s += 2) {
-                    x = cfma(G[s], s_c[buf][0][t * SC + s], x);
-                    if (s + 1 < SC) y = cfma(G[s + 1], s_c[buf][0][t * SC + s + 1], y);
+                    x = cfma(G[s], s_c[buf][0][grp * NS + t * SC + s], x);
+                    if (s + 1 < SC) y = cfma(G[s + 1], s_c[buf][0][grp * NS + t * SC + s + 1], y);
                 }
                 s_acc[2 * slot] = x.x + y.x;
                 s_acc[2 * slot + 1] = x.y + y.y;
@@ -243,8 +252,8 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 
         for (int i = tid; i < JT * TT * BS * NA; i += BS) s_acc[i] = 0.f;
 
-        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SC) {
-            if (tid < SC) {
+        for (int s0 = it.s_begin; s0 < it.s_end; s0 += NG * SC) {
+            if (tid < NG * SC) {
                 const int s = s0 + tid;
                 float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
                 if (s < it.s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
@@ -254,7 +263,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
             Geo g[SC];
 #pragma unroll
             for (int s = 0; s < SC; ++s) {
-                const float4 v = s_sc[s];
+                const float4 v = s_sc[grp * SC + s];
                 g[s] = make_geo<HASY>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g[s].E = make_float2(0.f, 0.f);
                 if (TABLE) g[s].kap *= P.kscale;          // delta_fetch's argument
@@ -311,7 +320,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                         const float w2 = (tid & 1) ? W[t].x : -W[t].y;
 #pragma unroll
                         for (int s = 0; s < SC; ++s)
-                            red[2 * (t * SC + s) * RS + tid] = fmaf(w1, Gc[s].x, w2 * Gc[s].y);
+                            red[2 * (grp * NS + t * SC + s) * RS + n] = fmaf(w1, Gc[s].x, w2 * Gc[s].y);
                     }
                 } else {
                     // both lanes of a pair hold the same pair sum and store it
@@ -323,7 +332,7 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
                             float2 p = cmul(W[t], Gc[s]);
                             p.x += dpp<DPP_XOR1>(p.x);
                             p.y += dpp<DPP_XOR1>(p.y);
-                            s_red[buf][(t * SC + s) * RS + (tid >> 1)] = p;
+                            s_red[buf][(grp * NS + t * SC + s) * RS + (n >> 1)] = p;
                         }
                 }
                 __syncthreads();
@@ -356,9 +365,12 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
 SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds, bool alt)
 {
     SynthConfig c{};
-    int bs = 64;
-    while (bs < M) bs *= 2;
-    c.bs = bs;
+    int bg = 64;
+    while (bg < M) bg *= 2;
+    // probes of fewer than 256 sub-elements: several groups per 256-thread
+    // block share its elevation table and barriers
+    c.groups = bg < 256 ? 256 / bg : 1;
+    c.bs = bg * c.groups;
     // Transmits per group: a pair of transmits costs 1.8x a single one here
     // (fewer scatterers per chunk), so pairs pay for even counts and for 11
     // or more transmits; wider groups (4, 8: 2 scatterers per chunk, 8 or 4
@@ -367,31 +379,31 @@ SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds, bo
     c.tt = (alt ? !pairs && n_tx >= 2 : pairs) ? 2 : 1;
     c.sc = c.tt == 2 ? 4 : SIMUS_SC1;
     c.pair = nu == 2;
-    c.jt = synth_jt(bs, c.tt, c.pair, table_lds);
+    c.jt = synth_jt(c.bs, c.tt, c.pair, table_lds, c.groups);
     c.has_y = has_y;
     return c;
 }
 
-template <int BS, int SC, int TT, bool PAIR>
+template <int BS, int SC, int TT, bool PAIR, int NG>
 static SynthKernel synth_kernel_y(const SynthConfig& cfg)
 {
-    constexpr int JTT = synth_jt(BS, TT, PAIR, true);    // table in LDS
-    constexpr int JTN = synth_jt(BS, TT, PAIR, false);   // no table
+    constexpr int JTT = synth_jt(BS, TT, PAIR, true, NG);    // table in LDS
+    constexpr int JTN = synth_jt(BS, TT, PAIR, false, NG);   // no table
     if (cfg.sc != SC) return nullptr;
     const bool with_table = !cfg.has_y && !cfg.dim2 && cfg.table;
     if (cfg.jt != (with_table ? JTT : JTN)) return nullptr;
-    if (cfg.has_y) return k_synth<BS, SC, JTN, TT, true, 0, PAIR>;
-    if (cfg.dim2) return k_synth<BS, SC, JTN, TT, false, 2, PAIR>;
-    if (cfg.table) return k_synth<BS, SC, JTT, TT, false, 1, PAIR>;
-    return k_synth<BS, SC, JTN, TT, false, 0, PAIR>;
+    if (cfg.has_y) return k_synth<BS, SC, JTN, TT, true, 0, PAIR, NG>;
+    if (cfg.dim2) return k_synth<BS, SC, JTN, TT, false, 2, PAIR, NG>;
+    if (cfg.table) return k_synth<BS, SC, JTT, TT, false, 1, PAIR, NG>;
+    return k_synth<BS, SC, JTN, TT, false, 0, PAIR, NG>;
 }
 
-template <int BS, bool PAIR>
+template <int BS, bool PAIR, int NG>
 static SynthKernel synth_kernel_bs(const SynthConfig& cfg)
 {
     switch (cfg.tt) {
-    case 1: return synth_kernel_y<BS, SIMUS_SC1, 1, PAIR>(cfg);
-    case 2: return synth_kernel_y<BS, 4, 2, PAIR>(cfg);
+    case 1: return synth_kernel_y<BS, SIMUS_SC1, 1, PAIR, NG>(cfg);
+    case 2: return synth_kernel_y<BS, 4, 2, PAIR, NG>(cfg);
     default: return nullptr;
     }
 }
@@ -399,14 +411,12 @@ static SynthKernel synth_kernel_bs(const SynthConfig& cfg)
 template <bool PAIR>
 static SynthKernel synth_kernel_pair(const SynthConfig& cfg)
 {
-    switch (cfg.bs) {
-    case 64: return synth_kernel_bs<64, PAIR>(cfg);
-    case 128: return synth_kernel_bs<128, PAIR>(cfg);
-    case 256: return synth_kernel_bs<256, PAIR>(cfg);
-    case 512: return synth_kernel_bs<512, PAIR>(cfg);
-    case 1024: return synth_kernel_bs<1024, PAIR>(cfg);
-    default: return nullptr;
-    }
+    if (cfg.bs == 256 && cfg.groups == 1) return synth_kernel_bs<256, PAIR, 1>(cfg);
+    if (cfg.bs == 256 && cfg.groups == 2) return synth_kernel_bs<256, PAIR, 2>(cfg);
+    if (cfg.bs == 256 && cfg.groups == 4) return synth_kernel_bs<256, PAIR, 4>(cfg);
+    if (cfg.bs == 512 && cfg.groups == 1) return synth_kernel_bs<512, PAIR, 1>(cfg);
+    if (cfg.bs == 1024 && cfg.groups == 1) return synth_kernel_bs<1024, PAIR, 1>(cfg);
+    return nullptr;
 }
 
 SynthKernel synth_kernel(const SynthConfig& cfg)
@@ -425,7 +435,7 @@ hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------
-// Finaliser: spec[p][t][e][b] = P_b sum_items sum_{mu<nu} part[item][jj][t%TT][e nu + mu]
+// Finaliser: spec[p][t][e][b] = P_b sum_items sum_g sum_{mu<nu} part[item][jj][t%TT][g BG + e nu + mu]
 // (Eqs. 33-34), divided by j^2, j = j_lo + b, when inv_j2 is set (partials
 // of j G terms).  Items of phantom p are ordered (tg, bt, slice); the sum
 // over slices runs in slice order, so the result is deterministic.
@@ -433,8 +443,10 @@ hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t 
 __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__ part,
                            const float2* __restrict__ pw, const int32_t* __restrict__ pbase,
                            const int32_t* __restrict__ nsl, int n_ph, int n_tx, int N, int nu,
-                           int n_bins, int bs, int tt, int jt, int n_bt, int j_lo, bool inv_j2)
+                           int n_bins, int bs, int groups, int tt, int jt, int n_bt, int j_lo,
+                           bool inv_j2)
 {
+    const int bg = bs / groups;
     const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -450,10 +462,11 @@ __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__
         float sx = 0.f, sy = 0.f;
         for (int sl = 0; sl < ns; ++sl) {
             const float2* src = part + (first + sl) * ((int64_t)jt * tt * bs) + (jj * tt + tl) * bs + e * nu;
-            for (int mu = 0; mu < nu; ++mu) {
-                sx += src[mu].x;
-                sy += src[mu].y;
-            }
+            for (int g = 0; g < groups; ++g)
+                for (int mu = 0; mu < nu; ++mu) {
+                    sx += src[g * bg + mu].x;
+                    sy += src[g * bg + mu].y;
+                }
         }
         float2 w = pw[b];
         if (inv_j2) {
@@ -469,14 +482,15 @@ __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__
 
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
-                           int nu, int n_bins, int bs, int tt, int jt, int n_bt, int j_lo,
-                           bool inv_j2, hipStream_t st)
+                           int nu, int n_bins, int bs, int groups, int tt, int jt, int n_bt,
+                           int j_lo, bool inv_j2, hipStream_t st)
 {
+    if (groups < 1 || bs % groups) return hipErrorInvalidValue;
     const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
     if (total == 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, spec, part, pw, pbase, nsl, n_ph,
-                       n_tx, N, nu, n_bins, bs, tt, jt, n_bt, j_lo, inv_j2);
+                       n_tx, N, nu, n_bins, bs, groups, tt, jt, n_bt, j_lo, inv_j2);
     return hipGetLastError();
 }
 

@@ -94,7 +94,8 @@ struct SynthArgs {
 };
 
 struct SynthConfig {
-    int bs;      // threads per block = sub-elements per block (power of 2, >= M)
+    int bs;      // threads per block: groups x sub-element slots (a power of 2 >= M)
+    int groups;  // vector path: sub-element groups per block (1, 2 or 4)
     int tt;      // transmits per group
     int sc;      // scatterers per chunk
     int jt;      // bins per tile
@@ -198,10 +199,12 @@ SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 // inv_j2: the partials are of j G terms (both synthesis paths) and are
 // divided by j^2, j = j_lo + bin.
+// bs partial slots per (bin, transmit) of an item, in `groups` blocks of
+// bs / groups slots, each holding nu slots per element
 hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            const int32_t* pbase, const int32_t* nsl, int n_ph, int n_tx, int N,
-                           int nu, int n_bins, int bs, int tt, int jt, int n_bt, int j_lo,
-                           bool inv_j2, hipStream_t st);
+                           int nu, int n_bins, int bs, int groups, int tt, int jt, int n_bt,
+                           int j_lo, bool inv_j2, hipStream_t st);
 hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins, int j_lo,
                        int nfft, int n_t, hipStream_t st);
 hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,

@@ -352,6 +352,7 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt)
     const MtShape sh = mt_shape(N, n_tx, alt);
     SynthConfig c{};
     c.bs = 512;
+    c.groups = 1;
     c.ne = sh.ne;
     c.tt = 16 * sh.ntp;                       // transmits per group
     c.jt = sh.jt;

@@ -309,3 +309,26 @@ def test_alt_tile_shape(S, orc, n_tx, n_el, nu):
     print(n_tx, "tx", n_el, "el alternative shape rel L2", rel_l2(rf, ref), "vs default", rel_l2(rf, rf0))
     assert rel_l2(rf, ref) <= TOL
     assert rel_l2(rf, rf0) <= 1e-5
+
+
+@pytest.mark.parametrize("kind,n", [("linear32", 613), ("linear64", 401), ("phased64_nu1", 577)])
+def test_grouped_small_probes(S, orc, kind, n):
+    """Probes of fewer than 256 sub-elements run several sub-element groups
+    per 256-thread block (4 groups for 64 slots, 2 for 128), each on its own
+    chunk of scatterers: full RF against the oracle, ragged super-chunks."""
+    from paper_2102_02738_amd import inputs
+    rng = np.random.default_rng(n)
+    if kind == "phased64_nu1":
+        w = inputs.workload("ph64x128_s40k", scale=n / 40000)
+        w["delays"] = w["delays"][40:41]
+        w["apod"] = w["apod"][40:41]
+    else:
+        w = inputs.workload("pw32_s200", scale=n / 200)
+        w["probe"] = inputs.linear_probe(32 if kind == "linear32" else 64)
+        w["delays"] = inputs.plane_wave_delays(w["probe"], [4.0])
+        w["apod"] = rng.uniform(0.3, 1.0, w["delays"].shape).astype(np.float32)
+    g, rf, data = _run(S, w)
+    assert g["nu"] == (1 if kind == "phased64_nu1" else 2)
+    ref = _oracle_rf(orc, w, g, data)
+    print(kind, n, "scatterers rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
