@@ -332,3 +332,5 @@ def test_grouped_small_probes(S, orc, kind, n):
     ref = _oracle_rf(orc, w, g, data)
     print(kind, n, "scatterers rel L2", rel_l2(rf, ref))
     assert rel_l2(rf, ref) <= TOL
+    _, rf_static, _ = _run(S, w, flags=S.FLAG_STATIC)
+    assert np.array_equal(rf, rf_static)
