@@ -104,7 +104,8 @@ __device__ __forceinline__ SubFrame load_frame(const SubGeo& g, int n)
 //   qd = (dr / d xi) / (2 r^2)     (dq = k qd for y = 0).
 // c, dc carry cos(j theta) by the same recurrence as s (for sinc'(u)).
 struct GeoD {
-    float la[3], rd[3], ud[3], qd[3];
+    float la[3], rd[3], ud[3];
+    float hq;     // 1 / (2 r^2): dq/dr per unit wavenumber
     float c, dc;
     float inv_theta;
     float r, y;
@@ -197,8 +198,8 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
             D->la[a] = ok ? dobl * dct * inv_obl - apow * dr * inv_r : 0.f;
             D->rd[a] = ok ? dr : 0.f;
             D->ud[a] = ok ? K.b_sub * dst : 0.f;
-            D->qd[a] = ok ? 0.5f * dr * inv_r * inv_r : 0.f;
         }
+        D->hq = 0.5f * inv_r * inv_r;
         D->c = cos_turns(jf0 * sigma);
         D->dc = -theta * sin_turns((jf0 - 0.5f) * sigma) * sh;
         D->inv_theta = (theta != 0.f) ? rcp_fast(theta) : 0.f;
@@ -403,24 +404,32 @@ __device__ __forceinline__ float2 green_grad_next(const ModelConst& K, Geo& g, G
     const float2 Gv = cmul(A, dl);
     const float2 Ed = cmul(g.E, dl);
     const float dsn = (D.c - sn) * inv_j * D.inv_theta;    // sinc'(u)
+    // d delta / dr, through q = (k/2)(1/R_f - 1/r): dq/dr = k / (2 r^2)
+    float2 ddr;
+    if (TABLE) {
+        const float s = k * D.hq;
+        ddr = make_float2(d_dq.x * s, d_dq.y * s);
+    } else {
+        ddr = d_r;
+    }
+    // everything in dG/dr but the obliquity: (i k - k_a) G + A d delta/dr;
+    // a coordinate's gradient is then G la + Rr dr/dxi + Ed sinc' k du/dxi
+    float2 Rr = cmul(A, ddr);
+    Rr.x = fmaf(-ka, Gv.x, fmaf(-k, Gv.y, Rr.x));
+    Rr.y = fmaf(-ka, Gv.y, fmaf(k, Gv.x, Rr.y));
+    const float su = dsn * k;
+    const float2 Q = make_float2(Ed.x * su, Ed.y * su);
     constexpr int idx[3] = {0, 2, 1};                      // X, Z, Y
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
         const int a = idx[i];
-        const float2 phi = make_float2(D.la[a] - ka * D.rd[a], k * D.rd[a]);
-        float2 v = cmul(Gv, phi);
-        const float su = dsn * k * D.ud[a];
-        v.x = fmaf(Ed.x, su, v.x);
-        v.y = fmaf(Ed.y, su, v.y);
-        float2 dd;
-        if (TABLE) {
-            const float s = k * D.qd[a];
-            dd = make_float2(d_dq.x * s, d_dq.y * s);
-        } else {
-            dd = make_float2(d_r.x * D.rd[a] + (a == 1 ? d_y.x : 0.f),
-                             d_r.y * D.rd[a] + (a == 1 ? d_y.y : 0.f));
-        }
-        dG[i] = cfma(A, dd, v);
+        float2 v = make_float2(Gv.x * D.la[a], Gv.y * D.la[a]);
+        v.x = fmaf(Rr.x, D.rd[a], v.x);
+        v.y = fmaf(Rr.y, D.rd[a], v.y);
+        v.x = fmaf(Q.x, D.ud[a], v.x);
+        v.y = fmaf(Q.y, D.ud[a], v.y);
+        if (!TABLE && a == 1) v = cfma(A, d_y, v);
+        dG[i] = v;
     }
     g.E = cmul(g.E, g.dE);
     g.d = fmaf(g.lam, g.s, g.d);
