@@ -159,6 +159,12 @@ def test_device_entry_points_validate_before_gpu(L):
                       pd, pa, 2, bad.ctypes.data_as(C.POINTER(C.c_int64)), fake, None, fake, fake,
                       fake, None)
     assert rc == -1 and b"non-decreasing" in lib.simus_last_error()
+    # work items index scatterers with int32: 2^31 scatterers are rejected
+    huge = np.array([0, 1 << 31], dtype=np.int64)
+    rc = lib.simus_rf(C.byref(P), C.byref(M), C.byref(L.make_options(w["options"], nfft=1280)), 1,
+                      pd, pa, 1, huge.ctypes.data_as(C.POINTER(C.c_int64)), fake, None, fake, fake,
+                      fake, None)
+    assert rc == -1 and b"too many scatterers" in lib.simus_last_error()
     rc = lib.simus_spectrum_to_rf(1001, 10, 1, 4, 1, fake, fake, None)
     assert rc == -1
     rc = lib.simus_spectrum_to_rf(1000, 10, 499, 4, 1, fake, fake, None)
