@@ -143,11 +143,15 @@ __global__ void k_adjoint_reduce(const float4* __restrict__ part, int n_ranges, 
     }
 }
 
-// Lam in the layout [p][b][t][e] from dL/drf [p][t][e][q].
+// Lam in the layout [p][b][t][e] from dL/drf [p][t][e][q]: lam = sum_q rho[q]
+// e^{-2 pi i j q / nfft}.  Thread = bin; the phase factor is stepped from
+// sample to sample by e^{2 pi i j / nfft} and re-anchored every 32 samples
+// from the exact integer angle index j q mod nfft.
 __global__ __launch_bounds__(256) void k_dft_t(float2* __restrict__ lam, const float* __restrict__ rho,
                                                int64_t ch0, int n_bins, int j_lo, int nfft, int n_t,
                                                int n_tx, int N)
 {
+    constexpr int ANCHOR = 32;
     __shared__ float s_r[8192];
     const int64_t ch = ch0 + blockIdx.y;
     const float* R = rho + ch * n_t;
@@ -156,20 +160,27 @@ __global__ __launch_bounds__(256) void k_dft_t(float2* __restrict__ lam, const f
     const int j = (j_lo + (live ? b : 0)) % nfft;
     const float inv_n = 1.f / (float)nfft;
     const int half = nfft / 2;
-    int m = 0;
+    auto turns = [&](int m) { return (float)(m >= half ? m - nfft : m) * inv_n; };
+    const float dc = cos_turns(turns(j)), ds = sin_turns(turns(j));   // per-sample step
+    int m = 0;                                     // j q mod nfft at the next sample
     float re = 0.f, im = 0.f;
     for (int c0 = 0; c0 < n_t; c0 += 8192) {
         const int cn = min(8192, n_t - c0);
         __syncthreads();
         for (int q = threadIdx.x; q < cn; q += blockDim.x) s_r[q] = R[c0 + q];
         __syncthreads();
-        for (int q = 0; q < cn; ++q) {
-            const float tt = (float)(m >= half ? m - nfft : m) * inv_n;
-            const float v = s_r[q];
-            re = fmaf(v, cos_turns(tt), re);
-            im = fmaf(-v, sin_turns(tt), im);
-            m += j;
-            if (m >= nfft) m -= nfft;
+        for (int q0 = 0; q0 < cn; q0 += ANCHOR) {
+            const int nq = min(ANCHOR, cn - q0);
+            float ec = cos_turns(turns(m)), es = sin_turns(turns(m));
+            for (int q = 0; q < nq; ++q) {
+                const float v = s_r[q0 + q];
+                re = fmaf(v, ec, re);
+                im = fmaf(-v, es, im);
+                const float c1 = ec * dc - es * ds;
+                es = fmaf(es, dc, ec * ds);
+                ec = c1;
+            }
+            m = (int)(((int64_t)m + (int64_t)nq * j) % nfft);
         }
     }
     if (live) {

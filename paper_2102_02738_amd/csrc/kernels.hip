@@ -496,12 +496,15 @@ hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
 
 // ---------------------------------------------------------------------------
 // Inverse transform (Eq. 1): rf[c][q] = sum_b Re(spec[c][b] e^{-2 pi i j q / nfft}),
-// j = j_lo + b.  The angle index j q mod nfft is carried exactly in integers
-// and turned into turns in [-1/2, 1/2) for the hardware sine/cosine.  One
-// block per (channel, 256 samples); the channel's spectrum is staged in LDS
-// in chunks.
+// j = j_lo + b.  Thread = sample q; the phase factor of bin j is stepped to
+// bin j + 1 by one complex product with e^{2 pi i q / nfft} and re-anchored
+// every IDFT_ANCHOR bins from the exact integer angle index j q mod nfft
+// (hardware sine/cosine of turns in [-1/2, 1/2)), so rounding grows over at
+// most IDFT_ANCHOR steps.  One block per (channel, 256 samples); the
+// channel's spectrum is staged in LDS in chunks.
 // ---------------------------------------------------------------------------
 constexpr int DFT_CHUNK = 4096;
+constexpr int IDFT_ANCHOR = 32;
 
 __global__ __launch_bounds__(256) void k_idft(float* __restrict__ rf, const float2* __restrict__ spec,
                                               int64_t ch0, int n_bins, int j_lo, int nfft, int n_t)
@@ -511,34 +514,36 @@ __global__ __launch_bounds__(256) void k_idft(float* __restrict__ rf, const floa
     const float2* X = spec + ch * n_bins;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = q < n_t;
-    const int qq = live ? q : 0;
+    const int qn = (live ? q : 0) % nfft;
     const float inv_n = 1.f / (float)nfft;
     const int half = nfft / 2;
-    int m = (int)(((int64_t)j_lo * qq) % nfft);
+    auto turns = [&](int m) { return (float)(m >= half ? m - nfft : m) * inv_n; };
+    // per-bin step of the phase: 2 pi q / nfft
+    const float dc = cos_turns(turns(qn)), ds = sin_turns(turns(qn));
+    int m = (int)(((int64_t)j_lo * qn) % nfft);   // j q mod nfft at the next bin
     float acc0 = 0.f, acc1 = 0.f;
     for (int c0 = 0; c0 < n_bins; c0 += DFT_CHUNK) {
         const int cn = min(DFT_CHUNK, n_bins - c0);
         __syncthreads();
         for (int b = threadIdx.x; b < cn; b += blockDim.x) s_x[b] = X[c0 + b];
         __syncthreads();
-        int b = 0;
-        for (; b + 1 < cn; b += 2) {
-            const int m1 = (m + qq >= nfft) ? m + qq - nfft : m + qq;
-            const float t0 = (float)(m >= half ? m - nfft : m) * inv_n;
-            const float t1 = (float)(m1 >= half ? m1 - nfft : m1) * inv_n;
-            const float2 x0 = s_x[b], x1 = s_x[b + 1];
-            acc0 = fmaf(x0.x, cos_turns(t0), acc0);
-            acc0 = fmaf(x0.y, sin_turns(t0), acc0);
-            acc1 = fmaf(x1.x, cos_turns(t1), acc1);
-            acc1 = fmaf(x1.y, sin_turns(t1), acc1);
-            m = (m1 + qq >= nfft) ? m1 + qq - nfft : m1 + qq;
-        }
-        if (b < cn) {
-            const float t0 = (float)(m >= half ? m - nfft : m) * inv_n;
-            const float2 x0 = s_x[b];
-            acc0 = fmaf(x0.x, cos_turns(t0), acc0);
-            acc0 = fmaf(x0.y, sin_turns(t0), acc0);
-            m = (m + qq >= nfft) ? m + qq - nfft : m + qq;
+        for (int b0 = 0; b0 < cn; b0 += IDFT_ANCHOR) {
+            const int nb = min(IDFT_ANCHOR, cn - b0);
+            float ec = cos_turns(turns(m)), es = sin_turns(turns(m));
+            int b = 0;
+            for (; b + 1 < nb; b += 2) {
+                const float2 x0 = s_x[b0 + b], x1 = s_x[b0 + b + 1];
+                acc0 = fmaf(x0.x, ec, fmaf(x0.y, es, acc0));
+                float c1 = ec * dc - es * ds, s1 = fmaf(es, dc, ec * ds);
+                acc1 = fmaf(x1.x, c1, fmaf(x1.y, s1, acc1));
+                ec = c1 * dc - s1 * ds;
+                es = fmaf(s1, dc, c1 * ds);
+            }
+            if (b < nb) {
+                const float2 x0 = s_x[b0 + b];
+                acc0 = fmaf(x0.x, ec, fmaf(x0.y, es, acc0));
+            }
+            m = (int)(((int64_t)m + (int64_t)nb * qn) % nfft);
         }
     }
     if (live) rf[ch * n_t + q] = acc0 + acc1;
@@ -551,51 +556,6 @@ hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins
     for (int64_t c0 = 0; c0 < n_chan; c0 += 65535) {
         const unsigned nc = (unsigned)std::min<int64_t>(65535, n_chan - c0);
         hipLaunchKernelGGL(k_idft, dim3((n_t + 255) / 256, nc), dim3(256), 0, st, rf, spec, c0,
-                           n_bins, j_lo, nfft, n_t);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-// Adjoint transform: lam[c][b] = sum_q rho[c][q] e^{-2 pi i j q / nfft}.
-__global__ __launch_bounds__(256) void k_dft(float2* __restrict__ lam, const float* __restrict__ rho,
-                                             int64_t ch0, int n_bins, int j_lo, int nfft, int n_t)
-{
-    __shared__ float s_r[2 * DFT_CHUNK];
-    const int64_t ch = ch0 + blockIdx.y;
-    const float* R = rho + ch * n_t;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = b < n_bins;
-    const int j = (j_lo + (live ? b : 0)) % nfft;
-    const float inv_n = 1.f / (float)nfft;
-    const int half = nfft / 2;
-    int m = 0;
-    float re = 0.f, im = 0.f;
-    for (int c0 = 0; c0 < n_t; c0 += 2 * DFT_CHUNK) {
-        const int cn = min(2 * DFT_CHUNK, n_t - c0);
-        __syncthreads();
-        for (int q = threadIdx.x; q < cn; q += blockDim.x) s_r[q] = R[c0 + q];
-        __syncthreads();
-        for (int q = 0; q < cn; ++q) {
-            const float t = (float)(m >= half ? m - nfft : m) * inv_n;
-            const float v = s_r[q];
-            re = fmaf(v, cos_turns(t), re);
-            im = fmaf(-v, sin_turns(t), im);
-            m += j;
-            if (m >= nfft) m -= nfft;
-        }
-    }
-    if (live) lam[ch * n_bins + b] = make_float2(re, im);
-}
-
-hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,
-                      int nfft, int n_t, hipStream_t st)
-{
-    if (n_chan == 0 || n_bins == 0) return hipSuccess;
-    for (int64_t c0 = 0; c0 < n_chan; c0 += 65535) {
-        const unsigned nc = (unsigned)std::min<int64_t>(65535, n_chan - c0);
-        hipLaunchKernelGGL(k_dft, dim3((n_bins + 255) / 256, nc), dim3(256), 0, st, lam, rho, c0,
                            n_bins, j_lo, nfft, n_t);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -207,8 +207,6 @@ hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
                            int j_lo, bool inv_j2, hipStream_t st);
 hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins, int j_lo,
                        int nfft, int n_t, hipStream_t st);
-hipError_t launch_dft(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo,
-                      int nfft, int n_t, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
 // Range of sub-element-to-scatterer distances (as float bits, [0] = min,
