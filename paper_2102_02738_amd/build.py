@@ -38,6 +38,9 @@ def _compile(src: str, device: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    # a failed build must not leave an older library behind to be loaded
+    if os.path.exists(OUT):
+        os.remove(OUT)
     srcs = [(s, d) for s, d in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         objs = list(ex.map(lambda sd: _compile(*sd), srcs))

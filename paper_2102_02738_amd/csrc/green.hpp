@@ -253,11 +253,11 @@ __device__ __forceinline__ float2 elevation(const Gauss4& G, float q, float k, f
 // Cubic table of delta(0, r, k) as a function of w = q / (|q| + L):
 // interval k of DELTA_NT holds (c0, c1, c2, c3) complex, delta = c0 + t (c1
 // + t (c2 + t c3)), t in [0, 1).  Stored as two float4 per interval, in two
-// arrays (dtab_a, dtab_b).
-__device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaParams& P, float q)
+// arrays (dtab_a, dtab_b).  Argument qs = q inv_dw / L (see delta_fetch).
+__device__ __forceinline__ float2 delta_table(const float4* tab, const DeltaParams& P, float qs)
 {
-    const float w = q * rcp_fast(fabsf(q) + P.L);
-    const float u = __builtin_amdgcn_fmed3f(fmaf(w, P.inv_dw, P.u0), 0.f, P.umax);
+    const float r = rcp_fast(fmaf(fabsf(qs), P.dw, 1.f));
+    const float u = __builtin_amdgcn_fmed3f(fmaf(qs, r, P.u0), 0.f, P.umax);
     // u >= 0 after the clamp: the conversion truncates to the interval and
     // the hardware fraction gives the local coordinate
     const int k = (int)u;
@@ -463,7 +463,7 @@ __device__ __forceinline__ float2 green_next_fetched(Geo& g, const DeltaFetch& f
 }
 
 // Green's term at absolute bin j (jf = j, inv_j = 1/j); advances the pair to
-// bin j + 1.
+// bin j + 1.  With TABLE the pair's kap must be pre-scaled by P.kscale.
 template <bool HASY, bool TABLE>
 __device__ __forceinline__ float2 green_next(const ModelConst& K, Geo& g, float jf, float inv_j,
                                              const float4* tab, const DeltaParams& P)

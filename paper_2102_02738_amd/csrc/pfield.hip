@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void k_pfield(FieldArgs A)
             const int e = n / A.nu;
             Geo g = make_geo<HASY>(A.K, fr, px, py, pz, A.j_lo + jb0);
             if (!live) g.E = make_float2(0.f, 0.f);
+            if (TABLE) g.kap *= P.kscale;              // the table lookup's argument
 #pragma unroll
             for (int jj = 0; jj < JT; ++jj) {
                 const int jb = jb0 + jj;
