@@ -124,7 +124,9 @@ typedef struct {
                                         elements) or 64 instead of 32 (64 or fewer); vector
                                         path: single transmits instead of pairs, or pairs
                                         instead of single transmits.  The autotuner tries
-                                        it; the results agree to rounding order */
+                                        it.  simus_rf_backward: the other of its two kernels
+                                        (matrix-core or vector) where both apply.  The
+                                        results agree to rounding order */
 /* Other bits of options.flags are rejected with SIMUS_EINVAL. */
 
 /* Frequency grid of one call. */

@@ -605,8 +605,16 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     if (!dR && !dX && !dY && !dZ) return;
     if (C.ph.total == 0) return;
     const int N = C.P.N;
-    const bool use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && adjoint_mt_supported(C.P.M, N, n_tx) &&
-                        C.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
+    const bool mt_ok = !(opt->flags & SIMUS_FLAG_NO_MFMA) && adjoint_mt_supported(C.P.M, N, n_tx) &&
+                       C.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
+    // The matrix-core adjoint pads transmits to groups of 8 and elements to
+    // 128 slots; below N n_tx = 384, or under 48 elements, the vector kernel
+    // measured faster (50k scatterers, 128 elements: 1 transmit 32 vs 58 ms,
+    // 3 transmits 73 vs 61; 64 elements: 4 transmits 31 vs 54, 6-8 equal;
+    // 32 elements, 8 transmits: 26 vs 52).  SIMUS_FLAG_ALT_SHAPE takes the
+    // other kernel where both apply.
+    const bool mt_pref = N >= 48 && int64_t(N) * n_tx >= 384;
+    const bool use_mt = mt_ok && (((opt->flags & SIMUS_FLAG_ALT_SHAPE) != 0) != mt_pref);
     AdjConfig cfg = use_mt ? adjoint_mt_config(C.P.M, N, n_tx, C.has_y) : adjoint_config(n_tx, C.has_y);
     cfg.table = C.table;
     // items: (phantom, scatterer slice, bin range); about 3000 items (matrix-core

@@ -71,11 +71,19 @@ def _check(got, ref, keys):
         assert e <= TOL, (k, e)
 
 
+# "alt" runs the other adjoint kernel (SIMUS_FLAG_ALT_SHAPE): these small
+# probes take the vector kernel by default, the matrix-core one with it
+PATHS = ["default", "alt"]
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("with_y,convex,baffle,flags", [
     (False, False, 0, 0), (False, False, 0, 4), (True, False, 0, 0), (False, True, 2, 0),
     (False, False, 1, 0)])
-def test_adjoint_matches_oracle_adjoint(S, orc, with_y, convex, baffle, flags):
+def test_adjoint_matches_oracle_adjoint(S, orc, with_y, convex, baffle, flags, path):
     w = small(with_y=with_y, convex=convex, baffle=baffle)
+    if path == "alt":
+        flags |= S.FLAG_ALT_SHAPE
     x, y, z, R, off = concat_phantoms(w["phantoms"])
     g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, y if with_y else None, z)
     rho = np.random.default_rng(7).standard_normal((1, len(w["delays"]), w["probe"]["n_elements"],
@@ -85,13 +93,14 @@ def test_adjoint_matches_oracle_adjoint(S, orc, with_y, convex, baffle, flags):
     _check(got, ref, ["refl", "x", "z"] + (["y"] if with_y else []))
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n_tx", [1, 3, 5, 9])
-def test_adjoint_transmit_groups(S, orc, n_tx):
+def test_adjoint_transmit_groups(S, orc, n_tx, path):
     w = small(n_tx=n_tx, n_scat=30)
     x, y, z, R, off = concat_phantoms(w["phantoms"])
     g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
     rho = np.random.default_rng(n_tx).standard_normal((1, n_tx, 8, g0["n_t"])).astype(np.float32)
-    g, got = gpu_grads(S, w, rho)
+    g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
     ref = oracle_grads(orc, w, g, rho[0])
     _check(got, ref, ["refl", "x", "z"])
 
