@@ -49,12 +49,12 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int NSG = NB / MS;            // scatterer groups
-    constexpr int BST = NE + 4;             // row stride of the element sums
+    constexpr int BST = NE + 2;             // row stride of the element sums
     constexpr int TPG = 16 * NTP;           // transmit columns of the group
     constexpr int KP = 8 / NTP;             // element shares per column tile
     constexpr int KW = NE / KP;             // elements per wave
     constexpr int KS = KW / 4;              // transmit-GEMM k-steps per wave
-    constexpr int WS = NE + 1;              // row stride of the staged weights
+    constexpr int WS = NE + 2;              // row stride of the staged weights
     constexpr int RXE = NE / 16;            // receive element tiles
     constexpr int CS = 8 / RXE;             // waves per element tile (column split)
     constexpr int CPW = NTP / CS;           // receive column tiles per wave
@@ -63,12 +63,26 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(NX == 2 || NX == 3, "receive sums: (Re, Im) or three products");
     static_assert(PPT * NSG == SCH, "synthesis threads must cover the chunk");
+    // LDS layouts free of bank conflicts (64 banks of 4 bytes; a wave's 8-byte
+    // accesses are served 32 lanes at a time, its 4-byte ones 64):
+    //  - element sums and weights with rows NE + 2 apart, for the transmit
+    //    GEMM (lanes: 16 rows, 2 columns; the receive GEMM's reads of the sums,
+    //    16 columns by 2 rows, meet 2-way conflicts: a swizzle that also
+    //    serves them costs registers for per-step addresses);
+    //  - product tiles per lane with register v rows PV apart and waves PB
+    //    apart, so that the share sums read 64 distinct banks;
+    //  - scaled sums c with rows CST = 16 (mod 32) apart (lanes: 16 columns,
+    //    2 rows).
+    constexpr int PV = 80;
+    constexpr int PS = 4 * PV;              // stride of a product
+    constexpr int PB = 3 * PS + (NTP == 2 ? 32 : NTP == 4 ? 16 : 0);
+    constexpr int CST = TPG % 32 == 16 ? TPG : TPG + 16;
 
     __shared__ float4 s_sc[SCH];
     __shared__ float2 s_B[2 * SCH * BST];   // element sums, two buffers
     __shared__ float2 s_W[TPG * WS];
-    __shared__ float s_part[8][3][256];
-    __shared__ float2 s_c[SCH][TPG];
+    __shared__ float s_part[8 * PB];
+    __shared__ float2 s_c[SCH * CST];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
     const int tid = threadIdx.x;
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 for (int k = 0; k < PPT; ++k) {
                     const int s = sh * PPT + k;
                     if (NUV == 2) {
-                        // both lanes of the pair store the same element sum
+                        // both lanes of the pair store the same sum (no extra LDS cost)
                         const float bx = G[k].x + __int_as_float(__builtin_amdgcn_mov_dpp(
                                                       __float_as_int(G[k].x), 0xB1, 0xF, 0xF, true));
                         const float by = G[k].y + __int_as_float(__builtin_amdgcn_mov_dpp(
@@ -225,26 +239,28 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int d = (4 * gk + v) * 16 + gi;
-                        s_part[wave][0][d] = p1[v];
-                        s_part[wave][1][d] = p2[v];
-                        s_part[wave][2][d] = p3[v];
+                        float* sp = s_part + wave * PB + v * PV + lane;
+                        sp[0] = p1[v];
+                        sp[PS] = p2[v];
+                        sp[2 * PS] = p3[v];
                     }
                 }
                 __syncthreads();
                 // 3. sum the shares (fixed order), combine, scale by R_s
                 for (int idx = tid; idx < SCH * TPG; idx += NB) {
                     const int s = idx / TPG, t = idx % TPG;
-                    const int c = t >> 4, d = s * 16 + (t & 15);
+                    // row s of a tile = 4 (lane / 16) + v of the wave that wrote it
+                    const int c = t >> 4, d = (s & 3) * PV + (s >> 2) * 16 + (t & 15);
                     float q1 = 0.f, q2 = 0.f, q3 = 0.f;
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {
-                        q1 += s_part[k * NTP + c][0][d];
-                        q2 += s_part[k * NTP + c][1][d];
-                        q3 += s_part[k * NTP + c][2][d];
+                        const float* sp = s_part + (k * NTP + c) * PB + d;
+                        q1 += sp[0];
+                        q2 += sp[PS];
+                        q3 += sp[2 * PS];
                     }
                     const float R = s_sc[s].w;
-                    s_c[s][t] = make_float2(R * (q1 - q2), R * (q3 - q1 - q2));
+                    s_c[s * CST + t] = make_float2(R * (q1 - q2), R * (q3 - q1 - q2));
                 }
                 __syncthreads();
                 // 4. receive GEMM: X[e][t] += sum_s B[e][s] c[s][t], rows
@@ -256,7 +272,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                         const int s = 4 * k + gk;
                         ba[k] = sB[s * BST + mt_e + gi];
 #pragma unroll
-                        for (int c = 0; c < CPW; ++c) ca[k][c] = s_c[s][(rc0 + c) * 16 + gi];
+                        for (int c = 0; c < CPW; ++c) ca[k][c] = s_c[s * CST + (rc0 + c) * 16 + gi];
                     }
 #pragma unroll
                     for (int k = 0; k < SCH / 4; ++k)
