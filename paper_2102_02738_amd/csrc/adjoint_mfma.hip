@@ -17,7 +17,10 @@
 // per 32 bins and stepped across them (green.hpp).
 //
 // Block: 512 threads (8 waves), chunks of 8 scatterers (32 rows, two row
-// tiles); work item = (phantom, scatterer slice, bin range).
+// tiles); work item = (phantom, scatterer slice, bin range).  With y = 0 the
+// rows dB/dy are zero, and for nu = 2 a chunk takes 10 scatterers of three
+// rows instead (30 of the 32 rows), so that one GEMM serves 25 % more
+// scatterers.
 //   Synthesis: thread = (sub-element n, group of PPT scatterers): G and its
 //     gradient, element sums by one DPP exchange (nu = 2).
 //   GEMM: wave = (row tile, share of the elements); three product tiles per
@@ -45,15 +48,18 @@ __device__ __forceinline__ float dpp_xor1(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
 }
 
+// Scatterers per chunk: 10 of three rows for nu = 2 and y = 0, else 8 of four.
+constexpr int adj_mt_chunk(int nuv, bool hasy) { return nuv == 2 && !hasy ? 10 : 8; }
+
 template <int NTC, int NUV, bool HASY, bool TABLE>
 __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
 {
     constexpr int NB = 512;
     constexpr int NE = 128;                 // element slots
     constexpr int MS = NE * NUV;            // sub-element slots
-    constexpr int SCH = 8;                  // scatterers per chunk
-    constexpr int NL = 4;                   // rows per scatterer: B, dB/dx, dB/dz, dB/dy
-    constexpr int ROWS = SCH * NL;          // 32
+    constexpr int SCH = adj_mt_chunk(NUV, HASY);   // scatterers per chunk
+    constexpr int NL = SCH == 10 ? 3 : 4;   // rows per scatterer: B, dB/dx, dB/dz(, dB/dy)
+    constexpr int ROWS = 32;                // SCH NL rows, the rest zero
     constexpr int RT = ROWS / 16;           // row tiles
     constexpr int KP = 8 / RT;              // element shares per row tile
     constexpr int KW = NE / KP;             // elements per wave
@@ -61,18 +67,25 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
     constexpr int TG = 8 * NTC;             // transmits
     constexpr int NC = 2 * TG;              // columns: W, then Lam
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
-    constexpr int LST = NE + 4;             // row stride of the element sums
-    constexpr int WS = NE + 1;              // row stride of the staged columns
+    // LDS strides free of bank conflicts for the GEMM's reads (lanes: 16 rows,
+    // 2 columns, rows NE + 2 apart) and for the product tiles (per lane, the
+    // accumulator registers v rows PV apart, column tiles PC apart)
+    constexpr int LST = NE + 2;             // row stride of the element sums
+    constexpr int WS = NE + 2;              // row stride of the staged columns
+    constexpr int PV = 80;
+    constexpr int PC = 4 * PV + 32;         // per column tile
+    constexpr int PP = NTC * PC;            // per product
     constexpr int JS = 32;                  // bins per set-up
     constexpr int NX = HASY ? 3 : 2;        // coordinates: X, Z (, Y)
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * (NB / MS) == SCH, "synthesis threads must cover the chunk");
+    static_assert(SCH * NL <= ROWS, "rows of a chunk");
     static_assert(NC * NE % NB == 0, "column staging must divide evenly");
 
     __shared__ float4 s_sc[SCH];
     __shared__ float2 s_L[ROWS * LST];
     __shared__ float2 s_WL[NC * WS];
-    __shared__ float s_part[8][3][256 * NTC];
+    __shared__ float s_part[8][3 * PP];
     __shared__ float2 s_V[ROWS][NC];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
@@ -94,8 +107,9 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
         for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
         P = *A.dpar;
     }
-    if (!HASY)   // rows dB/dy stay zero
-        for (int i = tid; i < SCH * LST; i += NB) s_L[((i / LST) * NL + 3) * LST + i % LST] = make_float2(0.f, 0.f);
+    // rows that no scatterer fills (dB/dy for y = 0 with 8-scatterer chunks,
+    // rows 30 and 31 with 10) stay zero
+    for (int i = tid; i < ROWS * LST; i += NB) s_L[i] = make_float2(0.f, 0.f);
 
     const AdjItem it = A.items[blockIdx.x];
     const int b_begin = it.range * A.range_bins;
@@ -189,12 +203,13 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                             p2 = mfma_a(la[k].y, wa[k].y, p2);
                             p3 = mfma_a(la[k].x + la[k].y, wa[k].x + wa[k].y, p3);
                         }
+                        // D[row][col]: col = lane % 16, row = 4 (lane / 16) + v
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int d = ct * 256 + (4 * gk + v) * 16 + gi;
-                            s_part[wave][0][d] = p1[v];
-                            s_part[wave][1][d] = p2[v];
-                            s_part[wave][2][d] = p3[v];
+                            float* q = &s_part[wave][ct * PC + v * PV + lane];
+                            q[0] = p1[v];
+                            q[PP] = p2[v];
+                            q[2 * PP] = p3[v];
                         }
                     }
                 }
@@ -202,14 +217,14 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                 // 3. sum the shares (fixed order), combine the three products
                 for (int idx = tid; idx < ROWS * NC; idx += NB) {
                     const int r = idx / NC, col = idx % NC;
-                    const int d = (col >> 4) * 256 + (r & 15) * 16 + (col & 15);
+                    const int d = (col >> 4) * PC + (r & 3) * PV + ((r >> 2) & 3) * 16 + (col & 15);
                     const int w0 = (r >> 4) * KP;
                     float q1 = 0.f, q2 = 0.f, q3 = 0.f;
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {
-                        q1 += s_part[w0 + k][0][d];
-                        q2 += s_part[w0 + k][1][d];
-                        q3 += s_part[w0 + k][2][d];
+                        q1 += s_part[w0 + k][d];
+                        q2 += s_part[w0 + k][PP + d];
+                        q3 += s_part[w0 + k][2 * PP + d];
                     }
                     s_V[r][col] = make_float2(q1 - q2, q3 - q1 - q2);
                 }
@@ -268,8 +283,9 @@ AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y)
     c.mfma = true;
     c.tt = n_tx <= 8 ? 8 : 16;
     c.jt = 32;                // bins per set-up (JS), the bin-range granule
-    c.scatterers = 64;        // per item, a multiple of the 8-scatterer chunk
     c.pair = M == 2 * N;
+    // scatterers per item, a multiple of the chunk
+    c.scatterers = adj_mt_chunk(c.pair ? 2 : 1, has_y) == 10 ? 60 : 64;
     c.has_y = has_y;
     return c;
 }

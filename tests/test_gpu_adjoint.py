@@ -94,6 +94,21 @@ def test_adjoint_matches_oracle_adjoint(S, orc, with_y, convex, baffle, flags, p
 
 
 @pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n_scat", [7, 61, 137])
+def test_adjoint_ragged_chunks(S, orc, n_scat, path):
+    """Scatterer counts that leave a partial chunk (8 or, for nu = 2 and
+    y = 0 on the matrix cores, 10 scatterers) and span one to three items
+    of 60-64 scatterers."""
+    w = small(n_tx=3, n_scat=n_scat, seed=n_scat)
+    x, y, z, R, off = concat_phantoms(w["phantoms"])
+    g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
+    rho = np.random.default_rng(n_scat).standard_normal((1, 3, 8, g0["n_t"])).astype(np.float32)
+    g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    ref = oracle_grads(orc, w, g, rho[0])
+    _check(got, ref, ["refl", "x", "z"])
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n_tx", [1, 3, 5, 9])
 def test_adjoint_transmit_groups(S, orc, n_tx, path):
     w = small(n_tx=n_tx, n_scat=30)
