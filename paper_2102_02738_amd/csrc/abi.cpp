@@ -737,7 +737,7 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     C.table = C.P.dim2 || (!C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE));
     C.ph.n = 1;
     C.ph.total = n_pts;
-    const int JT = 8;
+    const int JT = PFIELD_JT;
     // frequency ranges: about 2000 blocks
     const int64_t n_pb = (n_pts + 255) / 256;
     int64_t rb = (int64_t(n_f) * n_pb + 1999) / 2000;

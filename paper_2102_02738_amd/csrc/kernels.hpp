@@ -172,6 +172,11 @@ struct FieldArgs {
     ModelConst K;
 };
 
+// Frequencies per (point, sub-element) set-up of the field kernel; frequency
+// ranges are a multiple of it.  Timed on the 64-element, 256 x 256-point,
+// 402-frequency field: 8 -> 1.74 ms, 16 -> 1.58 ms, 32 -> 1.66 ms (registers
+// halve the occupancy).
+constexpr int PFIELD_JT = 16;
 hipError_t launch_pfield(const FieldArgs& a, bool has_y, bool table, int n_ranges, hipStream_t st);
 hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, float dw, float* out,
                                 hipStream_t st);

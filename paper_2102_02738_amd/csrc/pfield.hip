@@ -5,8 +5,11 @@
 // The j = 0 node contributes nothing (S_P(0) = 0).
 //
 // One thread owns one field point and loops over all sub-elements for a tile
-// of JT frequencies; blocks cover (256 points, frequency range) and a second
-// kernel sums the ranges in a fixed order.
+// of JT frequencies, so that each (point, sub-element) set-up, with its FP64
+// distance, serves JT terms; blocks cover (256 points, frequency range) and a
+// second kernel sums the ranges in a fixed order.  The tile accumulates j P
+// (terms j G, as in the synthesis), and 1/j^2 is applied to |j P|^2 once per
+// point and frequency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(256) void k_pfield(FieldArgs A)
                 const int jb = jb0 + jj;
                 if (jb < b_end) {
                     const float jf = (float)(A.j_lo + jb);
-                    const float2 G = green_next<HASY, TABLE>(A.K, g, jf, rcp_fast(jf), s_tab, P);
+                    const float2 G = green_next<HASY, TABLE>(A.K, g, jf, 1.f, s_tab, P);   // j G
                     acc[jj] = cfma(A.W[(int64_t)jb * A.N + e], G, acc[jj]);
                 }
             }
@@ -58,8 +61,9 @@ __global__ __launch_bounds__(256) void k_pfield(FieldArgs A)
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
             if (jb0 + jj < b_end) {
+                const float inv_j = 1.f / (float)(A.j_lo + jb0 + jj);
                 const float2 v = cmul(A.ptx[jb0 + jj], acc[jj]);
-                sum = fmaf(v.x, v.x, fmaf(v.y, v.y, sum));
+                sum = fmaf(fmaf(v.x, v.x, v.y * v.y), inv_j * inv_j, sum);
             }
         }
     }
@@ -90,7 +94,7 @@ hipError_t launch_pfield(const FieldArgs& a, bool has_y, bool table, int n_range
 {
     if (a.n_pts == 0 || n_ranges == 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n_pts + 255) / 256), (unsigned)n_ranges);
-    return launch_pf<8>(a, has_y, table, grid, st);
+    return launch_pf<PFIELD_JT>(a, has_y, table, grid, st);
 }
 
 hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, float dw, float* out,

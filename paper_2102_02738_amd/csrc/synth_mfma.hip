@@ -20,9 +20,10 @@
 //     elements); its three product tiles go to LDS and are summed over the
 //     shares in a fixed order, scaled by R_s, into c[s][t].
 //   Receive GEMM: wave w owns elements 16 w .. 16 w + 15 and all column tiles.
-// Barriers per bin: after synthesis, after the transmit GEMM, after the
-// reduction.  The element sums are double-buffered, so the next bin's
-// synthesis may start while other waves still run this bin's receive GEMM.  Partial spectra of every item, per element, go to `part`
+// The steps are software-pipelined over the item's (chunk, bin) sequence with
+// two barriers per bin: [reduction of the previous bin, synthesis] and
+// [receive GEMM of the previous bin, transmit GEMM]; the element sums are
+// double-buffered by bin.  Partial spectra of every item, per element, go to `part`
 // ([item][JT][TPG][N]); like the vector path the terms are j G, and the
 // finaliser divides by j^2.
 #include <hip/hip_runtime.h>
@@ -63,6 +64,8 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(NX == 2 || NX == 3, "receive sums: (Re, Im) or three products");
     static_assert(PPT * NSG == SCH, "synthesis threads must cover the chunk");
+    static_assert(JT % 2 == 0, "the element sums alternate between two buffers by bin");
+    constexpr int NRED = (SCH * TPG + NB - 1) / NB;     // reduction outputs per thread
     // LDS layouts free of bank conflicts (64 banks of 4 bytes; a wave's 8-byte
     // accesses are served 32 lanes at a time, its 4-byte ones 64):
     //  - element sums and weights with rows NE + 2 apart, for the transmit
@@ -129,6 +132,71 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 #pragma unroll
                 for (int q = 0; q < NX; ++q) X[jj][c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+        // 3. the partial products of a bin -> c[s][t] = R_s (sum over the
+        //    element shares, in a fixed order, of the three products combined)
+        auto reduce = [&](const float (&R)[NRED]) {
+#pragma unroll
+            for (int q = 0; q < NRED; ++q) {
+                const int idx = tid + q * NB;
+                if (idx < SCH * TPG) {
+                    const int s = idx / TPG, t = idx % TPG;
+                    // row s of a tile = 4 (lane / 16) + v of the wave that wrote it
+                    const int c = t >> 4, d = (s & 3) * PV + (s >> 2) * 16 + (t & 15);
+                    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) {
+                        const float* sp = s_part + (k * NTP + c) * PB + d;
+                        q1 += sp[0];
+                        q2 += sp[PS];
+                        q3 += sp[2 * PS];
+                    }
+                    s_c[s * CST + t] = make_float2(R[q] * (q1 - q2), R[q] * (q3 - q1 - q2));
+                }
+            }
+        };
+        // 4. receive GEMM of a bin: Xj[e][t] += sum_s B[e][s] c[s][t], rows
+        //    e = mt_e + gi, columns of tiles rc0 ..., k = scatterer 4 k + gk
+        auto rgemm = [&](floatx4 (&Xj)[CPW][NX], const float2* sBp) {
+            if (!re_live) return;
+            float2 ba[SCH / 4], ca[SCH / 4][CPW];
+#pragma unroll
+            for (int k = 0; k < SCH / 4; ++k) {
+                const int s = 4 * k + gk;
+                ba[k] = sBp[s * BST + mt_e + gi];
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) ca[k][c] = s_c[s * CST + (rc0 + c) * 16 + gi];
+            }
+#pragma unroll
+            for (int k = 0; k < SCH / 4; ++k)
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) {
+                    if (NX == 3) {
+                        Xj[c][0] = mfma4(ba[k].x, ca[k][c].x, Xj[c][0]);
+                        Xj[c][1] = mfma4(ba[k].y, ca[k][c].y, Xj[c][1]);
+                        Xj[c][NX - 1] = mfma4(ba[k].x + ba[k].y, ca[k][c].x + ca[k][c].y, Xj[c][NX - 1]);
+                    } else {
+                        // Re += Br cr - Bi ci, Im += Br ci + Bi cr
+                        Xj[c][0] = mfma4(ba[k].x, ca[k][c].x, Xj[c][0]);
+                        Xj[c][0] = mfma4(-ba[k].y, ca[k][c].y, Xj[c][0]);
+                        Xj[c][1] = mfma4(ba[k].x, ca[k][c].y, Xj[c][1]);
+                        Xj[c][1] = mfma4(ba[k].y, ca[k][c].x, Xj[c][1]);
+                    }
+                }
+        };
+
+        // Software pipeline over the item's (chunk, bin) sequence, two barriers
+        // per bin:
+        //   A: reduce the previous bin (3); synthesise this bin's element
+        //      sums (1) and stage its weights;
+        //   B: the previous bin's receive GEMM (4); this bin's transmit GEMM (2).
+        // The element sums alternate between two buffers by bin (JT is even, so
+        // a chunk's first bin follows the previous chunk's last in the other
+        // one).  Every chunk runs all JT bins; bins past n_bins are computed
+        // (weights of the last bin) but not written.
+        bool prev = false;                     // uniform: a bin awaits steps 3-4
+        float Rc[NRED], Rp[NRED];              // R_s of the reduction rows: this chunk, previous
+#pragma unroll
+        for (int q = 0; q < NRED; ++q) Rc[q] = Rp[q] = 0.f;
         for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
             if (tid < SCH) {
                 const int s = s0 + tid;
@@ -137,6 +205,12 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 s_sc[tid] = v;
             }
             __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NRED; ++q) {
+                const int idx = tid + q * NB;
+                Rp[q] = Rc[q];
+                Rc[q] = idx < SCH * TPG ? s_sc[idx / TPG].w : 0.f;
+            }
             Geo g[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -146,13 +220,13 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 if (TABLE) g[k].kap *= P.kscale;          // delta_fetch's argument
             }
             // The bin loop is unrolled so that the receive sums X[jj] stay in
-            // registers; nb is uniform, so the barriers inside are too.
+            // registers.
 #pragma unroll
             for (int jj = 0; jj < JT; ++jj) {
-                if (jj >= nb) break;
-                const int jb = jb0 + jj;
-                const float jf = (float)(A.j_lo + jb);
+                const int jb = min(jb0 + jj, A.n_bins - 1);
+                const float jf = (float)(A.j_lo + jb0 + jj);
                 float2* sB = s_B + (jj & 1) * (SCH * BST);
+                // ---- segment A
                 // 0. transmit weights of this bin, W[t][e], zero outside N x n_tx.
                 //    With 16 columns they are loaded here and stored to LDS after
                 //    the synthesis, which hides the loads' latency; with 32 the
@@ -173,6 +247,7 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                 } else {
                     for (int idx = tid; idx < TPG * NE; idx += NB) s_W[(idx / NE) * WS + idx % NE] = w_at(idx);
                 }
+                if (prev) reduce(jj == 0 ? Rp : Rc);
                 // 1. j G of the chunk -> element sums B[s][e]
                 float2 G[PPT];
                 if constexpr (TABLE) {
@@ -212,6 +287,8 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     }
                 }
                 __syncthreads();
+                // ---- segment B
+                if (prev) rgemm(X[(jj + JT - 1) % JT], s_B + ((jj + 1) & 1) * (SCH * BST));
                 // 2. transmit GEMM share: rows s = gi, columns t = ct 16 + gi,
                 //    elements kp KW + 4 k + gk
                 {
@@ -246,53 +323,13 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
                     }
                 }
                 __syncthreads();
-                // 3. sum the shares (fixed order), combine, scale by R_s
-                for (int idx = tid; idx < SCH * TPG; idx += NB) {
-                    const int s = idx / TPG, t = idx % TPG;
-                    // row s of a tile = 4 (lane / 16) + v of the wave that wrote it
-                    const int c = t >> 4, d = (s & 3) * PV + (s >> 2) * 16 + (t & 15);
-                    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
-#pragma unroll
-                    for (int k = 0; k < KP; ++k) {
-                        const float* sp = s_part + (k * NTP + c) * PB + d;
-                        q1 += sp[0];
-                        q2 += sp[PS];
-                        q3 += sp[2 * PS];
-                    }
-                    const float R = s_sc[s].w;
-                    s_c[s * CST + t] = make_float2(R * (q1 - q2), R * (q3 - q1 - q2));
-                }
-                __syncthreads();
-                // 4. receive GEMM: X[e][t] += sum_s B[e][s] c[s][t], rows
-                //    e = mt_e + gi, columns of tiles rc0 ..., k = scatterer 4 k + gk
-                if (re_live) {
-                    float2 ba[SCH / 4], ca[SCH / 4][CPW];
-#pragma unroll
-                    for (int k = 0; k < SCH / 4; ++k) {
-                        const int s = 4 * k + gk;
-                        ba[k] = sB[s * BST + mt_e + gi];
-#pragma unroll
-                        for (int c = 0; c < CPW; ++c) ca[k][c] = s_c[s * CST + (rc0 + c) * 16 + gi];
-                    }
-#pragma unroll
-                    for (int k = 0; k < SCH / 4; ++k)
-#pragma unroll
-                        for (int c = 0; c < CPW; ++c) {
-                            if (NX == 3) {
-                                X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
-                                X[jj][c][1] = mfma4(ba[k].y, ca[k][c].y, X[jj][c][1]);
-                                X[jj][c][NX - 1] =
-                                    mfma4(ba[k].x + ba[k].y, ca[k][c].x + ca[k][c].y, X[jj][c][NX - 1]);
-                            } else {
-                                // Re += Br cr - Bi ci, Im += Br ci + Bi cr
-                                X[jj][c][0] = mfma4(ba[k].x, ca[k][c].x, X[jj][c][0]);
-                                X[jj][c][0] = mfma4(-ba[k].y, ca[k][c].y, X[jj][c][0]);
-                                X[jj][c][1] = mfma4(ba[k].x, ca[k][c].y, X[jj][c][1]);
-                                X[jj][c][1] = mfma4(ba[k].y, ca[k][c].x, X[jj][c][1]);
-                            }
-                        }
-                }
+                prev = true;
             }
+        }
+        if (prev) {     // steps 3-4 of the item's last bin
+            reduce(Rc);
+            __syncthreads();
+            rgemm(X[JT - 1], s_B + ((JT - 1) & 1) * (SCH * BST));
         }
         // per-element partials [item][JT][TPG][N]; D[row][col]: row = element
         // mt_e + 4 (lane / 16) + v, col = transmit (rc0 + c) 16 + lane % 16
