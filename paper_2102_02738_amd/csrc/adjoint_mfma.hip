@@ -27,6 +27,9 @@
 //     column tile go to LDS and are summed over the shares in a fixed order.
 //   Gradient: lane = (scatterer, transmit); lanes of a scatterer are summed
 //     once per chunk.
+// The steps are software-pipelined over a chunk's bins with two barriers per
+// bin: [reduction of the previous bin, synthesis] and [GEMM, gradient terms
+// of the previous bin].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -128,6 +131,41 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
 #pragma unroll
         for (int i = 0; i < NX; ++i) gX[i] = 0.f;
 
+        // 3. the partial products of a bin -> s_V (sum over the element
+        //    shares in a fixed order, the three products combined)
+        auto reduce = [&]() {
+            for (int idx = tid; idx < ROWS * NC; idx += NB) {
+                const int r = idx / NC, col = idx % NC;
+                const int d = (col >> 4) * PC + (r & 3) * PV + ((r >> 2) & 3) * 16 + (col & 15);
+                const int w0 = (r >> 4) * KP;
+                float q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    q1 += s_part[w0 + k][d];
+                    q2 += s_part[w0 + k][PP + d];
+                    q3 += s_part[w0 + k][2 * PP + d];
+                }
+                s_V[r][col] = make_float2(q1 - q2, q3 - q1 - q2);
+            }
+        };
+        // 4. gradient terms of bin jb for lane (scatterer gs, transmit gt)
+        auto gradient = [&](int jb) {
+            if (!glane) return;
+            const float2 pw = A.pw[jb];
+            const float2 a = s_V[gs * NL][gt], b = s_V[gs * NL][TG + gt];
+            gR += cmul(pw, cmul(a, b)).x;
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                const float2 da = s_V[gs * NL + 1 + i][gt], db = s_V[gs * NL + 1 + i][TG + gt];
+                gX[i] += cmul(pw, cfma(da, b, cmul(a, db))).x;
+            }
+        };
+        // Software pipeline over the chunk's bins, two barriers per bin:
+        //   A: reduce the previous bin (3); this bin's synthesis (1) and columns;
+        //   B: this bin's GEMM (2); the previous bin's gradient terms (4).
+        // The chunk's last bin is finished after the loop.
+        bool pend = false;                     // uniform: a bin awaits steps 3-4
+        int pend_jb = 0;
         for (int jb0 = b_begin; jb0 < b_end; jb0 += JS) {
             Geo g[PPT];
             GeoD D[PPT];
@@ -142,6 +180,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                 const int jb = jb0 + jj;
                 const float jf = (float)(A.j_lo + jb);
                 const float inv_j = rcp_fast(jf);
+                // ---- segment A
                 // 0. columns of this bin: W of the transmits, then Lam; zero
                 //    outside N x n_tx.  Loaded here, stored to LDS after the
                 //    synthesis so that the loads' latency is hidden behind it.
@@ -158,6 +197,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                     const bool use = e < A.N && t < A.n_tx;
                     wl[q] = make_float2(use ? w.x : 0.f, use ? w.y : 0.f);
                 }
+                if (pend) reduce();
                 // 1. G and its gradient -> element sums, rows (s, L)
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
@@ -183,6 +223,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                     s_WL[(idx / NE) * WS + idx % NE] = wl[q];
                 }
                 __syncthreads();
+                // ---- segment B
                 // 2. GEMM share: rows rt 16 + gi, columns ct 16 + gi, elements
                 //    kp KW + 4 k + gk
                 {
@@ -213,34 +254,16 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
                         }
                     }
                 }
+                if (pend) gradient(pend_jb);
                 __syncthreads();
-                // 3. sum the shares (fixed order), combine the three products
-                for (int idx = tid; idx < ROWS * NC; idx += NB) {
-                    const int r = idx / NC, col = idx % NC;
-                    const int d = (col >> 4) * PC + (r & 3) * PV + ((r >> 2) & 3) * 16 + (col & 15);
-                    const int w0 = (r >> 4) * KP;
-                    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
-#pragma unroll
-                    for (int k = 0; k < KP; ++k) {
-                        q1 += s_part[w0 + k][d];
-                        q2 += s_part[w0 + k][PP + d];
-                        q3 += s_part[w0 + k][2 * PP + d];
-                    }
-                    s_V[r][col] = make_float2(q1 - q2, q3 - q1 - q2);
-                }
-                __syncthreads();
-                // 4. gradient terms of lane (scatterer gs, transmit gt)
-                if (glane) {
-                    const float2 pw = A.pw[jb];
-                    const float2 a = s_V[gs * NL][gt], b = s_V[gs * NL][TG + gt];
-                    gR += cmul(pw, cmul(a, b)).x;
-#pragma unroll
-                    for (int i = 0; i < NX; ++i) {
-                        const float2 da = s_V[gs * NL + 1 + i][gt], db = s_V[gs * NL + 1 + i][TG + gt];
-                        gX[i] += cmul(pw, cfma(da, b, cmul(a, db))).x;
-                    }
-                }
+                pend = true;
+                pend_jb = jb;
             }
+        }
+        if (pend) {     // steps 3-4 of the chunk's last bin
+            reduce();
+            __syncthreads();
+            gradient(pend_jb);
         }
         // sum the transmit lanes of each scatterer; layout [range][s] of
         // (dR, dX, dY, dZ) before the R_s factor
