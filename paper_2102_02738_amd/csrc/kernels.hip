@@ -71,7 +71,7 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #define SIMUS_SC1 8
 #endif
 #ifndef SIMUS_JT_MAX
-#define SIMUS_JT_MAX 18
+#define SIMUS_JT_MAX 26
 #endif
 #ifndef SIMUS_WAVES_PER_EU
 #define SIMUS_WAVES_PER_EU 0
@@ -84,16 +84,17 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 
 // Bins per tile: the receive accumulators (JT TT BS slots of 8 bytes, or
 // of 4 bytes when paired) are kept within 64 KiB (32 KiB paired).  With the
-// elevation table in LDS, at most 18 bins: a paired 256-thread block then
-// takes 52 KB of LDS (accumulators 18, reduction rows 17, table 16), which
-// keeps three blocks per CU; with 20 bins only two fit.  Without the table
-// (2-D, y != 0, direct evaluation) paired blocks take up to 32 bins in the
-// same space.  Longer tiles amortise each pair's set-up.
+// elevation table in LDS, at most 26 bins: a paired 256-thread block then
+// takes 52 KB of LDS (accumulators 26, reduction rows 17, table 8), which
+// keeps three blocks per CU (config 2: 9.43 ms against 9.70 with 18 bins and
+// a 16 KiB table).  Without the table (2-D, y != 0, direct evaluation)
+// paired blocks take up to 32 bins in the same space.  Longer tiles amortise
+// each pair's set-up (an FP64 distance, ten transcendentals).
 constexpr int synth_jt(int bs, int tt, bool pair, bool table_lds, int groups = 1)
 {
     int jt = (pair && !table_lds) ? 32 : SIMUS_JT_MAX;
-    // four paired groups' reduction rows take 1.5 KB more LDS: 16 bins keep
-    // three blocks per CU (32-element probe: 2.39 vs 2.78 ms with 18)
+    // four paired groups' reduction rows take 1.5 KB more LDS: 16 bins
+    // (32-element probe: 2.34 ms; 2.32 ms with 24)
     if (pair && table_lds && groups == 4) jt = 16;
     const int slot = pair ? 4 : 8;
     const int budget = pair ? 32768 : 65536;

@@ -31,10 +31,10 @@ def test_bench_cost_constants_match_isa():
 
 def test_benchmark_instantiation_is_the_one_counted():
     """pw128_s50k (128 elements, nu = 2, one transmit, y = 0) runs
-    k_synth<256, 8, 18, 1, false, 1, true, 1>: block 256, 8 scatterers per
-    chunk, 18 bins per tile, 1 transmit, elevation table, paired lanes."""
+    k_synth<256, 8, 26, 1, false, 1, true, 1>: block 256, 8 scatterers per
+    chunk, 26 bins per tile, 1 transmit, elevation table, paired lanes."""
     sys.path.insert(0, ROOT)
     import bench
-    assert "ILi256ELi8ELi18ELi1ELb0ELi1ELb1ELi1E" in bench.SYNTH_KERNEL
+    assert "ILi256ELi8ELi26ELi1ELb0ELi1ELb1ELi1E" in bench.SYNTH_KERNEL
     src = open(os.path.join(ROOT, "paper_2102_02738_amd", "csrc", "kernels.hip")).read()
-    assert "#define SIMUS_SC1 8" in src and "#define SIMUS_JT_MAX 18" in src
+    assert "#define SIMUS_SC1 8" in src and "#define SIMUS_JT_MAX 26" in src
