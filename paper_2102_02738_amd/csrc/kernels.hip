@@ -96,6 +96,9 @@ constexpr int synth_jt(int bs, int tt, bool pair, bool table_lds, int groups = 1
     // four paired groups' reduction rows take 1.5 KB more LDS: 16 bins
     // (32-element probe: 2.34 ms; 2.32 ms with 24)
     if (pair && table_lds && groups == 4) jt = 16;
+    // unpaired lanes in four groups (nu = 1, 64 sub-elements): 24 bins keep
+    // the block within 80 KB of LDS, two blocks per CU
+    if (!pair && table_lds && groups == 4) jt = 24;
     const int slot = pair ? 4 : 8;
     const int budget = pair ? 32768 : 65536;
     while (jt > 1 && jt * tt * bs * slot > budget) jt /= 2;
@@ -439,18 +442,24 @@ hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t 
 // Finaliser: spec[p][t][e][b] = P_b sum_items sum_g sum_{mu<nu} part[item][jj][t%TT][g BG + e nu + mu]
 // (Eqs. 33-34), divided by j^2, j = j_lo + b, when inv_j2 is set (partials
 // of j G terms).  Items of phantom p are ordered (tg, bt, slice); the sum
-// over slices runs in slice order, so the result is deterministic.
+// over slices is split over FIN_K lanes in a fixed pattern, so the result is
+// deterministic.
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__ part,
-                           const float2* __restrict__ pw, const int32_t* __restrict__ pbase,
-                           const int32_t* __restrict__ nsl, int n_ph, int n_tx, int N, int nu,
-                           int n_bins, int bs, int groups, int tt, int jt, int n_bt, int j_lo,
-                           bool inv_j2)
+constexpr int FIN_K = 8;
+__global__ __launch_bounds__(256) void k_finalize(float2* __restrict__ spec, const float2* __restrict__ part,
+                                                  const float2* __restrict__ pw, const int32_t* __restrict__ pbase,
+                                                  const int32_t* __restrict__ nsl, int n_ph, int n_tx, int N, int nu,
+                                                  int n_bins, int bs, int groups, int tt, int jt, int n_bt,
+                                                  int j_lo, bool inv_j2)
 {
+    // FIN_K neighbouring lanes share one output: lane k sums the slices
+    // k, k + FIN_K, ... in order, and a fixed butterfly combines the lanes,
+    // so the result does not depend on scheduling
     const int bg = bs / groups;
     const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int kl = threadIdx.x % FIN_K;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / FIN_K);
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FIN_K; i < total; i += stride) {
         const int e = (int)(i % N);
         int64_t r = i / N;
         const int b = (int)(r % n_bins);
@@ -461,7 +470,7 @@ __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__
         const int ns = nsl[p];
         const int64_t first = pbase[p] + ((int64_t)tg * n_bt + bt) * ns;
         float sx = 0.f, sy = 0.f;
-        for (int sl = 0; sl < ns; ++sl) {
+        for (int sl = kl; sl < ns; sl += FIN_K) {
             const float2* src = part + (first + sl) * ((int64_t)jt * tt * bs) + (jj * tt + tl) * bs + e * nu;
             for (int g = 0; g < groups; ++g)
                 for (int mu = 0; mu < nu; ++mu) {
@@ -469,15 +478,22 @@ __global__ void k_finalize(float2* __restrict__ spec, const float2* __restrict__
                     sy += src[g * bg + mu].y;
                 }
         }
-        float2 w = pw[b];
-        if (inv_j2) {
-            // partials of j G terms (two per product): divide by j^2
-            const float j = (float)(j_lo + b);
-            const float s = 1.f / (j * j);
-            w = make_float2(w.x * s, w.y * s);
+#pragma unroll
+        for (int m = 1; m < FIN_K; m <<= 1) {
+            sx += __shfl_xor(sx, m, FIN_K);
+            sy += __shfl_xor(sy, m, FIN_K);
         }
-        spec[(((int64_t)p * n_tx + t) * N + e) * n_bins + b] =
-            make_float2(w.x * sx - w.y * sy, w.x * sy + w.y * sx);
+        if (kl == 0) {
+            float2 w = pw[b];
+            if (inv_j2) {
+                // partials of j G terms (two per product): divide by j^2
+                const float j = (float)(j_lo + b);
+                const float s = 1.f / (j * j);
+                w = make_float2(w.x * s, w.y * s);
+            }
+            spec[(((int64_t)p * n_tx + t) * N + e) * n_bins + b] =
+                make_float2(w.x * sx - w.y * sy, w.x * sy + w.y * sx);
+        }
     }
 }
 
@@ -489,7 +505,7 @@ hipError_t launch_finalize(float2* spec, const float2* part, const float2* pw,
     if (groups < 1 || bs % groups) return hipErrorInvalidValue;
     const int64_t total = (int64_t)n_ph * n_tx * n_bins * N;
     if (total == 0) return hipSuccess;
-    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    const int grid = (int)std::min<int64_t>((total * FIN_K + 255) / 256, 16384);
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, spec, part, pw, pbase, nsl, n_ph,
                        n_tx, N, nu, n_bins, bs, groups, tt, jt, n_bt, j_lo, inv_j2);
     return hipGetLastError();
