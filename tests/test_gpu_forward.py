@@ -232,6 +232,28 @@ def test_many_transmits_full_size_sampled_bins(S, orc):
     assert rel_l2(got, ref) <= TOL
 
 
+def test_uneven_phantoms_full_size_sampled_bins(S, orc):
+    """16 convex-probe phantoms of 10k-390k scatterers x 11 diverging waves
+    (2.27 M scatterers, the uneven-batch workload) in one persistent launch
+    on the matrix cores: the band's first and last bins of the smallest, a
+    middle and the largest phantom against the oracle."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("cvx128x11_p16")
+    g, spec, data = _run(S, w, flags=S.FLAG_PERSISTENT, spectrum=True)
+    x, y, z, R, off = data
+    sizes = np.diff(off)
+    order = np.argsort(sizes)
+    bins = sample_bins(g, 2)
+    su = oracle_setup(orc, w)
+    for p in (order[0], order[len(order) // 2], order[-1]):
+        sl = slice(off[p], off[p + 1])
+        ref = orc.spectrum(su, g["nfft"], w["delays"], w["apod"], x[sl], np.zeros(sizes[p]), z[sl], R[sl], bins)
+        got = spec[p][:, :, bins - g["j_lo"]]
+        e = rel_l2(got, ref)
+        print("phantom", p, "scatterers", sizes[p], "sampled bins rel L2", e)
+        assert e <= TOL
+
+
 def test_large_t_focused_small_full_rf(S, orc):
     """Phased array, 128 focused transmits (two groups of 64 transmit
     columns on the matrix cores), 20 scatterers: full RF against the oracle."""
