@@ -37,10 +37,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Issue-cost model of the synthesis kernel this workload runs,
-# k_synth<256, 8, 26, 1, false, 1, true, 1>: instructions per Green's term in
+# k_synth<256, 8, 27, 1, false, 1, true, 1>: instructions per Green's term in
 # its innermost loop (two bins of 8 scatterers per lane and iteration),
 # counted from the gfx950 assembly with paper_2102_02738_amd/diag/isa_count.py.
-SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi26ELi1ELb0ELi1ELb1ELi1EEEvNS_9SynthArgsE"
+SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi27ELi1ELb0ELi1ELb1ELi1EEEvNS_9SynthArgsE"
 SYNTH_TERMS_PER_ITER = 16
 SYNTH_VALU_PER_G = 33.0        # full-rate VALU instructions per G term
 SYNTH_TRANS_PER_G = 1.0        # transcendental instructions per G term
@@ -474,7 +474,7 @@ def main():
     achieved = g_terms * per_g / (synth_avg_ms * 1e-3)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="TOP/s",
                 frac=achieved / VALU_PEAK, traffic=measured_traffic(c.name),
-                kernel="k_synth<256, 8, 26, 1, false, 1, true, 1>", kernel_ms=synth_avg_ms,
+                kernel="k_synth<256, 8, 27, 1, false, 1, true, 1>", kernel_ms=synth_avg_ms,
                 ops_per_unit=per_g, valu_per_unit=SYNTH_VALU_PER_G, trans_per_unit=SYNTH_TRANS_PER_G,
                 unit_count=g_terms, unit_def="G term (sub-element x scatterer x bin)",
                 op_def="lane issue slot: full-rate VALU 1, transcendental 4")

@@ -156,6 +156,20 @@ def _dev(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(t, nbytes: int, name: str):
+    """The library takes raw device pointers: refuse a tensor smaller than
+    the bytes the call will read or write."""
+    if t is not None and t.numel() * t.element_size() < nbytes:
+        raise SimusError(-1, f"{name} holds {t.numel() * t.element_size()} bytes, {nbytes} needed")
+
+
+def _scatterers(x, y, z, refl):
+    n = x.numel()
+    for t, name in ((y, "y"), (z, "z"), (refl, "refl")):
+        _need(t, 4 * n, name)
+    return n
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -204,8 +218,10 @@ def _offsets(offsets, n_scat):
 
 def rf_spectrum_into(spec, probe, medium, options, delays, apod, x, y, z, refl,
                      offsets=None, stream=None):
+    """spec must hold [n_phantoms][n_tx][N][n_bins] complex64, n_bins from
+    rf_grid."""
     d, a, n_tx = _tx(probe, delays, apod)
-    o, n_ph = _offsets(offsets, x.numel())
+    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl))
     check(lib().simus_rf_spectrum(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                                   C.byref(make_options(options)), n_tx, _p(d, C.c_double),
                                   _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y),
@@ -214,7 +230,8 @@ def rf_spectrum_into(spec, probe, medium, options, delays, apod, x, y, z, refl,
 
 def rf_into(rf, probe, medium, options, delays, apod, x, y, z, refl, offsets=None, stream=None):
     d, a, n_tx = _tx(probe, delays, apod)
-    o, n_ph = _offsets(offsets, x.numel())
+    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl))
+    _need(rf, 4 * n_ph * n_tx * int(probe["n_elements"]) * max(int(options.get("n_t", 0)), 0), "rf")
     check(lib().simus_rf(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                          C.byref(make_options(options)), n_tx, _p(d, C.c_double), _p(a, C.c_float),
                          n_ph, _p(o, C.c_int64), _dev(x), _dev(y), _dev(z), _dev(refl), _dev(rf),
@@ -222,6 +239,8 @@ def rf_into(rf, probe, medium, options, delays, apod, x, y, z, refl, offsets=Non
 
 
 def spectrum_to_rf_into(rf, spec, nfft, n_t, j_lo, n_bins, n_chan, stream=None):
+    _need(rf, 4 * max(int(n_chan), 0) * max(int(n_t), 0), "rf")
+    _need(spec, 8 * max(int(n_chan), 0) * max(int(n_bins), 0), "spec")
     check(lib().simus_spectrum_to_rf(int(nfft), int(n_t), int(j_lo), int(n_bins), int(n_chan),
                                      _dev(spec), _dev(rf), _stream(stream)))
 
@@ -230,7 +249,11 @@ def rf_backward_into(grads, probe, medium, options, delays, apod, x, y, z, refl,
                      offsets=None, stream=None):
     """grads: dict with optional device tensors 'refl', 'x', 'y', 'z'."""
     d, a, n_tx = _tx(probe, delays, apod)
-    o, n_ph = _offsets(offsets, x.numel())
+    n = _scatterers(x, y, z, refl)
+    o, n_ph = _offsets(offsets, n)
+    _need(drf, 4 * n_ph * n_tx * int(probe["n_elements"]) * max(int(options.get("n_t", 0)), 0), "drf")
+    for k in ("refl", "x", "y", "z"):
+        _need(grads.get(k), 4 * n, "gradient " + k)
     check(lib().simus_rf_backward(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                                   C.byref(make_options(options)), n_tx, _p(d, C.c_double),
                                   _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y),
@@ -240,6 +263,9 @@ def rf_backward_into(grads, probe, medium, options, delays, apod, x, y, z, refl,
 
 
 def pfield_into(p_rms, probe, medium, options, n_f, delays, apod, X, Y, Z, stream=None):
+    n = X.numel()
+    for t, name in ((Y, "Y"), (Z, "Z"), (p_rms, "p_rms")):
+        _need(t, 4 * n, name)
     d = _f64(delays)
     a = _f32(np.ones(d.size) if apod is None else apod)
     check(lib().simus_pfield(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
@@ -266,18 +292,27 @@ class RFPlan:
                                          1 if has_y else 0, _stream(stream), C.byref(h)))
         self._h = h
         self.n_phantoms, self.n_tx, self.n_elements = n_ph, n_tx, int(probe["n_elements"])
+        self.n_scat, self.n_t = int(o[-1]), max(int(options.get("n_t", 0)), 0)
+
+    def _check_sizes(self, rf, x, y, z, refl):
+        _need(x, 4 * self.n_scat, "x")
+        _scatterers(x, y, z, refl)
+        _need(rf, 4 * self.n_phantoms * self.n_tx * self.n_elements * self.n_t, "rf")
 
     def execute_into(self, rf, x, y, z, refl, stream=None):
+        self._check_sizes(rf, x, y, z, refl)
         check(lib().simus_rf_plan_execute(self._handle(), _dev(x), _dev(y), _dev(z), _dev(refl),
                                           _dev(rf), _stream(stream)))
 
     def graph_launch_into(self, rf, x, y, z, refl, stream=None):
+        self._check_sizes(rf, x, y, z, refl)
         check(lib().simus_rf_plan_graph_launch(self._handle(), _dev(x), _dev(y), _dev(z),
                                                _dev(refl), _dev(rf), _stream(stream)))
 
     def autotune_into(self, rf, x, y, z, refl, stream=None) -> dict:
         """Runs the plan's autotuner on these scatterers; returns the chosen
         options (tile_scat, flags)."""
+        self._check_sizes(rf, x, y, z, refl)
         ts = C.c_int64()
         fl = C.c_int32()
         check(lib().simus_rf_plan_autotune(self._handle(), _dev(x), _dev(y), _dev(z), _dev(refl),

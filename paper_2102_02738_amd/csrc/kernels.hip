@@ -66,12 +66,9 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 // ---------------------------------------------------------------------------
 
 // Tunables of the synthesis launch (compile-time): scatterers per chunk for
-// single-transmit groups, longest bin tile, and a waves-per-SIMD floor.
+// single-transmit groups and a waves-per-SIMD floor.
 #ifndef SIMUS_SC1
 #define SIMUS_SC1 8
-#endif
-#ifndef SIMUS_JT_MAX
-#define SIMUS_JT_MAX 26
 #endif
 #ifndef SIMUS_WAVES_PER_EU
 #define SIMUS_WAVES_PER_EU 0
@@ -82,26 +79,43 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 #define SIMUS_OCCUPANCY
 #endif
 
-// Bins per tile: the receive accumulators (JT TT BS slots of 8 bytes, or
-// of 4 bytes when paired) are kept within 64 KiB (32 KiB paired).  With the
-// elevation table in LDS, at most 26 bins: a paired 256-thread block then
-// takes 52 KB of LDS (accumulators 26, reduction rows 17, table 8), which
-// keeps three blocks per CU (config 2: 9.43 ms against 9.70 with 18 bins and
-// a 16 KiB table).  Without the table (2-D, y != 0, direct evaluation)
-// paired blocks take up to 32 bins in the same space.  Longer tiles amortise
-// each pair's set-up (an FP64 distance, ten transcendentals).
+// LDS of one k_synth block in bytes, term by term as the kernel declares it:
+// scatterer chunk, transmit-reduction rows (two buffers), reduced values,
+// receive accumulators of the tile, elevation table, work-item slot.
+constexpr int synth_lds(int bs, int sc, int tt, int groups, bool pair, bool table_lds, int jt)
+{
+    const int nt = sc * tt * groups;
+    const int rs = bs / groups / 2 + 4;
+    return 16 * groups * sc + 8 * 2 * nt * rs + 8 * 2 * (pair ? 2 : 1) * nt +
+           4 * jt * tt * bs * (pair ? 1 : 2) + 16 * (table_lds ? 2 * DELTA_NT : 1) + 4;
+}
+
+// LDS is allocated to blocks in 2 KiB granules of the CU's 160 KiB (measured:
+// a 53,124-byte block runs three per CU, a 54,020-byte one two).
+constexpr int LDS_PER_CU = 163840;
+constexpr int LDS_GRANULE = 2048;
+
+// Blocks per CU that the registers allow: paired kernels take about 155
+// VGPRs (three waves per SIMD), unpaired ones about 175 (two); at least one.
+constexpr int synth_blocks_per_cu(int bs, bool pair)
+{
+    const int b = 4 * (pair ? 3 : 2) / (bs / 64);
+    return b < 1 ? 1 : b;
+}
+
+// Bins per tile: the longest tile, up to 32, whose blocks fit the CU's LDS
+// at that occupancy.  Longer tiles amortise each pair's set-up (an FP64
+// distance, ten transcendentals).  Single transmits, 128 elements: 27 bins
+// (config 2: 9.32 ms; 26 bins 9.42, 18 bins with the 512-interval table 9.70;
+// 28 bins leave two blocks per CU: 11.7).
 constexpr int synth_jt(int bs, int tt, bool pair, bool table_lds, int groups = 1)
 {
-    int jt = (pair && !table_lds) ? 32 : SIMUS_JT_MAX;
-    // four paired groups' reduction rows take 1.5 KB more LDS: 16 bins
-    // (32-element probe: 2.34 ms; 2.32 ms with 24)
-    if (pair && table_lds && groups == 4) jt = 16;
-    // unpaired lanes in four groups (nu = 1, 64 sub-elements): 24 bins keep
-    // the block within 80 KB of LDS, two blocks per CU
-    if (!pair && table_lds && groups == 4) jt = 24;
-    const int slot = pair ? 4 : 8;
-    const int budget = pair ? 32768 : 65536;
-    while (jt > 1 && jt * tt * bs * slot > budget) jt /= 2;
+    const int sc = tt == 2 ? 4 : SIMUS_SC1;
+    const int limit = LDS_PER_CU / synth_blocks_per_cu(bs, pair) / LDS_GRANULE * LDS_GRANULE;
+    // at most 32 bins for 256-thread blocks, 16 for 512 and 6 for 1024 (whose
+    // 128-VGPR bound spills with 8 or more)
+    int jt = bs <= 256 ? 32 : bs == 512 ? 16 : 6;
+    while (jt > 1 && synth_lds(bs, sc, tt, groups, pair, table_lds, jt) > limit) --jt;
     return jt;
 }
 
@@ -161,6 +175,9 @@ __global__ __launch_bounds__(BS) SIMUS_OCCUPANCY void k_synth(SynthArgs A)
     __shared__ float s_acc[JT * TT * BS * NA];
     constexpr bool TABLE = EL == 1;
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+    static_assert(sizeof(s_sc) + sizeof(s_red) + sizeof(s_c) + sizeof(s_acc) + sizeof(s_tab) + sizeof(int) ==
+                      (size_t)synth_lds(BS, SC, TT, NG, PAIR, TABLE, JT),
+                  "synth_lds must follow the declarations");
 
     const int tid = threadIdx.x;
     const int n = tid % BG, grp = tid / BG;    // sub-element slot, group

@@ -94,6 +94,17 @@ def innermost(asm: str, kernel: str, min_ops: int):
     return best
 
 
+def lds_bytes(asm: str, kernel: str) -> int:
+    """The kernel's static LDS (group segment) size from the code object
+    metadata that hipcc writes into the assembly."""
+    for entry in asm.split("\n  - ")[1:]:
+        if re.search(r"^\s+\.name:\s+" + re.escape(kernel) + r"\s*$", entry, re.M):
+            m = re.search(r"\.group_segment_fixed_size:\s+(\d+)", entry)
+            if m:
+                return int(m.group(1))
+    raise KeyError(kernel)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("source")
@@ -119,6 +130,7 @@ def main():
         print(f"issue slots per term (valu + 4 trans): {slots / args.terms:.2f}")
         print(f"valu_per_term: {c['valu'] / args.terms:.3f}")
         print(f"trans_per_term: {c['trans'] / args.terms:.3f}")
+        print(f"lds_bytes: {lds_bytes(s, kernel)}")
         if c["mfma"]:
             print(f"mfma_per_term: {c['mfma'] / args.terms:.3f}")
 

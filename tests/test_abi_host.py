@@ -210,3 +210,34 @@ def test_package_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(_lib.SimusError):
         _lib.lib()
+
+
+def test_binding_refuses_small_buffers(L):
+    """The library takes raw device pointers; the binding refuses tensors
+    smaller than what a call reads or writes, before any library call (CPU
+    tensors of the right size are then refused as not on the device)."""
+    import torch
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.1)
+    ph = w["phantoms"][0]
+    n = ph["x"].size
+    x, z, R = (torch.from_numpy(ph[k].astype(np.float32)) for k in ("x", "z", "R"))
+    n_tx, N, n_t = w["delays"].shape[0], w["probe"]["n_elements"], 64
+    o = dict(w["options"], nfft=128, n_t=n_t)
+    args = (w["probe"], w["medium"], o, w["delays"], w["apod"])
+    good = torch.empty(n_tx * N * n_t)
+    with pytest.raises(L.SimusError, match="rf holds"):
+        L.rf_into(good[:-1], *args, x, None, z, R)
+    with pytest.raises(L.SimusError, match="refl holds"):
+        L.rf_into(good, *args, x, None, z, R[:-1])
+    with pytest.raises(L.SimusError, match="device tensor expected"):
+        L.rf_into(good, *args, x, None, z, R)
+    with pytest.raises(L.SimusError, match="drf holds"):
+        L.rf_backward_into({}, *args, x, None, z, R, good[:-1])
+    with pytest.raises(L.SimusError, match="gradient x holds"):
+        L.rf_backward_into({"x": torch.empty(n - 1)}, *args, x, None, z, R, good)
+    with pytest.raises(L.SimusError, match="p_rms holds"):
+        L.pfield_into(torch.empty(n - 1), w["probe"], w["medium"], o, 10, w["delays"][0], None,
+                      x, None, z)
+    with pytest.raises(L.SimusError, match="spec holds"):
+        L.spectrum_to_rf_into(torch.empty(4 * n_t), torch.empty(4 * 2 * 10 - 1), 128, n_t, 1, 10, 4)
