@@ -121,7 +121,9 @@ typedef struct {
                                         persistent); results are bitwise the same */
 #define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape: matrix-core groups of 16
                                         transmit columns instead of 32 (more than 64
-                                        elements) or 64 instead of 32 (64 or fewer); vector
+                                        elements), or for 64 or fewer elements and more
+                                        than 32 transmits the other of 32 and 64 columns
+                                        (the default takes 64 where it pads no more); vector
                                         path: single transmits instead of pairs, or pairs
                                         instead of single transmits.  The autotuner tries
                                         it.  simus_rf_backward: the other of its two kernels

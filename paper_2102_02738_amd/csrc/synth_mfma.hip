@@ -245,7 +245,20 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
 #pragma unroll
                     for (int q = 0; q < NW; ++q) wv[q] = w_at(tid + q * NB);
                 } else {
-                    for (int idx = tid; idx < TPG * NE; idx += NB) s_W[(idx / NE) * WS + idx % NE] = w_at(idx);
+                    // batches of four loads, so that a bin pays the load
+                    // latency twice rather than once per weight
+                    static_assert(NW % 4 == 0, "weights staged in batches of four");
+#pragma unroll 1
+                    for (int q0 = 0; q0 < NW; q0 += 4) {
+                        float2 wq[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) wq[q] = w_at(tid + (q0 + q) * NB);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int idx = tid + (q0 + q) * NB;
+                            s_W[(idx / NE) * WS + idx % NE] = wq[q];
+                        }
+                    }
                 }
                 if (prev) reduce(jj == 0 ? Rp : Rc);
                 // 1. j G of the chunk -> element sums B[s][e]
@@ -365,13 +378,16 @@ struct MtShape {
 
 static MtShape mt_shape(int N, int n_tx, bool alt)
 {
-    // 64 element slots: groups of 32 transmit columns with 6 bins per item
-    // (measured per transmit as fast as 64 columns at full groups, and finer:
-    // 96 transmits 35 vs 49 ms); alternative: 64 columns.  128 slots: 32
-    // columns above 16 transmits (21 transmits, 200k scatterers: 215 vs
-    // 258 ms with 16), 4 bins per item (5 spill); alternative: 16 columns.
+    // 64 element slots, 6 bins per item: above 32 transmits, groups of 64
+    // transmit columns where they pad no more than groups of 32 (40k
+    // scatterers: 128 transmits 42.5 vs 44.7 ms with 32; 40 and 64 equal; 96
+    // transmits 41.9 vs 32.5 ms, so 32 there); the alternative takes the
+    // other width.  128 slots: 32 columns above 16 transmits (21 transmits,
+    // 200k scatterers: 215 vs 258 ms with 16), 4 bins per item (5 spill);
+    // alternative: 16 columns.
     if (N <= 64) {
-        if (alt && n_tx > 32) return {64, 4, 6, 2};
+        const bool wide = (n_tx + 63) / 64 * 64 == (n_tx + 31) / 32 * 32;
+        if (n_tx > 32 && wide != alt) return {64, 4, 6, 2};
         return {64, 2, 6, 3};
     }
     if (n_tx <= 16 || alt) return {128, 1, 4, 3};
