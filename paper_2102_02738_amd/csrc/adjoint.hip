@@ -206,14 +206,19 @@ hipError_t launch_dft_t(float2* lam, const float* rho, int64_t n_chan, int n_bin
     return hipSuccess;
 }
 
+// Bins per tile of the vector adjoint for tt transmits per group, measured
+// (100k scatterers): one transmit 4 bins (126 VGPRs, four waves per SIMD;
+// 64.0 ms against 70.5 with 8), two transmits 4 (88.5 ms; 2 bins 96.7),
+// four transmits 1 (64 elements: 65.2 ms; 2 bins 67.1); with y != 0 two
+// transmits take 2 bins (4 would need 239 VGPRs).
+constexpr int adj_jt(int tt, bool has_y) { return tt == 1 ? 4 : tt == 2 ? (has_y ? 2 : 4) : 1; }
+
 AdjConfig adjoint_config(int n_tx, bool has_y)
 {
     AdjConfig c{};
     c.tt = n_tx >= 8 ? 8 : n_tx >= 4 ? 4 : n_tx >= 2 ? 2 : 1;
     if (has_y && c.tt > 4) c.tt = 4;
-    // accumulator registers: (2 + 2 NX) complex per (bin, transmit)
-    const int budget = has_y ? 4 : 8;
-    c.jt = std::max(1, budget / c.tt);
+    c.jt = adj_jt(c.tt, has_y);
     c.scatterers = 256;
     c.has_y = has_y;
     return c;
@@ -231,22 +236,17 @@ static hipError_t launch_adj_jt(const AdjConfig& c, const AdjArgs& a, int n_item
     return hipGetLastError();
 }
 
+
 hipError_t launch_adjoint(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    if (c.has_y) {
-        switch (c.tt) {
-        case 1: return launch_adj_jt<4, 1>(c, a, n_items, st);
-        case 2: return launch_adj_jt<2, 2>(c, a, n_items, st);
-        case 4: return launch_adj_jt<1, 4>(c, a, n_items, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
+    // the kernel's tile must be the one the item ranges were cut for
+    if (c.jt != adj_jt(c.tt, c.has_y)) return hipErrorInvalidValue;
     switch (c.tt) {
-    case 1: return launch_adj_jt<8, 1>(c, a, n_items, st);
-    case 2: return launch_adj_jt<4, 2>(c, a, n_items, st);
-    case 4: return launch_adj_jt<2, 4>(c, a, n_items, st);
-    case 8: return launch_adj_jt<1, 8>(c, a, n_items, st);
+    case 1: return launch_adj_jt<4, 1>(c, a, n_items, st);
+    case 2: return c.has_y ? launch_adj_jt<2, 2>(c, a, n_items, st) : launch_adj_jt<4, 2>(c, a, n_items, st);
+    case 4: return launch_adj_jt<1, 4>(c, a, n_items, st);
+    case 8: return c.has_y ? hipErrorInvalidValue : launch_adj_jt<1, 8>(c, a, n_items, st);
     default: return hipErrorInvalidValue;
     }
 }
