@@ -208,3 +208,29 @@ def test_autograd_function(S, orc):
     ref["refl"] = ref.pop("R")
     _check({"refl": dR.grad.cpu().numpy(), "x": dx.grad.cpu().numpy(), "z": dz.grad.cpu().numpy()},
            ref, ["refl", "x", "z"])
+
+
+def test_adjoint_empty_phantom(S):
+    """No scatterers: the call succeeds and the gradients are empty."""
+    import torch
+    w = small()
+    x, y, z, R, off = concat_phantoms(w["phantoms"])
+    g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
+    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"])
+    e = torch.empty(0, device="cuda")
+    rho = torch.ones((1, 2, 8, g["n_t"]), device="cuda")
+    gr = S.rf_backward(w["probe"], w["medium"], o, w["delays"], w["apod"], e, None, e, e, rho)
+    torch.cuda.synchronize()
+    assert set(gr) >= {"refl", "x", "z"} and all(v.numel() == 0 for v in gr.values())
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_adjoint_single_scatterer(S, orc, path):
+    """One scatterer: a single partial chunk on either kernel."""
+    w = small(n_tx=3, n_scat=1, seed=5)
+    x, y, z, R, off = concat_phantoms(w["phantoms"])
+    g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
+    rho = np.random.default_rng(5).standard_normal((1, 3, 8, g0["n_t"])).astype(np.float32)
+    g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    ref = oracle_grads(orc, w, g, rho[0])
+    _check(got, ref, ["refl", "x", "z"])

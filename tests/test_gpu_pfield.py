@@ -69,3 +69,25 @@ def test_pfield_matches_oracle(S, orc, kind, direct):
     e = rel_l2(got.cpu().numpy(), ref)
     print(kind, "nf", nf, "rel L2", e)
     assert e <= TOL
+
+
+def test_pfield_empty_and_single_point(S, orc):
+    """No field points: the call succeeds with an empty result; one point
+    matches the oracle."""
+    import torch
+    w, dl, X, Y, Z = _case("linear_pw10")
+    apod = np.ones(w["probe"]["n_elements"], np.float32)
+    nf = S.pfield_nf(w["probe"], w["medium"], w["options"], dl, X, Y, Z)
+    e = torch.empty(0, device="cuda")
+    got = S.pfield(w["probe"], w["medium"], w["options"], nf, dl, apod, e, None, e)
+    torch.cuda.synchronize()
+    assert got.numel() == 0
+    X1, Z1 = X[len(X) // 2:len(X) // 2 + 1], Z[len(Z) // 2:len(Z) // 2 + 1]
+    dX, dZ = to_dev(X1, Z1)
+    got = S.pfield(w["probe"], w["medium"], w["options"], nf, dl, apod, dX, None, dZ)
+    torch.cuda.synchronize()
+    su = oracle_setup(orc, w)
+    ref = orc.pfield(su, dl, apod, nf, X1, np.zeros_like(X1), Z1)
+    e1 = rel_l2(got.cpu().numpy(), ref)
+    print("single point rel L2", e1)
+    assert e1 <= TOL
