@@ -241,3 +241,27 @@ def test_binding_refuses_small_buffers(L):
                       x, None, z)
     with pytest.raises(L.SimusError, match="spec holds"):
         L.spectrum_to_rf_into(torch.empty(4 * n_t), torch.empty(4 * 2 * 10 - 1), 128, n_t, 1, 10, 4)
+
+
+def test_product_and_oracle_share_no_code():
+    """The HIP path and the FP64 oracle are independent: no package source
+    imports or includes anything under oracle/, and no oracle source imports
+    the package (the seeded input generators are the only shared module, and
+    the oracle receives their arrays from the tests)."""
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2102_02738_amd")
+    bad = []
+    for d, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                src = open(os.path.join(d, f), encoding="utf-8").read()
+                if re.search(r"^\s*(from|import)\s+oracle\b|#include\s+[\"<][^\">]*oracle", src, re.M):
+                    bad.append(os.path.join(d, f))
+    for d, _, files in os.walk(os.path.join(root, "oracle")):
+        for f in files:
+            if f.endswith((".py", ".c", ".h")):
+                src = open(os.path.join(d, f), encoding="utf-8").read()
+                if re.search(r"^\s*(from|import)\s+paper_2102_02738_amd\b|#include\s+[\"<][^\">]*(simus\.h|csrc)", src, re.M):
+                    bad.append(os.path.join(d, f))
+    assert not bad, bad
