@@ -44,6 +44,21 @@
  *   when radius > 0 (apex at the origin, centre of curvature at (0, -R),
  *   flat elements of chord pitch, split along their face).  A sub-element
  *   does not radiate behind its face (G = 0 where the local depth <= 0).
+ * - Domain of the scatterers.  simus_rf_grid reads host copies and returns
+ *   SIMUS_EDOMAIN for a scatterer at depth z <= 0 in front of a linear
+ *   array, within 1e-9 m of a sub-element centroid, or with a non-finite
+ *   coordinate.  The device entry points (simus_rf_spectrum, simus_rf,
+ *   simus_rf_backward, simus_pfield, the plan calls) do not read device
+ *   data on the host and return no SIMUS_EDOMAIN: there, a (sub-element,
+ *   scatterer) pair with the scatterer at local depth <= 0 in front of the
+ *   sub-element's face, or within 1e-9 m of its centroid, has G = 0 (and
+ *   dG = 0).  So a scatterer behind every sub-element (z <= 0 before a
+ *   linear array) adds exactly nothing to spectra, RF or field, and gets
+ *   zero gradients; such scatterers do not widen the per-call elevation
+ *   table either, so appending them to a phantom leaves its spectra and RF
+ *   bit for bit unchanged when the partition into work items
+ *   (options.tile_scat) does not move the other scatterers.  Non-finite
+ *   device coordinates are not checked and give undefined results.
  */
 #ifndef SIMUS_H
 #define SIMUS_H
@@ -58,7 +73,7 @@ extern "C" {
 
 #define SIMUS_OK 0
 #define SIMUS_EINVAL (-1)   /* invalid argument (NULL pointer, bad size, bad parameter) */
-#define SIMUS_EDOMAIN (-2)  /* scatterer outside the model's domain (host checks) */
+#define SIMUS_EDOMAIN (-2)  /* scatterer outside the model's domain (simus_rf_grid only) */
 #define SIMUS_ENOMEM (-3)   /* device or pinned host allocation failed */
 #define SIMUS_EHIP (-4)     /* a HIP runtime call failed */
 

@@ -112,21 +112,25 @@ def pfield(probe, medium, options, n_f, delays, apod, X, Y, Z, stream=None):
 class RFPlan(_lib.RFPlan):
     """Forward plan (see rf_plan)."""
 
-    def rf(self, x, y, z, refl, n_t, graph=False, stream=None):
-        """RF [n_phantoms, n_tx, N, n_t] of the plan for device scatterers; with
-        graph=True through the plan's captured HIP graph."""
+    def _out(self, x, n_t):
         import torch
-        out = torch.empty((self.n_phantoms, self.n_tx, self.n_elements, n_t), dtype=torch.float32,
-                          device=x.device)
+        if n_t is not None and int(n_t) != self.n_t:
+            raise SimusError(-1, f"the plan writes {self.n_t} samples per channel, not {n_t}")
+        return torch.empty((self.n_phantoms, self.n_tx, self.n_elements, self.n_t),
+                           dtype=torch.float32, device=x.device)
+
+    def rf(self, x, y, z, refl, n_t=None, graph=False, stream=None):
+        """RF [n_phantoms, n_tx, N, n_t] of the plan for device scatterers; with
+        graph=True through the plan's captured HIP graph.  n_t, if given, must
+        be the plan's."""
+        out = self._out(x, n_t)
         (self.graph_launch_into if graph else self.execute_into)(out, x, y, z, refl, stream)
         return out
 
-    def autotune(self, x, y, z, refl, n_t, stream=None) -> dict:
+    def autotune(self, x, y, z, refl, n_t=None, stream=None) -> dict:
         """Times launch shapes on these scatterers and keeps the fastest in the
         plan; returns the chosen options (tile_scat, flags)."""
-        import torch
-        out = torch.empty((self.n_phantoms, self.n_tx, self.n_elements, n_t), dtype=torch.float32,
-                          device=x.device)
+        out = self._out(x, n_t)
         return self.autotune_into(out, x, y, z, refl, stream)
 
 

@@ -145,28 +145,45 @@ def _p(a: np.ndarray, t):
     return a.ctypes.data_as(C.POINTER(t))
 
 
-def _dev(t):
-    """Device pointer of a CUDA/HIP tensor (or None)."""
+def _dev(t, like=None):
+    """Device pointer of a contiguous float32 CUDA/HIP tensor (or None); with
+    `like`, the tensor must sit on the same device."""
     if t is None:
         return None
     if not t.is_cuda:
         raise SimusError(-1, "device tensor expected")
     if not t.is_contiguous():
         raise SimusError(-1, "contiguous tensor expected")
+    if like is not None and t.device != like.device:
+        raise SimusError(-1, f"tensors on different devices ({t.device} and {like.device})")
     return C.c_void_p(t.data_ptr())
 
 
-def _need(t, nbytes: int, name: str):
-    """The library takes raw device pointers: refuse a tensor smaller than
-    the bytes the call will read or write."""
-    if t is not None and t.numel() * t.element_size() < nbytes:
-        raise SimusError(-1, f"{name} holds {t.numel() * t.element_size()} bytes, {nbytes} needed")
+def _need(t, n: int, name: str):
+    """The library takes raw device pointers to float32 data: refuse a tensor
+    of another dtype, or one holding fewer than the n floats the call will
+    read or write."""
+    if t is None:
+        return
+    if str(t.dtype) != "torch.float32":
+        raise SimusError(-1, f"{name} must be float32, not {t.dtype}")
+    if t.numel() < n:
+        raise SimusError(-1, f"{name} holds {t.numel() * t.element_size()} bytes, {4 * n} needed")
 
 
-def _scatterers(x, y, z, refl):
-    n = x.numel()
-    for t, name in ((y, "y"), (z, "z"), (refl, "refl")):
-        _need(t, 4 * n, name)
+def _n_t(options: dict) -> int:
+    """RF samples per channel the library writes: options n_t, else nfft."""
+    return max(int(options.get("n_t", 0) or options.get("nfft", 0) or 0), 0)
+
+
+def _scatterers(x, y, z, refl, offsets=None):
+    """Scatterers the call reads (the last offset, else all of x); every
+    array must hold that many floats."""
+    n = x.numel() if offsets is None else int(np.asarray(offsets, dtype=np.int64)[-1])
+    if offsets is not None and n > x.numel():
+        raise SimusError(-1, f"scat_offsets end at {n}, x holds {x.numel()} scatterers")
+    for t, name in ((x, "x"), (y, "y"), (z, "z"), (refl, "refl")):
+        _need(t, n, name)
     return n
 
 
@@ -207,7 +224,11 @@ def _tx(probe, delays, apod):
     d = _f64(delays)
     N = max(int(probe["n_elements"]), 1)
     n_tx = d.size // N
+    if d.size != n_tx * N or n_tx < 1:
+        raise SimusError(-1, f"delays hold {d.size} values, not n_tx x {N}")
     a = _f32(np.ones((n_tx, N)) if apod is None else apod)
+    if a.size != n_tx * N:
+        raise SimusError(-1, f"apod holds {a.size} values, delays {n_tx} x {N}")
     return d, a, n_tx
 
 
@@ -218,60 +239,68 @@ def _offsets(offsets, n_scat):
 
 def rf_spectrum_into(spec, probe, medium, options, delays, apod, x, y, z, refl,
                      offsets=None, stream=None):
-    """spec must hold [n_phantoms][n_tx][N][n_bins] complex64, n_bins from
-    rf_grid."""
+    """spec must hold [n_phantoms][n_tx][N][n_bins] complex64 (as float32
+    pairs), n_bins from rf_grid."""
     d, a, n_tx = _tx(probe, delays, apod)
-    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl))
+    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl, offsets))
+    n_bins = rf_grid(probe, medium, options, d.reshape(n_tx, -1), [], None, [])["n_bins"]
+    _need(spec, 2 * n_ph * n_tx * int(probe["n_elements"]) * n_bins, "spec")
     check(lib().simus_rf_spectrum(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                                   C.byref(make_options(options)), n_tx, _p(d, C.c_double),
-                                  _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y),
-                                  _dev(z), _dev(refl), _dev(spec), _stream(stream)))
+                                  _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y, x),
+                                  _dev(z, x), _dev(refl, x), _dev(spec, x), _stream(stream)))
 
 
 def rf_into(rf, probe, medium, options, delays, apod, x, y, z, refl, offsets=None, stream=None):
     d, a, n_tx = _tx(probe, delays, apod)
-    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl))
-    _need(rf, 4 * n_ph * n_tx * int(probe["n_elements"]) * max(int(options.get("n_t", 0)), 0), "rf")
+    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl, offsets))
+    _need(rf, n_ph * n_tx * int(probe["n_elements"]) * _n_t(options), "rf")
     check(lib().simus_rf(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                          C.byref(make_options(options)), n_tx, _p(d, C.c_double), _p(a, C.c_float),
-                         n_ph, _p(o, C.c_int64), _dev(x), _dev(y), _dev(z), _dev(refl), _dev(rf),
-                         _stream(stream)))
+                         n_ph, _p(o, C.c_int64), _dev(x), _dev(y, x), _dev(z, x), _dev(refl, x),
+                         _dev(rf, x), _stream(stream)))
 
 
 def spectrum_to_rf_into(rf, spec, nfft, n_t, j_lo, n_bins, n_chan, stream=None):
-    _need(rf, 4 * max(int(n_chan), 0) * max(int(n_t), 0), "rf")
-    _need(spec, 8 * max(int(n_chan), 0) * max(int(n_bins), 0), "spec")
+    _need(rf, max(int(n_chan), 0) * max(int(n_t), 0), "rf")
+    _need(spec, 2 * max(int(n_chan), 0) * max(int(n_bins), 0), "spec")
     check(lib().simus_spectrum_to_rf(int(nfft), int(n_t), int(j_lo), int(n_bins), int(n_chan),
-                                     _dev(spec), _dev(rf), _stream(stream)))
+                                     _dev(spec), _dev(rf, spec), _stream(stream)))
 
 
 def rf_backward_into(grads, probe, medium, options, delays, apod, x, y, z, refl, drf,
                      offsets=None, stream=None):
     """grads: dict with optional device tensors 'refl', 'x', 'y', 'z'."""
     d, a, n_tx = _tx(probe, delays, apod)
-    n = _scatterers(x, y, z, refl)
+    n = _scatterers(x, y, z, refl, offsets)
     o, n_ph = _offsets(offsets, n)
-    _need(drf, 4 * n_ph * n_tx * int(probe["n_elements"]) * max(int(options.get("n_t", 0)), 0), "drf")
+    _need(drf, n_ph * n_tx * int(probe["n_elements"]) * _n_t(options), "drf")
     for k in ("refl", "x", "y", "z"):
-        _need(grads.get(k), 4 * n, "gradient " + k)
+        _need(grads.get(k), n, "gradient " + k)
     check(lib().simus_rf_backward(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                                   C.byref(make_options(options)), n_tx, _p(d, C.c_double),
-                                  _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y),
-                                  _dev(z), _dev(refl), _dev(drf), _dev(grads.get("refl")),
-                                  _dev(grads.get("x")), _dev(grads.get("y")), _dev(grads.get("z")),
+                                  _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y, x),
+                                  _dev(z, x), _dev(refl, x), _dev(drf, x),
+                                  _dev(grads.get("refl"), x), _dev(grads.get("x"), x),
+                                  _dev(grads.get("y"), x), _dev(grads.get("z"), x),
                                   _stream(stream)))
 
 
 def pfield_into(p_rms, probe, medium, options, n_f, delays, apod, X, Y, Z, stream=None):
     n = X.numel()
-    for t, name in ((Y, "Y"), (Z, "Z"), (p_rms, "p_rms")):
-        _need(t, 4 * n, name)
+    for t, name in ((X, "X"), (Y, "Y"), (Z, "Z"), (p_rms, "p_rms")):
+        _need(t, n, name)
     d = _f64(delays)
+    N = int(probe["n_elements"])
+    if d.size != N:
+        raise SimusError(-1, f"delays hold {d.size} values, the probe has {N} elements")
     a = _f32(np.ones(d.size) if apod is None else apod)
+    if a.size != N:
+        raise SimusError(-1, f"apod holds {a.size} values, the probe has {N} elements")
     check(lib().simus_pfield(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
                              C.byref(make_options(options)), int(n_f), _p(d, C.c_double),
-                             _p(a, C.c_float), X.numel(), _dev(X), _dev(Y), _dev(Z), _dev(p_rms),
-                             _stream(stream)))
+                             _p(a, C.c_float), X.numel(), _dev(X), _dev(Y, X), _dev(Z, X),
+                             _dev(p_rms, X), _stream(stream)))
 
 
 class RFPlan:
@@ -292,22 +321,25 @@ class RFPlan:
                                          1 if has_y else 0, _stream(stream), C.byref(h)))
         self._h = h
         self.n_phantoms, self.n_tx, self.n_elements = n_ph, n_tx, int(probe["n_elements"])
-        self.n_scat, self.n_t = int(o[-1]), max(int(options.get("n_t", 0)), 0)
+        self.n_scat, self.n_t = int(o[-1]), _n_t(options)
 
     def _check_sizes(self, rf, x, y, z, refl):
-        _need(x, 4 * self.n_scat, "x")
-        _scatterers(x, y, z, refl)
-        _need(rf, 4 * self.n_phantoms * self.n_tx * self.n_elements * self.n_t, "rf")
+        _need(x, self.n_scat, "x")
+        _scatterers(x, y, z, refl, [0, self.n_scat])
+        _need(rf, self.n_phantoms * self.n_tx * self.n_elements * self.n_t, "rf")
+
+    def _ptrs(self, rf, x, y, z, refl):
+        return _dev(x), _dev(y, x), _dev(z, x), _dev(refl, x), _dev(rf, x)
 
     def execute_into(self, rf, x, y, z, refl, stream=None):
         self._check_sizes(rf, x, y, z, refl)
-        check(lib().simus_rf_plan_execute(self._handle(), _dev(x), _dev(y), _dev(z), _dev(refl),
-                                          _dev(rf), _stream(stream)))
+        check(lib().simus_rf_plan_execute(self._handle(), *self._ptrs(rf, x, y, z, refl),
+                                          _stream(stream)))
 
     def graph_launch_into(self, rf, x, y, z, refl, stream=None):
         self._check_sizes(rf, x, y, z, refl)
-        check(lib().simus_rf_plan_graph_launch(self._handle(), _dev(x), _dev(y), _dev(z),
-                                               _dev(refl), _dev(rf), _stream(stream)))
+        check(lib().simus_rf_plan_graph_launch(self._handle(), *self._ptrs(rf, x, y, z, refl),
+                                               _stream(stream)))
 
     def autotune_into(self, rf, x, y, z, refl, stream=None) -> dict:
         """Runs the plan's autotuner on these scatterers; returns the chosen
@@ -315,8 +347,8 @@ class RFPlan:
         self._check_sizes(rf, x, y, z, refl)
         ts = C.c_int64()
         fl = C.c_int32()
-        check(lib().simus_rf_plan_autotune(self._handle(), _dev(x), _dev(y), _dev(z), _dev(refl),
-                                           _dev(rf), _stream(stream), C.byref(ts), C.byref(fl)))
+        check(lib().simus_rf_plan_autotune(self._handle(), *self._ptrs(rf, x, y, z, refl),
+                                           _stream(stream), C.byref(ts), C.byref(fl)))
         return dict(tile_scat=int(ts.value), flags=int(fl.value))
 
     def _handle(self):

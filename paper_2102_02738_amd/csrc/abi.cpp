@@ -50,8 +50,13 @@ const char* const kKindNames[K_COUNT] = {"synth",   "wtable",         "finalize"
                                          "adjoint", "adjoint_reduce", "pfield",   "graph"};
 
 // Set while this thread captures a graph: launches are then not bracketed by
-// timing events.
-thread_local bool t_capturing = false;
+// timing events (no event is created).
+thread_local bool t_untimed = false;
+
+struct Untimed {
+    Untimed() { t_untimed = true; }
+    ~Untimed() { t_untimed = false; }
+};
 
 struct Profiler {
     std::mutex mu;
@@ -99,7 +104,7 @@ Profiler g_prof;
 template <class F>
 hipError_t timed(Kind k, hipStream_t st, F&& launch)
 {
-    if (t_capturing) return launch();
+    if (t_untimed) return launch();
     {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (!g_prof.on) return launch();
@@ -400,13 +405,64 @@ struct FwdPlan {
     std::vector<char> host;
 };
 
+// Workspace layout of a forward plan with n_items work items: the upload
+// region (tables, items, draw order, per-phantom item bases and slice
+// counts) first, then the device-only tables, partial spectra, work counter
+// and, with own_spec, the spectra.  Sets F's offsets; returns the size.
+size_t fwd_layout(FwdPlan& F, int n_items, bool own_spec)
+{
+    const Common& C = F.C;
+    Layout up;
+    layout_upload(up, F.L, C);
+    F.o_it = up.add(sizeof(Item) * std::max(n_items, 1));
+    F.o_or = up.add(sizeof(int32_t) * std::max(n_items, 1));
+    F.o_pb = up.add(sizeof(int32_t) * C.ph.n);
+    F.o_ns = up.add(sizeof(int32_t) * C.ph.n);
+    Layout dv = up;
+    layout_device(dv, F.L, C);
+    F.o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * F.cfg.jt * F.cfg.tt * F.slots);
+    F.o_tk = dv.add(sizeof(int32_t) * 4);
+    const size_t spec_bytes = sizeof(float2) * size_t(C.ph.n) * C.n_tx * C.P.N * std::max(C.B.n_bins, 1);
+    F.o_spec = own_spec ? dv.add(spec_bytes) : 0;
+    F.up_size = up.size;
+    F.dv_size = dv.size;
+    return dv.size;
+}
+
+// The synthesis grid: as many blocks as can be resident at once for the
+// persistent launch, else one block per item.
+void set_launch_grid(FwdPlan& F, const simus_options* opt)
+{
+    SynthConfig& cfg = F.cfg;
+    // resident blocks draw items from a work counter (measurably faster than
+    // a static grid on both paths); SIMUS_FLAG_STATIC asks for one block per
+    // item on the vector path
+    cfg.persistent = (F.use_mt || !(opt->flags & SIMUS_FLAG_STATIC)) && F.n_items > 0;
+    if (cfg.persistent) {
+        hipDeviceProp_t prop;
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        const SynthKernel k = F.use_mt ? synth_mt_kernel(cfg) : synth_kernel(cfg);
+        if (!k) throw Error{SIMUS_EINVAL, "no synthesis kernel for this configuration"};
+        int per_cu = 0;
+        hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
+                                                               F.use_mt ? 512 : cfg.bs, 0),
+                  "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        cfg.grid = std::min(F.n_items, prop.multiProcessorCount * std::max(per_cu, 1));
+    } else {
+        cfg.grid = F.n_items;
+    }
+}
+
+// Everything before the launch grid is host work only.
 FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, const float* apod,
                       bool own_spec)
 {
     FwdPlan F;
     F.C = std::move(C);
     const Common& Cc = F.C;
-    const int N = Cc.P.N, M = Cc.P.M, n_tx = Cc.n_tx, n_ph = Cc.ph.n;
+    const int M = Cc.P.M, N = Cc.P.N, n_tx = Cc.n_tx, n_ph = Cc.ph.n;
     F.use_mt = !(opt->flags & SIMUS_FLAG_NO_MFMA) && mt_supported(M, N, n_tx) &&
                Cc.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
     SynthConfig& cfg = F.cfg;
@@ -434,9 +490,18 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     }
     // a multiple of the super-chunk (groups x chunk) that the kernel steps by
     const int SCG = SC * (F.use_mt ? 1 : std::max(cfg.groups, 1));
-    slice = std::max<int64_t>(slice, 4 * SCG);
-    slice = (slice + SCG - 1) / SCG * SCG;
-    slice = std::min<int64_t>(slice, int64_t(1) << 30);
+    auto round_slice = [&](int64_t sl) {
+        sl = std::max<int64_t>(sl, 4 * SCG);
+        sl = (sl + SCG - 1) / SCG * SCG;
+        return std::min<int64_t>(sl, int64_t(1) << 30);
+    };
+    slice = round_slice(slice);
+    auto count_items = [&](int64_t sl) {
+        int64_t n = 0;
+        for (int p = 0; p < n_ph; ++p) n += (Cc.ph.off[p + 1] - Cc.ph.off[p] + sl - 1) / sl;
+        return n * F.n_bt * n_tg;
+    };
+    if (count_items(slice) >= (int64_t(1) << 31)) throw Error{SIMUS_EINVAL, "too many work items"};
     F.slice = slice;
 
     std::vector<Item> items;
@@ -465,22 +530,8 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
 
-    Layout up;
-    layout_upload(up, F.L, Cc);
-    F.o_it = up.add(sizeof(Item) * std::max(F.n_items, 1));
-    F.o_or = up.add(sizeof(int32_t) * std::max(F.n_items, 1));
-    F.o_pb = up.add(sizeof(int32_t) * n_ph);
-    F.o_ns = up.add(sizeof(int32_t) * n_ph);
-    Layout dv = up;
-    layout_device(dv, F.L, Cc);
-    F.o_part = dv.add(sizeof(float2) * size_t(std::max(F.n_items, 1)) * JT * TT * F.slots);
-    F.o_tk = dv.add(sizeof(int32_t) * 4);
-    const size_t spec_bytes = sizeof(float2) * size_t(n_ph) * n_tx * N * std::max(Cc.B.n_bins, 1);
-    F.o_spec = own_spec ? dv.add(spec_bytes) : 0;
-    F.up_size = up.size;
-    F.dv_size = dv.size;
-
-    F.host.assign(up.size, 0);
+    fwd_layout(F, F.n_items, own_spec);
+    F.host.assign(F.up_size, 0);
     char* h = F.host.data();
     fill_upload(h, F.L, Cc, delays, apod);
     if (F.n_items) {
@@ -489,27 +540,7 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
     }
     std::memcpy(h + F.o_pb, pbase.data(), sizeof(int32_t) * n_ph);
     std::memcpy(h + F.o_ns, nsl.data(), sizeof(int32_t) * n_ph);
-
-    // resident blocks draw items from a work counter (measurably faster than
-    // a static grid on both paths); SIMUS_FLAG_STATIC asks for one block per
-    // item on the vector path
-    cfg.persistent = (F.use_mt || !(opt->flags & SIMUS_FLAG_STATIC)) && F.n_items > 0;
-    if (cfg.persistent) {
-        hipDeviceProp_t prop;
-        int dev = 0;
-        hip_check(hipGetDevice(&dev), "hipGetDevice");
-        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        // as many blocks as can be resident at once
-        const SynthKernel k = F.use_mt ? synth_mt_kernel(cfg) : synth_kernel(cfg);
-        if (!k) throw Error{SIMUS_EINVAL, "no synthesis kernel for this configuration"};
-        int per_cu = 0;
-        hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
-                                                               F.use_mt ? 512 : BS, 0),
-                  "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-        cfg.grid = std::min(F.n_items, prop.multiProcessorCount * std::max(per_cu, 1));
-    } else {
-        cfg.grid = F.n_items;
-    }
+    set_launch_grid(F, opt);
     return F;
 }
 
@@ -1012,16 +1043,14 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
             hip_check(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal),
                       "hipStreamBeginCapture");
             hipGraph_t g = nullptr;
-            t_capturing = true;
             try {
+                Untimed untimed;
                 enqueue_fwd(plan->F, plan->dev, x, y, z, refl, nullptr, rf, plan->cap);
             } catch (...) {
-                t_capturing = false;
                 (void)hipStreamEndCapture(plan->cap, &g);
                 if (g) (void)hipGraphDestroy(g);
                 throw;
             }
-            t_capturing = false;
             hip_check(hipStreamEndCapture(plan->cap, &g), "hipStreamEndCapture");
             const hipError_t e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);

@@ -111,6 +111,35 @@ struct GeoD {
     float r, y;
 };
 
+// A (sub-element, scatterer) pair in the sub-element's frame: squared
+// distance in FP64, the point's coordinates along the face (xl) and along
+// its normal (zl), and whether the pair lies in the model's domain: in front
+// of the face (zl > 0) and farther than 1e-9 m from the centroid.  Outside
+// it the pair's Green's term is 0 (a flat piston does not radiate behind its
+// face; Eq. 22's 1/r is undefined at r = 0).  The table of the elevation
+// term covers the distances of in-domain pairs only (k_rrange), so both use
+// this one test.
+struct PairFrame {
+    double r2;
+    float xl, zl;
+    bool ok;
+};
+
+template <bool HASY>
+__device__ __forceinline__ PairFrame pair_frame(const SubFrame& f, float px, float py, float pz)
+{
+    const double dx = (double)px - f.xc;
+    const double dz = (double)pz - f.zc;
+    const double yy = HASY ? (double)py : 0.0;
+    PairFrame p;
+    p.r2 = fma(dx, dx, fma(dz, dz, yy * yy));
+    const float dxf = (float)dx, dzf = (float)dz;
+    p.xl = dxf * f.tx + dzf * f.tz;
+    p.zl = dxf * f.nx + dzf * f.nz;
+    p.ok = (p.zl > 0.f) && (p.r2 > 1e-18);
+    return p;
+}
+
 // Set-up of a pair at bin j0: distance r in FP64, azimuthal angle theta of
 // the point seen from the sub-element face (Eq. 23), obliquity of Eq. (39).
 // With D != nullptr also the derivative data of the pair.
@@ -118,16 +147,12 @@ template <bool HASY, bool SMALL_SINC = false>
 __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, float px, float py,
                                         float pz, int j0, GeoD* D = nullptr)
 {
-    const double dx = (double)px - f.xc;
-    const double dz = (double)pz - f.zc;
-    const double yy = HASY ? (double)py : 0.0;
+    const PairFrame pf = pair_frame<HASY>(f, px, py, pz);
     // r in FP64 without a double-precision root: the FP32 root of the FP64
     // square, refined by one Newton step in FP64 (relative error ~1e-14)
-    const double r2 = fma(dx, dx, fma(dz, dz, yy * yy));
-    const float dxf = (float)dx, dzf = (float)dz;
-    const float xl = dxf * f.tx + dzf * f.tz;
-    const float zl = dxf * f.nx + dzf * f.nz;
-    const bool ok = (zl > 0.f) && (r2 > 1e-18);
+    const double r2 = pf.r2;
+    const float xl = pf.xl, zl = pf.zl;
+    const bool ok = pf.ok;
     const double r2s = ok ? r2 : 1.0;
     const float r2f = (float)r2s;
     const float inv_r0 = rsq_fast(r2f);

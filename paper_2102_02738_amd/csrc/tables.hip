@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "eq18.hpp"
+#include "green.hpp"
 #include "kernels.hpp"
 
 namespace simus {
@@ -17,26 +18,24 @@ __global__ void k_rr_init(uint32_t* rr)
     rr[1] = 0u;
 }
 
-// Min / max sub-element-to-scatterer distance over all pairs (FP32; the
-// table adds a margin).  Positive floats order like their bit patterns.
+// Min / max distance over the (sub-element, scatterer) pairs of the model's
+// domain (pair_frame: in front of the sub-element's face, farther than
+// 1e-9 m), which are the only pairs whose elevation term is read from the
+// table; as float bits (positive floats order like their bit patterns).
+// The table adds a margin.
 __global__ __launch_bounds__(256) void k_rrange(uint32_t* rr, const float* __restrict__ x,
                                                 const float* __restrict__ y,
                                                 const float* __restrict__ z, int64_t n, SubGeo sub,
                                                 int M)
 {
-    __shared__ float s_x[1024], s_z[1024];
-    for (int m = threadIdx.x; m < M; m += blockDim.x) {
-        s_x[m] = (float)sub.xc[m];
-        s_z[m] = (float)sub.zc[m];
-    }
-    __syncthreads();
     float lo = INFINITY, hi = 0.f;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
         const float px = x[s], pz = z[s], py = y ? y[s] : 0.f;
         for (int m = 0; m < M; ++m) {
-            const float dx = px - s_x[m], dz = pz - s_z[m];
-            const float r2 = fmaf(dx, dx, fmaf(dz, dz, py * py));
+            const PairFrame p = pair_frame<true>(load_frame(sub, m), px, py, pz);
+            if (!p.ok) continue;
+            const float r2 = (float)p.r2;
             lo = fminf(lo, r2);
             hi = fmaxf(hi, r2);
         }

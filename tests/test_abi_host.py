@@ -241,6 +241,36 @@ def test_binding_refuses_small_buffers(L):
                       x, None, z)
     with pytest.raises(L.SimusError, match="spec holds"):
         L.spectrum_to_rf_into(torch.empty(4 * n_t), torch.empty(4 * 2 * 10 - 1), 128, n_t, 1, 10, 4)
+    # offsets past the end of the scatterer arrays
+    with pytest.raises(L.SimusError, match="scat_offsets end at"):
+        L.rf_into(good, *args, x, None, z, R, offsets=[0, n + 1])
+    with pytest.raises(L.SimusError, match="scat_offsets end at"):
+        L.rf_backward_into({}, *args, x, None, z, R, good, offsets=[0, 2, n + 3])
+    # n_t = 0 means nfft samples per channel
+    o0 = dict(o, n_t=0)
+    with pytest.raises(L.SimusError, match="rf holds"):
+        L.rf_into(good, w["probe"], w["medium"], o0, w["delays"], w["apod"], x, None, z, R)
+    with pytest.raises(L.SimusError, match="drf holds"):
+        L.rf_backward_into({}, w["probe"], w["medium"], o0, w["delays"], w["apod"], x, None, z, R, good)
+    # the spectra of rf_spectrum_into: [n_ph][n_tx][N][n_bins] complex
+    n_bins = L.rf_grid(w["probe"], w["medium"], o, w["delays"], [], None, [])["n_bins"]
+    with pytest.raises(L.SimusError, match="spec holds"):
+        L.rf_spectrum_into(torch.empty(2 * n_tx * N * n_bins - 1), *args, x, None, z, R)
+    with pytest.raises(L.SimusError, match="device tensor expected"):
+        L.rf_spectrum_into(torch.empty(2 * n_tx * N * n_bins), *args, x, None, z, R)
+    # float32 only
+    with pytest.raises(L.SimusError, match="must be float32"):
+        L.rf_into(good.double(), *args, x, None, z, R)
+    with pytest.raises(L.SimusError, match="must be float32"):
+        L.rf_into(good, *args, x.double(), None, z, R)
+    # transmit arrays of the probe's shape
+    with pytest.raises(L.SimusError, match="apod holds"):
+        L.rf_into(good, w["probe"], w["medium"], o, w["delays"], w["apod"][:, :-1], x, None, z, R)
+    with pytest.raises(L.SimusError, match="delays hold"):
+        L.rf_into(good, w["probe"], w["medium"], o, w["delays"][:, :-1], None, x, None, z, R)
+    with pytest.raises(L.SimusError, match="delays hold"):
+        L.pfield_into(torch.empty(n), w["probe"], w["medium"], o, 10, w["delays"][0][:-1], None,
+                      x, None, z)
 
 
 def test_product_and_oracle_share_no_code():

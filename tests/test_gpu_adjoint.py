@@ -234,3 +234,40 @@ def test_adjoint_single_scatterer(S, orc, path):
     g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
     ref = oracle_grads(orc, w, g, rho[0])
     _check(got, ref, ["refl", "x", "z"])
+
+
+def test_adjoint_600_sub_elements(S, orc):
+    """300 elements with nu = 2: the vector adjoint over 600 sub-elements
+    (the matrix-core adjoint serves up to 128 elements) against the
+    oracle's adjoint."""
+    w = small(n_el=300, n_tx=2, n_scat=50, seed=8)
+    x, y, z, R, off = concat_phantoms(w["phantoms"])
+    g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
+    assert g0["nu"] == 2
+    rho = np.random.default_rng(8).standard_normal((1, 2, 300, g0["n_t"])).astype(np.float32)
+    g, got = gpu_grads(S, w, rho)
+    ref = oracle_grads(orc, w, g, rho[0])
+    _check(got, ref, ["refl", "x", "z"])
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_adjoint_out_of_domain_scatterers(S, path):
+    """Scatterers at z <= 0 before a linear array (G = 0 and dG = 0 on the
+    device): appended to a phantom they get exactly zero gradients, and the
+    other scatterers' gradients are bit for bit those without them."""
+    import torch
+    w = small(n_tx=3, n_scat=40, seed=13)
+    ph = w["phantoms"][0]
+    g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], ph["x"], None, ph["z"])
+    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"], flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    rng = np.random.default_rng(14)
+    xo = np.concatenate([ph["x"], rng.uniform(-3e-3, 3e-3, 10)]).astype(np.float32)
+    zo = np.concatenate([ph["z"], -rng.uniform(0, 2e-3, 10)]).astype(np.float32)
+    Ro = np.concatenate([ph["R"], rng.standard_normal(10)]).astype(np.float32)
+    (rho,) = to_dev(rng.standard_normal((1, 3, 8, g["n_t"])))
+    a = S.rf_backward(w["probe"], w["medium"], o, w["delays"], w["apod"], *to_dev(ph["x"], None, ph["z"], ph["R"]), rho)
+    b = S.rf_backward(w["probe"], w["medium"], o, w["delays"], w["apod"], *to_dev(xo, None, zo, Ro), rho)
+    torch.cuda.synchronize()
+    for k in ("refl", "x", "z"):
+        assert torch.equal(a[k], b[k][:40]), k
+        assert torch.all(b[k][40:] == 0), k

@@ -7,7 +7,8 @@ repeated calls and for the persistent launch.
 import numpy as np
 import pytest
 
-from tests.helpers import concat_phantoms, oracle_setup, rel_l2, sample_bins, to_dev
+from tests.helpers import (assert_grid_matches, band_peak_bin, concat_phantoms, oracle_setup,
+                           oracle_spectrum_split, rel_l2, sample_bins, to_dev)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -83,6 +84,7 @@ def test_spectrum_pw128_s50k_full_size_sampled_bins(S, orc):
     g, spec, data = _run(S, w, spectrum=True)
     bins = sample_bins(g, 6)
     x, y, z, R, off = data
+    assert_grid_matches(orc, w, g, x, None, z)
     ref = orc.spectrum(oracle_setup(orc, w), g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
     got = spec[0][:, :, bins - g["j_lo"]]
     print("pw128_s50k sampled bins rel L2", rel_l2(got, ref))
@@ -226,6 +228,7 @@ def test_many_transmits_full_size_sampled_bins(S, orc):
     g, spec, data = _run(S, w, spectrum=True)
     bins = sample_bins(g, 3)
     x, y, z, R, off = data
+    assert_grid_matches(orc, w, g, x, None, z)
     ref = orc.spectrum(oracle_setup(orc, w), g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
     got = spec[0][:, :, bins - g["j_lo"]]
     print("pw128x21_s200k sampled bins rel L2", rel_l2(got, ref))
@@ -235,23 +238,30 @@ def test_many_transmits_full_size_sampled_bins(S, orc):
 def test_uneven_phantoms_full_size_sampled_bins(S, orc):
     """16 convex-probe phantoms of 10k-390k scatterers x 11 diverging waves
     (2.27 M scatterers, the uneven-batch workload) in one persistent launch
-    on the matrix cores: the band's first and last bins of the smallest, a
-    middle and the largest phantom against the oracle."""
+    on the matrix cores: the band's first and last bins, the bin of peak
+    |S_P S_T| and the middle bin, for the smallest, a middle and the largest
+    phantom, against the oracle.  The grid is the oracle's."""
     from paper_2102_02738_amd import inputs
     w = inputs.workload("cvx128x11_p16")
     g, spec, data = _run(S, w, flags=S.FLAG_PERSISTENT, spectrum=True)
     x, y, z, R, off = data
+    assert_grid_matches(orc, w, g, x, None, z)
     sizes = np.diff(off)
     order = np.argsort(sizes)
-    bins = sample_bins(g, 2)
     su = oracle_setup(orc, w)
+    peak = band_peak_bin(orc, su, g)
+    bins = np.unique(np.concatenate([sample_bins(g, 2), [peak, g["j_lo"] + g["n_bins"] // 2]]))
+    assert bins.size == 4
     for p in (order[0], order[len(order) // 2], order[-1]):
         sl = slice(off[p], off[p + 1])
-        ref = orc.spectrum(su, g["nfft"], w["delays"], w["apod"], x[sl], np.zeros(sizes[p]), z[sl], R[sl], bins)
+        ref = oracle_spectrum_split(orc, su, g["nfft"], w["delays"], w["apod"], x[sl], None, z[sl],
+                                    R[sl], bins, parts=4)
         got = spec[p][:, :, bins - g["j_lo"]]
         e = rel_l2(got, ref)
-        print("phantom", p, "scatterers", sizes[p], "sampled bins rel L2", e)
+        print("phantom", p, "scatterers", sizes[p], "bins", bins, "rel L2", e)
         assert e <= TOL
+        for k in range(bins.size):
+            assert rel_l2(got[..., k], ref[..., k]) <= 3 * TOL, (bins[k], rel_l2(got[..., k], ref[..., k]))
 
 
 def test_large_t_focused_small_full_rf(S, orc):
@@ -273,6 +283,7 @@ def test_large_t_focused_full_size_sampled_bins(S, orc):
     g, spec, data = _run(S, w, spectrum=True)
     bins = sample_bins(g, 3)
     x, y, z, R, off = data
+    assert_grid_matches(orc, w, g, x, None, z)
     ref = orc.spectrum(oracle_setup(orc, w), g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
     got = spec[0][:, :, bins - g["j_lo"]]
     print("ph64x128_s40k sampled bins rel L2", rel_l2(got, ref))
@@ -356,3 +367,55 @@ def test_grouped_small_probes(S, orc, kind, n):
     assert rel_l2(rf, ref) <= TOL
     _, rf_static, _ = _run(S, w, flags=S.FLAG_STATIC)
     assert np.array_equal(rf, rf_static)
+
+
+@pytest.mark.parametrize("n_tx", [1, 2])
+def test_1024_thread_vector_kernel(S, orc, n_tx):
+    """300 elements with nu = 2 (600 sub-elements) run the vector synthesis
+    in 1024-thread blocks (6-bin tiles): full RF against the oracle, one
+    transmit (8-scatterer chunks) and a pair of transmits (4-scatterer
+    chunks), 300 scatterers (ragged last chunk)."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=1.5)
+    w["probe"] = inputs.linear_probe(300)
+    w["delays"] = inputs.plane_wave_delays(w["probe"], np.linspace(-6, 6, n_tx))
+    w["apod"] = np.random.default_rng(n_tx).uniform(0.4, 1.0, w["delays"].shape).astype(np.float32)
+    w["phantoms"][0]["x"] = (w["phantoms"][0]["x"] * 4).astype(np.float32)
+    g, rf, data = _run(S, w)
+    assert g["nu"] == 2
+    ref = _oracle_rf(orc, w, g, data)
+    print("300 elements,", n_tx, "tx rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["vector", "mfma"])
+def test_out_of_domain_scatterers_add_nothing(S, orc, kind):
+    """Scatterers at z <= 0 before a linear array lie behind every
+    sub-element (G = 0 on the device, no EDOMAIN there): appended to a
+    phantom, with the partition into work items fixed, they leave its RF
+    bit for bit unchanged (on the vector path and on the matrix cores)."""
+    import torch
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=1.28)            # 256 scatterers
+    if kind == "mfma":
+        w["delays"] = inputs.plane_wave_delays(w["probe"], np.linspace(-8, 8, 5))
+        w["apod"] = np.ones(w["delays"].shape, np.float32)
+    ph = w["phantoms"][0]
+    n = ph["x"].size
+    assert n == 256
+    g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], ph["x"], None, ph["z"])
+    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"], tile_scat=128)
+    rng = np.random.default_rng(17)
+    k = 128
+    xo = np.concatenate([ph["x"], rng.uniform(-6e-3, 6e-3, k)]).astype(np.float32)
+    zo = np.concatenate([ph["z"], -rng.uniform(0, 5e-3, k)]).astype(np.float32)
+    zo[n] = 0.0
+    Ro = np.concatenate([ph["R"], rng.standard_normal(k)]).astype(np.float32)
+    dx, dz, dR = to_dev(ph["x"], ph["z"], ph["R"])
+    ex, ez, eR = to_dev(xo, zo, Ro)
+    a = S.rf(w["probe"], w["medium"], o, w["delays"], w["apod"], dx, None, dz, dR)
+    b = S.rf(w["probe"], w["medium"], o, w["delays"], w["apod"], ex, None, ez, eR)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ref = _oracle_rf(orc, w, g, (ph["x"], ph["y"], ph["z"], ph["R"], np.array([0, n])))
+    assert rel_l2(b.cpu().numpy(), ref) <= TOL

@@ -89,8 +89,9 @@ def test_delta_approximates_rectangle_integral(orc):
 @pytest.mark.parametrize("theta_deg", [0.0, 5.0, 20.0, 45.0, 70.0, -30.0])
 def test_directivity_is_the_aperture_integral(orc, theta_deg):
     """Rigid baffle D = sinc(kb sin(theta)) must equal (1/2b) times the
-    integral of Eq. (10), computed by quadrature; soft and finite-impedance
-    baffles multiply it by the obliquity factors of Eq. (39)."""
+    integral of Eq. (10), computed by quadrature; the soft baffle multiplies
+    it by cos(theta) (Eq. 39).  The finite-impedance factor is pinned by its
+    limits below."""
     f, b = 7.6e6, 0.135e-3
     k = 2 * np.pi * f / 1540.0
     th = math.radians(theta_deg)
@@ -99,10 +100,71 @@ def test_directivity_is_the_aperture_integral(orc, theta_deg):
     assert abs(integ.imag) < 1e-12
     rigid = orc.directivity(setup(orc, baffle=1), math.sin(th), math.cos(th), k, b)
     soft = orc.directivity(setup(orc, baffle=0), math.sin(th), math.cos(th), k, b)
-    zeta = orc.directivity(setup(orc, baffle=2, zeta=1.75), math.sin(th), math.cos(th), k, b)
     assert abs(rigid - integ.real) < 1e-8
     assert abs(soft - integ.real * math.cos(th)) < 1e-8
-    assert abs(zeta - integ.real * math.cos(th) / (math.cos(th) + 1.75)) < 1e-8
+
+
+# zeta is the ratio of the medium's impedance to the baffle's (Eq. 39 and the
+# text that defines it): a baffle of infinite impedance (zeta = 0) is the
+# rigid baffle, and one of vanishing impedance (zeta -> inf) the soft baffle,
+# whose obliquity cos(theta) the finite-impedance factor approaches as
+# zeta * D(zeta).  These two limits fix the factor's form independently of
+# the oracle's own formula.
+ZETA_BIG = 1e9
+
+
+@pytest.mark.parametrize("theta_deg", [0.0, 12.0, 35.0, -50.0, 80.0])
+def test_impedance_baffle_limits_directivity(orc, theta_deg):
+    f, b = 7.6e6, 0.135e-3
+    k = 2 * np.pi * f / 1540.0
+    th = math.radians(theta_deg)
+    s, c = math.sin(th), math.cos(th)
+    rigid = orc.directivity(setup(orc, baffle=1), s, c, k, b)
+    soft = orc.directivity(setup(orc, baffle=0), s, c, k, b)
+    z0 = orc.directivity(setup(orc, baffle=2, zeta=0.0), s, c, k, b)
+    zinf = orc.directivity(setup(orc, baffle=2, zeta=ZETA_BIG), s, c, k, b)
+    # zeta = 0: the rigid value up to the rounding of (s c) / c
+    assert abs(z0 - rigid) <= 1e-15 * abs(rigid)
+    assert abs(ZETA_BIG * zinf - soft) <= 1e-8 * abs(soft) + 1e-300
+    # between the limits the factor lies strictly between 0 and the rigid value
+    mid = orc.directivity(setup(orc, baffle=2, zeta=1.75), s, c, k, b)
+    assert abs(mid) < abs(rigid) or rigid == 0.0
+
+
+def test_impedance_baffle_limits_green_and_spectrum(orc):
+    """The same limits through the whole model: the sub-element Green's term
+    (Eqs. 19-20, 39), the two-way element spectra (Eqs. 29-34, quadratic in
+    the obliquity, so zeta^2 X -> X_soft) and the adjoint's gradients."""
+    kw = dict(n_elements=3, nu=2, alpha_db=0.5)
+    rigid, soft = setup(orc, baffle=1, **kw), setup(orc, baffle=0, **kw)
+    z0, zinf = setup(orc, baffle=2, zeta=0.0, **kw), setup(orc, baffle=2, zeta=ZETA_BIG, **kw)
+    pts = [(1e-3, 0.0, 8e-3), (-2.5e-3, 0.4e-3, 15e-3), (4e-3, 0.0, 6e-3)]
+    for n in range(6):
+        for X, Y, Z in pts:
+            w = 2 * np.pi * 6.5e6
+            gr, gs = orc.green(rigid, n, X, Y, Z, w), orc.green(soft, n, X, Y, Z, w)
+            assert abs(orc.green(z0, n, X, Y, Z, w) - gr) <= 1e-15 * abs(gr)
+            assert abs(ZETA_BIG * orc.green(zinf, n, X, Y, Z, w) - gs) <= 1e-8 * abs(gs)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-3e-3, 3e-3, 6)
+    z = rng.uniform(5e-3, 20e-3, 6)
+    y = np.zeros(6)
+    R = rng.standard_normal(6)
+    dl = np.linspace(0, 1e-7, 3)[None, :]
+    ap = np.ones((1, 3))
+    g = orc.grid(soft, dl, x, y, z)
+    bins = orc.all_bins(g)[::7]
+    Xr = orc.spectrum(rigid, g["nfft"], dl, ap, x, y, z, R, bins)
+    Xs = orc.spectrum(soft, g["nfft"], dl, ap, x, y, z, R, bins)
+    assert np.linalg.norm(orc.spectrum(z0, g["nfft"], dl, ap, x, y, z, R, bins) - Xr) <= 1e-13 * np.linalg.norm(Xr)
+    Xz = orc.spectrum(zinf, g["nfft"], dl, ap, x, y, z, R, bins) * ZETA_BIG ** 2
+    assert np.linalg.norm(Xz - Xs) <= 1e-7 * np.linalg.norm(Xs)
+    rho = rng.standard_normal((1, 3, g["n_t"]))
+    ar, as_ = orc.adjoint(rigid, g, dl, ap, x, y, z, R, rho), orc.adjoint(soft, g, dl, ap, x, y, z, R, rho)
+    a0, ai = orc.adjoint(z0, g, dl, ap, x, y, z, R, rho), orc.adjoint(zinf, g, dl, ap, x, y, z, R, rho)
+    for key in ("R", "x", "z"):
+        assert np.linalg.norm(a0[key] - ar[key]) <= 1e-13 * np.linalg.norm(ar[key])
+        assert np.linalg.norm(ai[key] * ZETA_BIG ** 2 - as_[key]) <= 1e-7 * np.linalg.norm(as_[key])
 
 
 # ----------------------------------------------------------------- Eqs. 25-27, 47-49
