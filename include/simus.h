@@ -76,6 +76,7 @@ extern "C" {
 #define SIMUS_EDOMAIN (-2)  /* scatterer outside the model's domain (simus_rf_grid only) */
 #define SIMUS_ENOMEM (-3)   /* device or pinned host allocation failed */
 #define SIMUS_EHIP (-4)     /* a HIP runtime call failed */
+#define SIMUS_ETOOBIG (-5)  /* simus_rf_noalloc: the call needs more than its scratch */
 
 typedef enum {
     SIMUS_BAFFLE_SOFT = 0,   /* D = sinc(k b sin t) cos t   (Eq. 39, default) */
@@ -197,6 +198,32 @@ int simus_rf(const simus_probe* probe, const simus_medium* medium,
              int32_t n_phantoms, const int64_t* scat_offsets,
              const float* x, const float* y, const float* z, const float* refl,
              float* rf, void* hip_stream);
+
+/* simus_rf without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, grid rules and results as simus_rf (to
+ * rounding order; bit for bit when the default work-item partition fits).
+ * The workspace is a static device array of the library, 64 MiB per GPU,
+ * which the GPU holds from the library's first use there until the process
+ * ends; the call allocates nothing (no hipMalloc, hipFree, pinned staging or
+ * event).  A call whose workspace would exceed the scratch gets longer
+ * work items (fewer partial spectra) until it fits; one that cannot fit even
+ * then returns SIMUS_ETOOBIG before any HIP call.  The bound is roughly 2e6
+ * spectral values n_phantoms x n_tx x N x n_bins (a 128-element plane wave
+ * with 850 bins fits; 21 transmits of it do not).  The host
+ * tables (about 20 bytes per work item plus the probe's frames and weights)
+ * are copied from pageable host memory with hipMemcpyAsync, which may wait
+ * for the stream's earlier work.  Every call on a GPU shares that GPU's
+ * scratch, and the scratch keeps the last call's contents: calls that may
+ * overlap on one GPU (different streams, or several host threads) race and
+ * must be serialised by the caller.  Kernel timing (simus_profile_enable)
+ * does not record these calls. */
+int simus_rf_noalloc(const simus_probe* probe, const simus_medium* medium,
+                     const simus_options* options, int32_t n_tx,
+                     const double* delays, const float* apod,
+                     int32_t n_phantoms, const int64_t* scat_offsets,
+                     const float* x, const float* y, const float* z, const float* refl,
+                     float* rf, void* hip_stream);
 
 /* Inverse transform alone: rf[c][q] = Re sum_b spec[c][b] exp(-2 pi i (j_lo + b) q / nfft)
  * for q < n_t.  spec: device [n_chan][n_bins][2]; rf: device [n_chan][n_t]. */

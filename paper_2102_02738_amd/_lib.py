@@ -15,7 +15,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsimus.so")
 
 SIMUS_OK = 0
-ERRORS = {-1: "SIMUS_EINVAL", -2: "SIMUS_EDOMAIN", -3: "SIMUS_ENOMEM", -4: "SIMUS_EHIP"}
+ERRORS = {-1: "SIMUS_EINVAL", -2: "SIMUS_EDOMAIN", -3: "SIMUS_ENOMEM", -4: "SIMUS_EHIP",
+          -5: "SIMUS_ETOOBIG"}
 FLAG_NO_MFMA = 1
 FLAG_PERSISTENT = 2
 FLAG_NO_DELTA_TABLE = 4
@@ -25,6 +26,7 @@ FLAG_ALT_SHAPE = 32
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",
+           "simus_rf_noalloc",
            "simus_spectrum_to_rf", "simus_rf_backward", "simus_pfield_nf", "simus_pfield",
            "simus_rf_plan_create", "simus_rf_plan_execute", "simus_rf_plan_graph_launch",
            "simus_rf_plan_autotune", "simus_rf_plan_destroy", "simus_release_workspace", "simus_profile_enable",
@@ -83,6 +85,7 @@ def lib():
             "simus_rf_grid": (C.c_int, [pP, pM, pO, i32, pd, i64, pf, pf, pf, pG]),
             "simus_rf_spectrum": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp, vp]),
             "simus_rf": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp, vp]),
+            "simus_rf_noalloc": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp, vp]),
             "simus_spectrum_to_rf": (C.c_int, [i32, i32, i32, i32, i64, vp, vp, vp]),
             "simus_rf_backward": (C.c_int, [pP, pM, pO, i32, pd, pf, i32, pi64, vp, vp, vp, vp, vp,
                                             vp, vp, vp, vp, vp]),
@@ -259,6 +262,19 @@ def rf_into(rf, probe, medium, options, delays, apod, x, y, z, refl, offsets=Non
                          C.byref(make_options(options)), n_tx, _p(d, C.c_double), _p(a, C.c_float),
                          n_ph, _p(o, C.c_int64), _dev(x), _dev(y, x), _dev(z, x), _dev(refl, x),
                          _dev(rf, x), _stream(stream)))
+
+
+def rf_noalloc_into(rf, probe, medium, options, delays, apod, x, y, z, refl, offsets=None,
+                    stream=None):
+    """simus_rf_noalloc: as rf_into, with the library's static scratch as
+    workspace (no allocation)."""
+    d, a, n_tx = _tx(probe, delays, apod)
+    o, n_ph = _offsets(offsets, _scatterers(x, y, z, refl, offsets))
+    _need(rf, n_ph * n_tx * int(probe["n_elements"]) * _n_t(options), "rf")
+    check(lib().simus_rf_noalloc(C.byref(make_probe(probe)), C.byref(make_medium(medium)),
+                                 C.byref(make_options(options)), n_tx, _p(d, C.c_double),
+                                 _p(a, C.c_float), n_ph, _p(o, C.c_int64), _dev(x), _dev(y, x),
+                                 _dev(z, x), _dev(refl, x), _dev(rf, x), _stream(stream)))
 
 
 def spectrum_to_rf_into(rf, spec, nfft, n_t, j_lo, n_bins, n_chan, stream=None):

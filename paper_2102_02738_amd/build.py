@@ -21,7 +21,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-fno-gpu-rdc", "-munsafe-fp-atomics"]
 
 SOURCES = [("kernels.hip", True), ("synth_mfma.hip", True), ("tables.hip", True), ("adjoint.hip", True),
-           ("adjoint_mfma.hip", True), ("pfield.hip", True),
+           ("adjoint_mfma.hip", True), ("pfield.hip", True), ("noalloc.hip", True),
            ("abi.cpp", False), ("plan.cpp", False)]
 
 

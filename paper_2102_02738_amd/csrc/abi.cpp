@@ -49,8 +49,8 @@ enum Kind { K_SYNTH, K_WTABLE, K_FINALIZE, K_IDFT, K_DFT, K_ADJ, K_ADJRED, K_PFI
 const char* const kKindNames[K_COUNT] = {"synth",   "wtable",         "finalize", "idft", "dft",
                                          "adjoint", "adjoint_reduce", "pfield",   "graph"};
 
-// Set while this thread captures a graph: launches are then not bracketed by
-// timing events (no event is created).
+// Set while this thread captures a graph or runs simus_rf_noalloc: launches
+// are then not bracketed by timing events (no event is created).
 thread_local bool t_untimed = false;
 
 struct Untimed {
@@ -455,9 +455,12 @@ void set_launch_grid(FwdPlan& F, const simus_options* opt)
     }
 }
 
-// Everything before the launch grid is host work only.
+// max_dev_bytes > 0 bounds the workspace (simus_rf_noalloc's scratch): the
+// scatterers per item grow until the plan fits, and a plan that does not fit
+// even with one slice per phantom, bin tile and transmit group throws
+// SIMUS_ETOOBIG.  Everything before the launch grid is host work only.
 FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, const float* apod,
-                      bool own_spec)
+                      bool own_spec, size_t max_dev_bytes = 0)
 {
     FwdPlan F;
     F.C = std::move(C);
@@ -501,6 +504,22 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
         for (int p = 0; p < n_ph; ++p) n += (Cc.ph.off[p + 1] - Cc.ph.off[p] + sl - 1) / sl;
         return n * F.n_bt * n_tg;
     };
+    if (max_dev_bytes > 0) {
+        int64_t s_max = 1;
+        for (int p = 0; p < n_ph; ++p) s_max = std::max(s_max, Cc.ph.off[p + 1] - Cc.ph.off[p]);
+        s_max = round_slice(s_max);
+        for (;;) {
+            const int64_t ni = count_items(slice);
+            if (ni < (int64_t(1) << 30) && fwd_layout(F, (int)ni, own_spec) <= max_dev_bytes) break;
+            if (slice >= s_max) {
+                fwd_layout(F, (int)std::min<int64_t>(ni, int64_t(1) << 30), own_spec);
+                throw Error{SIMUS_ETOOBIG, "the call needs " + std::to_string(F.dv_size) +
+                                               " bytes of workspace; the no-allocation scratch holds " +
+                                               std::to_string(max_dev_bytes)};
+            }
+            slice = std::min(s_max, round_slice(slice + slice / 4));
+        }
+    }
     if (count_items(slice) >= (int64_t(1) << 31)) throw Error{SIMUS_EINVAL, "too many work items"};
     F.slice = slice;
 
@@ -946,6 +965,31 @@ int simus_rf(const simus_probe* probe, const simus_medium* medium, const simus_o
         if (!rf) throw Error{SIMUS_EINVAL, "rf must be non-NULL"};
         forward_spectra(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl, nullptr,
                         rf, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int simus_rf_noalloc(const simus_probe* probe, const simus_medium* medium,
+                     const simus_options* opt, int32_t n_tx, const double* delays,
+                     const float* apod, int32_t n_ph, const int64_t* offs, const float* x,
+                     const float* y, const float* z, const float* refl, float* rf,
+                     void* hip_stream)
+{
+    return guarded([&] {
+        if (!rf) throw Error{SIMUS_EINVAL, "rf must be non-NULL"};
+        Common C = make_common(probe, medium, opt, n_tx, delays, apod, n_ph, offs, x, y, z, refl);
+        // host work only up to here: a call that cannot fit the scratch is
+        // refused (SIMUS_ETOOBIG) before any HIP call
+        const FwdPlan F = make_fwd_plan(std::move(C), opt, delays, apod, true, NOALLOC_SCRATCH_BYTES);
+        char* d = nullptr;
+        hip_check(noalloc_scratch(&d), "scratch address");
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        // the plan's tables, from pageable host memory: the runtime copies
+        // them out of F.host before the call returns (HIP's pageable-copy
+        // semantics), so F.host may go when this function ends
+        hip_check(hipMemcpyAsync(d, F.host.data(), F.up_size, hipMemcpyHostToDevice, st),
+                  "hipMemcpyAsync");
+        Untimed untimed;
+        enqueue_fwd(F, d, x, y, z, refl, nullptr, rf, st);
     });
 }
 

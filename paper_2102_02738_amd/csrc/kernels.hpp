@@ -218,6 +218,12 @@ hipError_t launch_idft(float* rf, const float2* spec, int64_t n_chan, int n_bins
                        int nfft, int n_t, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
+// Scratch of simus_rf_noalloc: one static device array per GPU of this many
+// bytes (noalloc.hip).  noalloc_scratch gives its device address on the
+// current device (looked up on the device's first call, then kept).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+hipError_t noalloc_scratch(char** ptr);
+
 // Range of sub-element-to-scatterer distances (as float bits, [0] = min,
 // [1] = max) over all pairs, then the elevation table for the call's range
 // of q = (pi f / c)(1/R_f - 1/r), f over the evaluated band.
