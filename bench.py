@@ -1,25 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the SIMUS RF synthesis hot path on one MI355X.
 
-Main line: one step = one simus_rf call on the 128-element, 50,000-scatterer
-plane-wave workload (pw128_s50k): transmit weights, elevation table,
-Green's-tile synthesis with both contractions, finalisation and the inverse
-transform to RF, inputs already resident in HBM.  Prints one JSON line.
+Main line: one step = one replay of the persistent HIP graph of a simus_rf
+plan on the batched uneven-phantom workload (cvx128x11_p16): a convex
+128-element array, 11 diverging waves, 16 phantoms of 10k-390k scatterers
+(2.27 M in all).  A step runs every row of the path: transmit weights,
+elevation table, Green's-tile synthesis with both contractions on the
+matrix cores, finalisation and the inverse transform to RF, with the inputs
+already resident in HBM.  The plan (host planning, upload) is built once
+before the timed region; one whole simus_rf call is timed beside it.
+Prints one JSON line.
 
 Extras in the same line (skipped with --no-extras), each against the plain
 path (a per-transmit, per-phantom loop of single-transmit calls on the
-vector path, no graph):
+vector path, no graph) where one exists:
+  single_transmit     the 128-element, 50,000-scatterer plane wave on the
+                      vector path (k_synth), with its roofline
+  autotune            the autotuner on the single-transmit and the uneven
+                      workloads
   batched_transmits   21 plane waves x 200,000 scatterers in one call
-                      (transmit and receive contractions on the matrix cores)
-  uneven_phantoms     16 convex-probe phantoms of 10k-500k scatterers x 11
-                      diverging waves in one persistent launch replayed as a
-                      HIP graph
+  uneven_phantoms     the main workload against its plain loop
   forward_adjoint     5 plane waves x 100,000 scatterers: forward, residual
                       against a perturbed phantom's RF, adjoint gradients
-  two_d               the main workload in 2-D acoustics (Section V), with the
-                      synthesis kernel's roofline
+  two_d               the single-transmit workload in 2-D acoustics
   large_t             128 focused transmits of a 64-element phased array,
                       40,000 scatterers (the shape of Fig. 12's sequence)
+  pfield              the RMS field of a Fig. 9-like focused phased array
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
 """
@@ -36,10 +42,41 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Issue-cost model of the synthesis kernel this workload runs,
+# Algorithmic work of the path, in lane issue slots of the FP32 vector unit
+# (a full-rate VALU lane-instruction is one slot, a transcendental four; an
+# FP32 MFMA lane-MAC is one slot as well, since the FP32 matrix rate equals
+# the FP32 FMA rate on gfx950: 157.3 TFLOP/s each).  Counted from the
+# formulas the library evaluates, not from the instructions its kernels
+# issue: no pair set-up (it is amortised over a tile of bins), no address
+# arithmetic, no padding of transmit groups, no waits.
+#   One Green's term (Eqs. 10, 14-20, 39-40 by the bin recurrences and the
+#   elevation table): q = j kappa (1); table coordinate r = rcp(|b| dw + 1)
+#   (1 + 4), u = med3(fma(b, r, u0)) (2), interval and fraction (2); the
+#   complex cubic (6); A = E s (2); G = A delta (4); rotor E dE (4); sinc
+#   recurrence (2): 28 slots.
+G_EVAL_SLOTS = 28.0
+#   Element sum of Eqs. 32-33 for nu = 2: one complex add per element, i.e.
+#   one slot per G term ((nu - 1) / nu * 2 in general).
+#   The two contractions (Eq. 29 over elements after the sum, Eq. 33): two
+#   complex MACs per (element, scatterer, transmit, bin): 3 real MACs each on
+#   the matrix cores (three-product form), 4 FMAs each on the VALU.
+CMAC_SLOTS_MFMA = 3.0
+CMAC_SLOTS_VALU = 4.0
+
+
+def alg_slots(S: float, M: int, N: int, T: int, n_bins: int, nu: int, mfma: bool) -> float:
+    """Algorithmic issue slots of one synthesis over S scatterers (see above)."""
+    g_terms = S * M * n_bins
+    per_g = G_EVAL_SLOTS + 2.0 * (nu - 1) / nu
+    cm = CMAC_SLOTS_MFMA if mfma else CMAC_SLOTS_VALU
+    return g_terms * per_g + 2.0 * S * N * T * n_bins * cm + 2.0 * S * T * n_bins
+
+
+# Instruction count of the single-transmit vector kernel,
 # k_synth<256, 8, 27, 1, false, 1, true, 1>: instructions per Green's term in
 # its innermost loop (two bins of 8 scatterers per lane and iteration),
-# counted from the gfx950 assembly with paper_2102_02738_amd/diag/isa_count.py.
+# counted from the gfx950 assembly with paper_2102_02738_amd/diag/isa_count.py
+# (its issue count, beside the algorithmic count above).
 SYNTH_KERNEL = "_ZN5simus7k_synthILi256ELi8ELi27ELi1ELb0ELi1ELb1ELi1EEEvNS_9SynthArgsE"
 SYNTH_TERMS_PER_ITER = 16
 SYNTH_VALU_PER_G = 33.0        # full-rate VALU instructions per G term
@@ -54,52 +91,85 @@ TRANS_ISSUE_COST = 4.0         # a transcendental issues at 1/4 of the FP32 rate
 # (256 CU x 128 FP32 lanes/clk x 2.4 GHz); one "slot" = one lane-instruction.
 VALU_PEAK = 256 * 128 * 2.4e9
 MFMA_FP32_PEAK = 157.3e12      # dense FP32 matrix-core FLOP/s
+# The main workload's synthesis kernel (16-column transmit groups, 128
+# element slots, 4 bins per item, nu = 2, three-product receive sums, y = 0,
+# elevation table).
+MT_KERNEL = "k_synth_mt<128, 1, 4, 2, 3, false, true>"
 
 
-def kernel_sources_digest() -> str:
+def kernel_sources_digest(files) -> str:
     h = hashlib.sha256()
-    # the kernel and its launch configuration (items, tiles) decide the traffic
-    for f in ["kernels.hip", "green.hpp", "kernels.hpp", "abi.cpp"]:
+    # the kernel and its launch configuration (items, tiles) decide the counts
+    for f in files:
         with open(os.path.join(ROOT, "paper_2102_02738_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per synthesis launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"synth_{workload}_traffic.txt")
+VECTOR_SOURCES = ["kernels.hip", "green.hpp", "kernels.hpp", "abi.cpp"]
+MT_SOURCES = ["synth_mfma.hip", "green.hpp", "kernels.hpp", "abi.cpp"]
+
+
+def profile_summary(name: str, files) -> dict:
+    """key: value lines of a committed rocprofv3 summary under profiles/, if
+    it was taken on the current kernel sources (else {})."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_sources") != kernel_sources_digest():
-        return None
+    if vals.get("kernel_sources") != kernel_sources_digest(files):
+        return {}
+    return vals
+
+
+def measured_traffic(name: str, files):
+    """HBM bytes per synthesis launch from a committed counter summary."""
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(profile_summary(name, files)["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(w, g, x, y, z, R, stride: int):
-    """The FP64 oracle on every `stride`-th evaluated bin (all scatterers)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, g, x, y, z, R, off, bin_stride: int, scat_stride: int):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    every `bin_stride`-th evaluated bin and every `scat_stride`-th scatterer
+    of each phantom, all transmits and elements.  Its cost is linear in
+    scatterers and bins, so the rate (evals/s) stands for the whole job."""
     import numpy as np
     from oracle import oracle as O
     from tests.helpers import oracle_setup
     su = oracle_setup(O, w)
-    bins = np.arange(g["j_lo"], g["j_lo"] + g["n_bins"], stride, dtype=np.int32)
+    bins = np.arange(g["j_lo"], g["j_lo"] + g["n_bins"], bin_stride, dtype=np.int32)
     t0 = time.perf_counter()
-    O.spectrum(su, g["nfft"], w["delays"], w["apod"], x, y, z, R, bins)
+    n_s = 0
+    for p in range(len(off) - 1):
+        sl = slice(int(off[p]), int(off[p + 1]), scat_stride)
+        if x[sl].size == 0:
+            continue
+        n_s += x[sl].size
+        O.spectrum(su, g["nfft"], w["delays"], w["apod"], x[sl], y[sl], z[sl], R[sl], bins)
     dt = time.perf_counter() - t0
     T = w["delays"].shape[0]
-    evals = x.size * w["probe"]["n_elements"] * bins.size * T
+    evals = n_s * w["probe"]["n_elements"] * bins.size * T
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=evals / dt, unit="evals/s", cores=threads, kind="oracle",
-                sample=f"{w['name']}: all {x.size} scatterers, every {stride}th of {g['n_bins']} "
-                       f"bins ({bins.size} bins), direct FP64 sum, {dt:.1f} s")
+    return dict(value=evals / dt, unit="evals/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
+                sample=f"{w['name']}: every {scat_stride}th scatterer of each of {len(off) - 1} phantoms "
+                       f"({n_s} of {x.size}), every {bin_stride}th of {g['n_bins']} bins ({bins.size}), "
+                       f"{T} transmits, direct FP64 sum, {dt:.1f} s")
 
 
 def _sync_ms(fn) -> float:
@@ -176,29 +246,31 @@ def extra_batched_transmits(steps: int) -> dict:
     synth_ms, n = _lib.profile_read("synth")
     synth_ms /= max(n, 1)
     p_ms = _median_ms(loop, 1, warmup=0)
-    # contraction flops (algorithmic, 21 transmits): Tx over nu N sub-elements
-    # and Rx over N elements, 8 real flops per complex multiply-add
-    flops = 8.0 * c.S * c.g["n_bins"] * c.T * (c.g["nu"] * c.N + c.N)
+    # contraction flops: Tx (Eq. 29, over elements after the element sum) and
+    # Rx (Eq. 33), 8 real flops per complex multiply-add
+    flops = 8.0 * c.S * c.g["n_bins"] * c.T * 2 * c.N
+    alg = alg_slots(c.S, c.g["nu"] * c.N, c.N, c.T, c.g["n_bins"], c.g["nu"], True)
     return dict(workload=c.name, n_tx=c.T, n_scatterers=c.S, n_bins=c.g["n_bins"],
                 batched_ms=b_ms, plain_ms=p_ms, speedup_vs_plain=p_ms / b_ms,
                 evals_per_s=c.evals() / (b_ms * 1e-3), rf_frames_per_s=c.T / (b_ms * 1e-3),
                 synth_kernel_ms=synth_ms,
-                mfma_contraction_tflops=flops / (synth_ms * 1e-3) / 1e12,
-                mfma_frac_of_fp32_peak=flops / (synth_ms * 1e-3) / MFMA_FP32_PEAK,
+                roofline=dict(bound="alu", achieved=alg / (synth_ms * 1e-3) / 1e12,
+                              peak=VALU_PEAK / 1e12, unit="TOP/s",
+                              frac=alg / (synth_ms * 1e-3) / VALU_PEAK),
+                contraction_tflops=flops / (synth_ms * 1e-3) / 1e12,
                 rel_l2_batched_vs_plain=_rel(out, plain))
 
 
 def extra_uneven_phantoms(steps: int) -> dict:
-    """16 uneven phantoms x 11 diverging waves: one persistent graph launch
-    vs a loop of single-phantom, single-transmit calls."""
+    """The main workload's plan against a loop of single-phantom,
+    single-transmit calls (vector path, no graph), and the autotuner on it."""
     import torch
-    from paper_2102_02738_amd import _lib, rf_plan, FLAG_PERSISTENT, FLAG_NO_MFMA
+    from paper_2102_02738_amd import _lib, rf_plan, FLAG_NO_MFMA
     c = Case("cvx128x11_p16")
     w = c.w
     out = torch.empty((c.P, c.T, c.N, c.n_t), device="cuda")
     plain = torch.empty_like(out)
-    plan = rf_plan(w["probe"], w["medium"], dict(c.o, flags=FLAG_PERSISTENT), w["delays"], w["apod"],
-                   offsets=c.off)
+    plan = rf_plan(w["probe"], w["medium"], c.o, w["delays"], w["apod"], offsets=c.off)
 
     def graph():
         plan.graph_launch_into(out, c.x, None, c.z, c.R)
@@ -206,14 +278,10 @@ def extra_uneven_phantoms(steps: int) -> dict:
     g_ms = _median_ms(graph, steps)
     first = out.clone()
     t0 = time.perf_counter()
-    chosen = plan.autotune(c.x, None, c.z, c.R, c.n_t)
+    chosen = plan.autotune(c.x, None, c.z, c.R)
     tune_s = time.perf_counter() - t0
     gt_ms = _median_ms(graph, steps)
     tuned = out.clone()
-    out.copy_(first)
-    static = torch.empty_like(out)
-    s_ms = _median_ms(lambda: _lib.rf_into(static, w["probe"], w["medium"], c.o, w["delays"],
-                                           w["apod"], c.x, None, c.z, c.R, c.off), 1)
     po = dict(c.o, flags=FLAG_NO_MFMA)
     off = c.off
 
@@ -227,14 +295,10 @@ def extra_uneven_phantoms(steps: int) -> dict:
 
     p_ms = _median_ms(loop, 1, warmup=0)
     plan.close()
-    return dict(workload=c.name, n_phantoms=c.P, n_tx=c.T, n_scatterers=c.S,
-                scatterers_min=int(min(off[1:] - off[:-1])), scatterers_max=int(max(off[1:] - off[:-1])),
-                graph_ms=g_ms, batched_static_call_ms=s_ms, plain_ms=p_ms,
-                speedup_vs_plain=p_ms / min(g_ms, gt_ms), evals_per_s=c.evals() / (min(g_ms, gt_ms) * 1e-3),
-                rf_frames_per_s=c.P * c.T / (min(g_ms, gt_ms) * 1e-3),
+    return dict(workload=c.name, graph_ms=g_ms, plain_ms=p_ms, speedup_vs_plain=p_ms / g_ms,
                 autotune=dict(chosen=chosen, tuning_s=tune_s, graph_ms_default=g_ms,
                               graph_ms_autotuned=gt_ms, rel_l2_autotuned_vs_plain=_rel(tuned, plain)),
-                rel_l2_graph_vs_plain=_rel(out, plain), graph_equals_static=bool(torch.equal(out, static)))
+                rel_l2_graph_vs_plain=_rel(first, plain))
 
 
 def extra_autotune(steps: int, name: str) -> dict:
@@ -395,12 +459,53 @@ def extra_two_d(steps: int, ms_3d: float) -> dict:
                               kernel="k_synth<256, 8, 32, 1, false, 2, true, 1>", ops_per_unit=per_g))
 
 
+def extra_single_transmit(steps: int) -> dict:
+    """One 0-degree plane wave, 128 elements, 50,000 scatterers on the vector
+    path (k_synth), whole simus_rf calls, with the synthesis kernel's
+    roofline: algorithmic slots, and the issue count of its bin loop."""
+    import torch
+    from paper_2102_02738_amd import _lib
+    c = Case("pw128_s50k")
+    w = c.w
+    out = torch.empty((c.P, c.T, c.N, c.n_t), dtype=torch.float32, device="cuda")
+
+    def step():
+        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R)
+
+    for _ in range(3):
+        step()
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    _lib.profile_enable(False)
+    synth_ms, n = _lib.profile_read("synth")
+    synth_ms /= max(n, 1)
+    g_terms = float(c.S) * c.N * c.g["nu"] * c.g["n_bins"]
+    alg = alg_slots(c.S, c.g["nu"] * c.N, c.N, c.T, c.g["n_bins"], c.g["nu"], False)
+    issue = g_terms * (SYNTH_VALU_PER_G + TRANS_ISSUE_COST * SYNTH_TRANS_PER_G)
+    return dict(workload=c.name, ms_per_call=ms, evals_per_s=c.evals() / (ms * 1e-3),
+                g_terms_per_s=g_terms / (ms * 1e-3), rf_frames_per_s=c.T / (ms * 1e-3),
+                synth_kernel_ms=synth_ms,
+                roofline=dict(bound="alu", achieved=alg / (synth_ms * 1e-3) / 1e12,
+                              peak=VALU_PEAK / 1e12, unit="TOP/s",
+                              frac=alg / (synth_ms * 1e-3) / VALU_PEAK,
+                              traffic=measured_traffic("synth_pw128_s50k_traffic.txt", VECTOR_SOURCES),
+                              kernel="k_synth<256, 8, 27, 1, false, 1, true, 1>",
+                              bin_loop_issue_frac=issue / (synth_ms * 1e-3) / VALU_PEAK))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-stride", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-bin-stride", type=int, default=32)
+    ap.add_argument("--cpu-scat-stride", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=2)
@@ -429,10 +534,11 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 3}))
         return
 
-    from paper_2102_02738_amd import _lib
+    from paper_2102_02738_amd import _lib, rf_plan
 
     if args.only_extra:
         fns = {"autotune": lambda k: extra_autotune(max(k, 5), "pw128_s50k"),
+               "single_transmit": lambda k: extra_single_transmit(max(k, 5)),
                "batched_transmits": extra_batched_transmits, "uneven_phantoms": extra_uneven_phantoms,
                "forward_adjoint": extra_forward_adjoint, "large_t": extra_large_t,
                "pfield": extra_pfield,
@@ -443,13 +549,15 @@ def main():
         print(json.dumps({args.only_extra: fns[args.only_extra](args.extra_steps)}))
         return
 
-    c = Case("pw128_s50k")
+    c = Case("cvx128x11_p16")
     w = c.w
     out = torch.empty((c.P, c.T, c.N, c.n_t), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    plan = rf_plan(w["probe"], w["medium"], c.o, w["delays"], w["apod"], offsets=c.off)
+    plan_s = time.perf_counter() - t0
 
     def step():
-        _lib.rf_into(out, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R,
-                     c.offsets())
+        plan.graph_launch_into(out, c.x, None, c.z, c.R)
 
     for _ in range(args.warmup):
         step()
@@ -463,47 +571,85 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     _lib.profile_enable(False)
-    synth_ms, synth_n = _lib.profile_read("synth")
-    other = {k: _lib.profile_read(k) for k in ("wtable", "finalize", "idft")}
+    graph_ms, graph_n = _lib.profile_read("graph")
+    graph_ms /= max(graph_n, 1)
+    # the same kernels launched one by one (plan execution), each bracketed by
+    # HIP events on the launch stream: the synthesis kernel's duration and
+    # the rest of the graph's
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    eager = torch.empty_like(out)
+    for _ in range(2):
+        plan.execute_into(eager, c.x, None, c.z, c.R)
+    torch.cuda.synchronize()
+    _lib.profile_enable(False)
+    kern = {k: _lib.profile_read(k) for k in ("synth", "wtable", "finalize", "idft")}
+    kern = {k: v[0] / max(v[1], 1) for k, v in kern.items()}
+    graph_equals_eager = bool(torch.equal(out, eager))
+    # one whole simus_rf call (host planning, upload and the same kernels)
+    call = torch.empty_like(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _lib.rf_into(call, w["probe"], w["medium"], c.o, w["delays"], w["apod"], c.x, None, c.z, c.R, c.off)
+    torch.cuda.synchronize()
+    call_ms = (time.perf_counter() - t0) * 1e3
+    plan.close()
 
     ms_per_step = wall * 1e3 / args.steps
     value = c.evals() / (ms_per_step * 1e-3)
-    g_terms = float(c.S) * c.N * c.g["nu"] * c.g["n_bins"]   # each G term serves every transmit
-    synth_avg_ms = synth_ms / max(synth_n, 1)
-    per_g = SYNTH_VALU_PER_G + TRANS_ISSUE_COST * SYNTH_TRANS_PER_G
-    achieved = g_terms * per_g / (synth_avg_ms * 1e-3)
+    M = c.g["nu"] * c.N
+    g_terms = float(c.S) * M * c.g["n_bins"]
+    # the synthesis kernel inside the timed graph launches: the graph's event
+    # time less the other kernels' (measured eagerly; < 0.1 %)
+    synth_ms = graph_ms - (kern["wtable"] + kern["finalize"] + kern["idft"])
+    alg = alg_slots(c.S, M, c.N, c.T, c.g["n_bins"], c.g["nu"], True)
+    achieved = alg / (synth_ms * 1e-3)
+    counters = profile_summary("synth_mt_cvx128x11_p16_counters.txt", MT_SOURCES)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="TOP/s",
-                frac=achieved / VALU_PEAK, traffic=measured_traffic(c.name),
-                kernel="k_synth<256, 8, 27, 1, false, 1, true, 1>", kernel_ms=synth_avg_ms,
-                ops_per_unit=per_g, valu_per_unit=SYNTH_VALU_PER_G, trans_per_unit=SYNTH_TRANS_PER_G,
-                unit_count=g_terms, unit_def="G term (sub-element x scatterer x bin)",
-                op_def="lane issue slot: full-rate VALU 1, transcendental 4")
+                frac=achieved / VALU_PEAK,
+                traffic=measured_traffic("synth_mt_cvx128x11_p16_traffic.txt", MT_SOURCES),
+                kernel=MT_KERNEL, kernel_ms=synth_ms, kernel_ms_eager=kern["synth"],
+                unit_count=dict(g_terms=g_terms, cmac_pairs=float(c.S) * c.N * c.T * c.g["n_bins"]),
+                work_per_unit=dict(g_term=G_EVAL_SLOTS + 2.0 * (c.g["nu"] - 1) / c.g["nu"],
+                                   cmac_pair=2 * CMAC_SLOTS_MFMA),
+                work_def="algorithmic lane issue slots: Green's term by recurrence and table, element "
+                         "sum, two complex MACs per (element, scatterer, transmit, bin) on the matrix "
+                         "cores (3 real MACs each); no set-up, padding or address arithmetic",
+                op_def="lane issue slot: full-rate FP32 VALU 1, transcendental 4, FP32 MFMA lane-MAC 1",
+                issue_counters={k: float(counters[k]) for k in ("valu_busy", "mfma_busy", "issue_busy")
+                                if k in counters} or None)
     res = {
         "metric": "scatterer*element*freq evals/s", "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": c.name, "n_elements": c.N, "n_scatterers": c.S,
-                   "n_tx": c.T, "n_phantoms": c.P, "nfft": c.g["nfft"], "n_bins": c.g["n_bins"],
-                   "n_t": c.n_t, "nu": c.g["nu"]},
+        "config": {"workload": c.name, "n_elements": c.N, "n_scatterers": c.S, "n_tx": c.T,
+                   "n_phantoms": c.P, "nfft": c.g["nfft"], "n_bins": c.g["n_bins"], "n_t": c.n_t,
+                   "nu": c.g["nu"], "launch": "one persistent hipGraph replay per step (plan built once)"},
         "g_terms_per_s": g_terms / (ms_per_step * 1e-3),
         "rf_frames_per_s": c.P * c.T / (ms_per_step * 1e-3),
-        "kernel_ms": {"synth": synth_avg_ms, **{k: v[0] / max(v[1], 1) for k, v in other.items()}},
+        "plan_create_s": plan_s, "simus_rf_call_ms": call_ms,
+        "simus_rf_call_evals_per_s": c.evals() / (call_ms * 1e-3),
+        "graph_equals_eager": graph_equals_eager, "rel_l2_call_vs_graph": _rel(call, out),
+        "kernel_ms": {"graph": graph_ms, **kern},
         "roofline": roof,
     }
     if not args.no_extras:
+        st = extra_single_transmit(max(args.extra_steps * 5, 10))
         res["extras"] = {
-            "autotune": extra_autotune(max(args.extra_steps, 5), c.name),
+            "single_transmit": st,
+            "autotune": extra_autotune(max(args.extra_steps, 5), "pw128_s50k"),
             "batched_transmits": extra_batched_transmits(args.extra_steps),
             "uneven_phantoms": extra_uneven_phantoms(args.extra_steps),
             "forward_adjoint": extra_forward_adjoint(args.extra_steps),
-            "two_d": extra_two_d(args.extra_steps, ms_per_step),
+            "two_d": extra_two_d(args.extra_steps, st["ms_per_call"]),
             "large_t": extra_large_t(args.extra_steps),
             "pfield": extra_pfield(args.extra_steps),
         }
     if not args.no_cpu_baseline:
         x, y, z, R = c.host
-        res["cpu_baseline"] = cpu_baseline(w, c.g, x, y, z, R, args.cpu_stride)
+        res["cpu_baseline"] = cpu_baseline(w, c.g, x, y, z, R, c.off, args.cpu_bin_stride,
+                                           args.cpu_scat_stride)
     print(json.dumps(res))
 
 

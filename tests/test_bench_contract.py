@@ -21,9 +21,9 @@ def test_bench_refuses_more_than_one_gpu():
 @pytest.mark.gpu
 def test_bench_line_has_the_contract_keys():
     """A short run prints one JSON line with the required keys, a roofline of
-    the synthesis kernel and the oracle's CPU rate."""
+    the synthesis kernel and the oracle's CPU rate on a small sample."""
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1",
-                        "--no-extras", "--cpu-stride", "200"],
+                        "--no-extras", "--cpu-bin-stride", "256", "--cpu-scat-stride", "2000"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
@@ -37,6 +37,8 @@ def test_bench_line_has_the_contract_keys():
     rl = d["roofline"]
     assert rl["bound"] == "alu" and 0 < rl["frac"] < 1
     assert abs(rl["achieved"] / rl["peak"] - rl["frac"]) < 1e-9
+    assert 0 < rl["kernel_ms"] <= d["ms_per_step"]
     cb = d["cpu_baseline"]
-    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
-    assert "workload" in d["config"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["cpu_model"]
+    assert d["config"]["workload"] == "cvx128x11_p16"
+    assert d["graph_equals_eager"]
