@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define SIMUS_VERSION 100
+#define SIMUS_VERSION 200
 
 #define SIMUS_OK 0
 #define SIMUS_EINVAL (-1)   /* invalid argument (NULL pointer, bad size, bad parameter) */
@@ -116,11 +116,18 @@ typedef struct {
                              every other entry point requires nfft > 0 */
     int32_t n_t;          /* RF samples returned per channel; 0 = nfft; <= nfft */
     int32_t flags;        /* SIMUS_FLAG_* */
-    int32_t tile_bins;    /* reserved: checked to lie in [0, 32], otherwise unused
-                             (bins per work item are fixed by the kernel shape) */
+    int32_t n_gauss;      /* Gaussians G of the elevation aperture (Eq. 12) in `gauss`,
+                             0..SIMUS_MAX_GAUSS; 0 = the four of Eq. (18) */
     int32_t tile_scat;    /* scatterers per work item; 0 = a default from the
                              problem size (simus_rf_plan_autotune measures) */
+    const double* gauss;  /* host [n_gauss][4]: Re A_g, Im A_g, Re B_g, Im B_g of
+                             Pi(u) ~ sum_g A_g exp(-B_g u^2) (Eqs. 12-16), finite,
+                             Re B_g > 0; read before the call returns (plans keep a
+                             copy).  Sets of complex-conjugate pairs (as Eq. 18's)
+                             make the aperture real.  NULL when n_gauss = 0 */
 } simus_options;
+
+#define SIMUS_MAX_GAUSS 32
 
 #define SIMUS_FLAG_NO_MFMA       1   /* never use the MFMA multi-transmit contraction */
 #define SIMUS_FLAG_PERSISTENT    2   /* persistent work-queue launch of the synthesis: the

@@ -43,6 +43,7 @@ class _Setup(C.Structure):
         ("c", C.c_double), ("alpha_db", C.c_double),
         ("fs", C.c_double), ("n_cycles", C.c_double),
         ("dim2", C.c_int32), ("pad1", C.c_int32),
+        ("n_gauss", C.c_int32), ("pad2", C.c_int32), ("gauss", C.c_void_p),
     ]
 
 
@@ -65,6 +66,7 @@ class Setup:
     zeta: float = 1.75
     nu: int = 0          # 0: Eq. (21)
     dim2: int = 0        # 1: 2-D acoustics (Section V)
+    gauss: object = None  # Gaussians of Eq. (12): complex pairs [(A_g, B_g)], None: Eq. (18)
 
     def resolved_nu(self) -> int:
         if self.nu > 0:
@@ -72,10 +74,16 @@ class Setup:
         return nu_eq21(self.width, self.fc, self.bandwidth, self.c)
 
     def to_c(self) -> _Setup:
+        n_g, ptr = 0, None
+        if self.gauss is not None:
+            ab = np.asarray(self.gauss, dtype=np.complex128).reshape(-1, 2)
+            self._gbuf = np.ascontiguousarray(np.stack([ab[:, 0].real, ab[:, 0].imag,
+                                                        ab[:, 1].real, ab[:, 1].imag], -1))
+            n_g, ptr = ab.shape[0], self._gbuf.ctypes.data
         return _Setup(self.n_elements, self.resolved_nu(), self.fc, self.pitch,
                       self.width, self.height, self.elev_focus, self.bandwidth,
                       self.radius, self.baffle, 0, self.zeta, self.c,
-                      self.alpha_db, self.fs, self.n_cycles, int(self.dim2), 0)
+                      self.alpha_db, self.fs, self.n_cycles, int(self.dim2), 0, n_g, 0, ptr)
 
 
 _lib = None

@@ -60,6 +60,9 @@ typedef struct {
     double n_cycles;        /* n_lambda, number of wavelengths of the pulse */
     int32_t dim2;           /* 1: 2-D acoustics of Section V */
     int32_t pad1;
+    int32_t n_gauss;        /* Gaussians of Eq. (12); 0: the four of Eq. (18) */
+    int32_t pad2;
+    const double *gauss;    /* [n_gauss][4]: Re A_g, Im A_g, Re B_g, Im B_g */
 } orc_setup;
 
 /* ------------------------------------------------------------------ */
@@ -80,28 +83,40 @@ static double dsinc(double x)
     return (cos(x) - sin(x) / x) / x;
 }
 
-/* Eq. (18): the four-Gaussian approximation of the rectangle function.
- * Coefficients 3 and 4 are the complex conjugates of 1 and 2. */
-static void gauss4(cplx A[4], cplx B[4])
+/* Eq. (12): the rectangle function as a sum of G complex Gaussians,
+ * Pi(u) ~ sum_g A_g exp(-B_g u^2).  The set is the caller's (su->gauss),
+ * or by default the four of Eq. (18), whose coefficients 3 and 4 are the
+ * complex conjugates of 1 and 2.  Returns G (at most ORC_MAX_GAUSS). */
+#define ORC_MAX_GAUSS 64
+static int gauss_set(const orc_setup *su, cplx A[ORC_MAX_GAUSS], cplx B[ORC_MAX_GAUSS])
 {
+    if (su->n_gauss > 0 && su->gauss) {
+        int G = su->n_gauss < ORC_MAX_GAUSS ? su->n_gauss : ORC_MAX_GAUSS;
+        for (int g = 0; g < G; ++g) {
+            A[g] = su->gauss[4 * g] + I * su->gauss[4 * g + 1];
+            B[g] = su->gauss[4 * g + 2] + I * su->gauss[4 * g + 3];
+        }
+        return G;
+    }
     A[0] = 0.187 + 0.275 * I;  B[0] = 4.558 - 25.59 * I;
     A[1] = 0.288 - 1.954 * I;  B[1] = 8.598 - 7.924 * I;
     A[2] = conj(A[0]);         B[2] = conj(B[0]);
     A[3] = conj(A[1]);         B[3] = conj(B[1]);
+    return 4;
 }
 
 /* Eqs. (14)-(16): elevation term delta(y, r, k) of the Gaussian
  * superposition model, principal square root. */
 static cplx elevation_delta(const orc_setup *su, double y, double r, double k)
 {
-    cplx A[4], B[4];
-    gauss4(A, B);
+    cplx A[ORC_MAX_GAUSS], B[ORC_MAX_GAUSS];
+    int G = gauss_set(su, A, B);
     double h = su->height;
     double inv_rf = 1.0 / su->elev_focus;   /* 0 when R_f = inf */
     cplx beta = -I * k * y / r;
     cplx gamma = I * k * y * y / (2.0 * r);
     cplx sum = 0.0;
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < G; ++g) {
         cplx alpha = B[g] / (h * h) + I * k / 2.0 * (inv_rf - 1.0 / r);
         sum += A[g] * csqrt(M_PI / alpha) * cexp(beta * beta / (4.0 * alpha) + gamma);
     }
@@ -113,8 +128,8 @@ static cplx elevation_delta(const orc_setup *su, double y, double r, double k)
 static void elevation_delta_grad(const orc_setup *su, double y, double r, double k,
                                  cplx *d_dr, cplx *d_dy)
 {
-    cplx A[4], B[4];
-    gauss4(A, B);
+    cplx A[ORC_MAX_GAUSS], B[ORC_MAX_GAUSS];
+    int G = gauss_set(su, A, B);
     double h = su->height;
     double inv_rf = 1.0 / su->elev_focus;
     cplx beta = -I * k * y / r;
@@ -124,7 +139,7 @@ static void elevation_delta_grad(const orc_setup *su, double y, double r, double
     cplx dalpha_dr = I * k / (2.0 * r * r);
     *d_dr = 0.0;
     *d_dy = 0.0;
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < G; ++g) {
         cplx alpha = B[g] / (h * h) + I * k / 2.0 * (inv_rf - 1.0 / r);
         cplx term = A[g] * csqrt(M_PI / alpha) * cexp(beta * beta / (4.0 * alpha) + gamma);
         /* d/dr of [alpha^{-1/2} exp(beta^2/(4 alpha) + gamma)] / itself */

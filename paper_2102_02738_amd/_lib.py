@@ -53,7 +53,7 @@ class Medium(C.Structure):
 class Options(C.Structure):
     _fields_ = [("fs", C.c_double), ("n_cycles", C.c_double), ("spectral_eps", C.c_double),
                 ("nu", C.c_int32), ("nfft", C.c_int32), ("n_t", C.c_int32), ("flags", C.c_int32),
-                ("tile_bins", C.c_int32), ("tile_scat", C.c_int32)]
+                ("n_gauss", C.c_int32), ("tile_scat", C.c_int32), ("gauss", C.c_void_p)]
 
 
 class Grid(C.Structure):
@@ -128,12 +128,26 @@ def make_medium(m: dict) -> Medium:
     return Medium(m.get("c", 1540.0), m.get("alpha_db", 0.0))
 
 
+def gauss_table(gset) -> np.ndarray:
+    """A set of Gaussians (Eq. 12) as the ABI's [G][4] FP64 table (Re A, Im A,
+    Re B, Im B); gset: (G, 2) complex (A_g, B_g), e.g. from gaussians.fit."""
+    g = np.asarray(gset, dtype=np.complex128).reshape(-1, 2)
+    return np.ascontiguousarray(np.stack([g[:, 0].real, g[:, 0].imag, g[:, 1].real, g[:, 1].imag], -1))
+
+
 def make_options(o: dict, **over) -> Options:
+    """options dict -> simus_options; o['gauss'] (optional) is a (G, 2) complex
+    set of Gaussians, kept alive with the returned structure."""
     d = dict(o)
     d.update(over)
-    return Options(d["fs"], d.get("n_cycles", 1.0), d.get("spectral_eps", 1e-7), int(d.get("nu", 0)),
-                   int(d.get("nfft", 0)), int(d.get("n_t", 0)), int(d.get("flags", 0)),
-                   int(d.get("tile_bins", 0)), int(d.get("tile_scat", 0)))
+    gs = d.get("gauss")
+    tab = None if gs is None else gauss_table(gs)
+    opt = Options(d["fs"], d.get("n_cycles", 1.0), d.get("spectral_eps", 1e-7), int(d.get("nu", 0)),
+                  int(d.get("nfft", 0)), int(d.get("n_t", 0)), int(d.get("flags", 0)),
+                  0 if tab is None else tab.shape[0], int(d.get("tile_scat", 0)),
+                  None if tab is None else tab.ctypes.data)
+    opt._gauss_table = tab
+    return opt
 
 
 def _f64(a):

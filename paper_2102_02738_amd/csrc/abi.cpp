@@ -13,7 +13,6 @@
 #include <string>
 #include <vector>
 
-#include "eq18.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "simus.h"
@@ -221,20 +220,21 @@ ModelConst model_constants(const Probe& P, const Band& B)
     K.zeta = (float)P.zeta;
     K.baffle = P.baffle;
     K.dim2 = P.dim2 ? 1 : 0;
-    // Eq. (18): A_3 = conj(A_1), B_3 = conj(B_1), A_4 = conj(A_2), B_4 = conj(B_2).
-    using eq18::Ar;
-    using eq18::Ai;
-    using eq18::Br;
-    using eq18::Bi;
+    // the Gaussians of Eq. (12) (Eq. 18's four by default): the unrolled
+    // constants when there are four; the device table (gset, set per launch
+    // from the workspace) serves any count
+    K.ng = (int32_t)P.gA.size();
     const double h2 = P.height * P.height;
     const double sq_pi = std::sqrt(M_PI);
-    for (int g = 0; g < 4; ++g) {
-        K.g.a[g] = (float)(Br[g] / h2);
-        K.g.a2[g] = (float)((Br[g] / h2) * (Br[g] / h2));
-        K.g.b[g] = (float)(Bi[g] / h2);
-        K.g.Ar[g] = (float)(sq_pi * Ar[g]);
-        K.g.Ai[g] = (float)(sq_pi * Ai[g]);
+    for (int g = 0; g < 4 && K.ng == 4; ++g) {
+        const double a = P.gB[g].real() / h2;
+        K.g.a[g] = (float)a;
+        K.g.a2[g] = (float)(a * a);
+        K.g.b[g] = (float)(P.gB[g].imag() / h2);
+        K.g.Ar[g] = (float)(sq_pi * P.gA[g].real());
+        K.g.Ai[g] = (float)(sq_pi * P.gA[g].imag());
     }
+    K.gset = nullptr;
     return K;
 }
 
@@ -311,8 +311,8 @@ Common make_common(const simus_probe* probe, const simus_medium* medium, const s
 
 // Host tables uploaded by every call, and device tables built on the device.
 struct CommonLayout {
-    size_t xc, zc, tx, tz, nx, nz, dl, ap, pw;   // upload region
-    size_t W, rr, dt, dp;                        // device-only region
+    size_t xc, zc, tx, tz, nx, nz, dl, ap, pw, gs, gd;   // upload region
+    size_t W, rr, dt, dp;                                // device-only region
 };
 
 void layout_upload(Layout& up, CommonLayout& L, const Common& C)
@@ -327,6 +327,8 @@ void layout_upload(Layout& up, CommonLayout& L, const Common& C)
     L.dl = up.add(sizeof(double) * TN);
     L.ap = up.add(sizeof(float) * TN);
     L.pw = up.add(sizeof(float2) * std::max(C.B.n_bins, 1));
+    L.gs = up.add(sizeof(float4) * C.K.ng);
+    L.gd = up.add(sizeof(double) * 4 * C.K.ng);
 }
 
 void layout_device(Layout& dv, CommonLayout& L, const Common& C)
@@ -352,6 +354,20 @@ void fill_upload(char* h, const CommonLayout& L, const Common& C, const double* 
         at<double>(h, L.dl)[i] = delays[i];
         at<float>(h, L.ap)[i] = apod ? apod[i] : 1.f;
     }
+    // the Gaussians of Eq. (12): scaled FP32 for the direct evaluation, FP64
+    // for the elevation table
+    const double h2 = C.P.height * C.P.height;
+    for (int g = 0; g < C.K.ng; ++g) {
+        const std::complex<double> A = C.P.gA[g], B = C.P.gB[g];
+        at<float4>(h, L.gs)[g] = make_float4((float)(B.real() / h2), (float)(B.imag() / h2),
+                                             (float)(std::sqrt(M_PI) * A.real()),
+                                             (float)(std::sqrt(M_PI) * A.imag()));
+        double* gd = at<double>(h, L.gd) + 4 * g;
+        gd[0] = A.real();
+        gd[1] = A.imag();
+        gd[2] = B.real();
+        gd[3] = B.imag();
+    }
     // two-way spectral weight (Eqs. 28, 34); in 2-D with the factor 2b of Eq. (38)
     const double f2 = C.P.dim2 ? C.P.width : 1.0;
     for (int b = 0; b < C.B.n_bins; ++b) {
@@ -359,6 +375,14 @@ void fill_upload(char* h, const CommonLayout& L, const Common& C, const double* 
         const std::complex<double> v = pulse_spectrum(C.P, w) * transducer_spectrum(C.P, w) * f2;
         at<float2>(h, L.pw)[b] = make_float2((float)v.real(), (float)v.imag());
     }
+}
+
+// The call's model constants with the device address of its Gaussian table.
+ModelConst dev_consts(const Common& C, char* d, const CommonLayout& L)
+{
+    ModelConst K = C.K;
+    K.gset = at<float4>(d, L.gs);
+    return K;
 }
 
 SubGeo sub_geo(char* d, const CommonLayout& L)
@@ -380,8 +404,8 @@ void launch_common(char* d, const CommonLayout& L, const Common& C, const float*
         hip_check(launch_rrange(at<uint32_t>(d, L.rr), x, y, z, C.ph.total, sub_geo(d, L), C.P.M, st),
                   "range launch");
         hip_check(launch_dtable(at<float4>(d, L.dt), at<DeltaParams>(d, L.dp), at<uint32_t>(d, L.rr),
-                                C.K, C.P.height, C.B.j_lo, C.B.j_lo + std::max(C.B.n_bins, 1) - 1,
-                                C.P.dim2, st),
+                                C.K, at<double>(d, L.gd), C.P.height, C.B.j_lo,
+                                C.B.j_lo + std::max(C.B.n_bins, 1) - 1, C.P.dim2, st),
                   "table launch");
     }
 }
@@ -592,7 +616,7 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     A.n_tx = n_tx;
     A.n_bins = C.B.n_bins;
     A.j_lo = C.B.j_lo;
-    A.K = C.K;
+    A.K = dev_consts(C, d, F.L);
     A.dtab = C.table ? at<float4>(d, F.L.dt) : nullptr;
     A.dpar = C.table ? at<DeltaParams>(d, F.L.dp) : nullptr;
     A.ticket = nullptr;
@@ -728,7 +752,7 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     A.n_bins = C.B.n_bins;
     A.j_lo = C.B.j_lo;
     A.range_bins = range_bins;
-    A.K = C.K;
+    A.K = dev_consts(C, d, L);
     if (log_enabled())
         std::fprintf(stderr, "[simus] adjoint S=%lld T=%d bins=%d TT=%d JT=%d range=%d items=%d y=%d table=%d mfma=%d\n",
                      (long long)C.ph.total, n_tx, C.B.n_bins, cfg.tt, cfg.jt, range_bins, n_items,
@@ -832,7 +856,7 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     F.n_bins = n_f;
     F.j_lo = 1;
     F.range_bins = range_bins;
-    F.K = C.K;
+    F.K = dev_consts(C, d, L);
     hip_check(timed(K_PFIELD, st, [&] { return launch_pfield(F, C.has_y, C.table, n_ranges, st); }),
               "field launch");
     const float dw = (float)(2.0 * M_PI * C.B.df);
@@ -1041,6 +1065,9 @@ int simus_rf_plan_create(const simus_probe* probe, const simus_medium* medium,
         std::unique_ptr<simus_rf_plan_s> pl(new simus_rf_plan_s);
         pl->F = make_fwd_plan(std::move(C), opt, delays, apod, true);
         pl->opt = *opt;
+        // the plan holds its Gaussians in its probe (the caller's array may go)
+        pl->opt.n_gauss = 0;
+        pl->opt.gauss = nullptr;
         pl->delays.assign(delays, delays + size_t(n_tx) * pl->F.C.P.N);
         if (apod) pl->apod.assign(apod, apod + size_t(n_tx) * pl->F.C.P.N);
         hip_check(hipGetDevice(&pl->device), "hipGetDevice");

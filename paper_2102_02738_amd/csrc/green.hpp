@@ -234,43 +234,59 @@ __device__ __forceinline__ Geo make_geo(const ModelConst& K, const SubFrame& f, 
     return g;
 }
 
-// Elevation term delta (Eqs. 14-16) for the four Gaussians of Eq. (18),
+// Elevation term delta (Eqs. 14-16), one Gaussian of Eq. (12) at a time:
 // alpha_g = a_g + i (b_g + q), evaluated directly.  alpha^{-1/2} is formed
 // without trig: sqrt(alpha) = s + i b/(2 s), s = sqrt((|alpha| + a)/2),
 // alpha^{-1/2} = conj(sqrt(alpha)) / |alpha|.  For y != 0 each term is
 // multiplied by exp(beta^2 / (4 alpha) + gamma), beta^2 = -k^2 y^2 / r^2,
-// gamma = i k y^2 / (2 r).
+// gamma = i k y^2 / (2 r).  Accumulates A_g sqrt(pi) alpha^{-1/2} e^(...)
+// into (dr, di).
 template <bool HASY>
-__device__ __forceinline__ float2 elevation(const Gauss4& G, float q, float k, float yr2, float y2r)
+__device__ __forceinline__ void elevation_term(float a, float a2, float b, float Ar, float Ai, float q,
+                                               float k, float yr2, float y2r, float& dr, float& di)
+{
+    const float bi = b + q;
+    const float m2 = fmaf(bi, bi, a2);
+    const float inv_mod = rsq_fast(m2);
+    const float mod = m2 * inv_mod;
+    const float x = 0.5f * (mod + a);
+    const float rx = rsq_fast(x);
+    float zr = x * rx * inv_mod;              // Re alpha^{-1/2}
+    float zi = -0.5f * bi * rx * inv_mod;     // Im alpha^{-1/2}
+    if (HASY) {
+        const float ar = zr * zr - zi * zi, ai = 2.f * zr * zi;   // 1/alpha
+        const float c0 = -0.25f * k * k * yr2;
+        const float er = c0 * ar;
+        const float ei = c0 * ai + k * y2r;   // radians
+        float et = ei * 0.15915494309189535f;
+        et -= rintf(et);
+        const float mag = exp2_fast(er * 1.4426950408889634f);
+        const float c = mag * cos_turns(et), s = mag * sin_turns(et);
+        const float nr = zr * c - zi * s, ni = zr * s + zi * c;
+        zr = nr;
+        zi = ni;
+    }
+    dr = fmaf(Ar, zr, dr);
+    dr = fmaf(-Ai, zi, dr);
+    di = fmaf(Ar, zi, di);
+    di = fmaf(Ai, zr, di);
+}
+
+// delta summed over the set: four Gaussians unrolled from the constants,
+// any other count from the device table.
+template <bool HASY>
+__device__ __forceinline__ float2 elevation(const ModelConst& K, float q, float k, float yr2, float y2r)
 {
     float dr = 0.f, di = 0.f;
+    if (K.ng == 4) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const float bi = G.b[g] + q;
-        const float m2 = fmaf(bi, bi, G.a2[g]);
-        const float inv_mod = rsq_fast(m2);
-        const float mod = m2 * inv_mod;
-        const float x = 0.5f * (mod + G.a[g]);
-        const float rx = rsq_fast(x);
-        float zr = x * rx * inv_mod;              // Re alpha^{-1/2}
-        float zi = -0.5f * bi * rx * inv_mod;     // Im alpha^{-1/2}
-        if (HASY) {
-            const float ar = zr * zr - zi * zi, ai = 2.f * zr * zi;   // 1/alpha
-            const float c0 = -0.25f * k * k * yr2;
-            const float er = c0 * ar;
-            const float ei = c0 * ai + k * y2r;   // radians
-            float et = ei * 0.15915494309189535f;
-            et -= rintf(et);
-            const float mag = exp2_fast(er * 1.4426950408889634f);
-            const float c = mag * cos_turns(et), s = mag * sin_turns(et);
-            const float nr = zr * c - zi * s, ni = zr * s + zi * c;
-            zr = nr;
-            zi = ni;
+        for (int g = 0; g < 4; ++g)
+            elevation_term<HASY>(K.g.a[g], K.g.a2[g], K.g.b[g], K.g.Ar[g], K.g.Ai[g], q, k, yr2, y2r, dr, di);
+    } else {
+        for (int g = 0; g < K.ng; ++g) {
+            const float4 c = K.gset[g];
+            elevation_term<HASY>(c.x, c.x * c.x, c.y, c.z, c.w, q, k, yr2, y2r, dr, di);
         }
-        dr = fmaf(G.Ar[g], zr, dr);
-        dr = fmaf(-G.Ai[g], zi, dr);
-        di = fmaf(G.Ar[g], zi, di);
-        di = fmaf(G.Ai[g], zr, di);
     }
     return make_float2(dr, di);
 }
@@ -329,57 +345,72 @@ __device__ __forceinline__ float2 delta_eval(const DeltaFetch& f)
 }
 
 // delta with its partial derivatives in r and y, evaluated directly
-// (y != 0 path of the adjoint, or without the table).  Per Gaussian,
-// T = A sqrt(pi) alpha^{-1/2} exp(phi), phi = beta^2/(4 alpha) + gamma, and
-// dT = T (-1/2 dalpha / alpha + dphi).
+// (y != 0 path of the adjoint, or without the table), one Gaussian at a
+// time.  Per Gaussian, T = A sqrt(pi) alpha^{-1/2} exp(phi), phi =
+// beta^2/(4 alpha) + gamma, and dT = T (-1/2 dalpha / alpha + dphi).
 template <bool HASY>
-__device__ __forceinline__ void elevation_grad(const Gauss4& G, float inv_rf, float k, float r,
-                                               float y, float2& dl, float2& d_r, float2& d_y)
+__device__ __forceinline__ void elevation_grad_term(float a, float a2, float b, float Ar, float Ai,
+                                                    float q, float ar_i, float k, float y, float inv_r,
+                                                    float2& dl, float2& d_r, float2& d_y)
+{
+    const float bi = b + q;
+    const float m2 = fmaf(bi, bi, a2);
+    const float inv_mod = rsq_fast(m2);
+    const float mod = m2 * inv_mod;
+    const float x = 0.5f * (mod + a);
+    const float rx = rsq_fast(x);
+    const float zr = x * rx * inv_mod, zi = -0.5f * bi * rx * inv_mod;   // alpha^{-1/2}
+    const float2 ia = make_float2(zr * zr - zi * zi, 2.f * zr * zi);     // 1/alpha
+    float2 T = make_float2(Ar * zr - Ai * zi, Ar * zi + Ai * zr);
+    // -1/2 (d alpha/dr) / alpha = -1/2 (i ar_i) ia
+    float2 lr = make_float2(0.5f * ar_i * ia.y, -0.5f * ar_i * ia.x);
+    float2 ly = make_float2(0.f, 0.f);
+    if (HASY) {
+        const float b2 = -k * k * y * y * inv_r * inv_r;               // beta^2 (real)
+        const float gam = 0.5f * k * y * y * inv_r;                    // gamma = i gam
+        const float2 phi = make_float2(0.25f * b2 * ia.x, 0.25f * b2 * ia.y + gam);
+        // beta = -i k y / r, dbeta/dr = i k y / r^2, dbeta/dy = -i k / r
+        // 2 beta dbeta/dr = 2 k^2 y^2 / r^3 (real); 2 beta dbeta/dy = -2 k^2 y / r^2
+        const float bbr = 2.f * k * k * y * y * inv_r * inv_r * inv_r;
+        const float bby = -2.f * k * k * y * inv_r * inv_r;
+        // - beta^2 dalpha/dr / (4 alpha^2) = -(b2 / 4) (i ar_i) ia^2
+        const float2 ia2 = cmul(ia, ia);
+        const float2 t2 = make_float2(0.25f * b2 * ar_i * ia2.y, -0.25f * b2 * ar_i * ia2.x);
+        lr.x += 0.25f * bbr * ia.x + t2.x;
+        lr.y += 0.25f * bbr * ia.y + t2.y - 0.5f * k * y * y * inv_r * inv_r;
+        ly = make_float2(0.25f * bby * ia.x, 0.25f * bby * ia.y + k * y * inv_r);
+        float et = phi.y * 0.15915494309189535f;
+        et -= rintf(et);
+        const float mag = exp2_fast(phi.x * 1.4426950408889634f);
+        T = cmul(T, make_float2(mag * cos_turns(et), mag * sin_turns(et)));
+    }
+    dl.x += T.x;
+    dl.y += T.y;
+    const float2 tr = cmul(T, lr), ty = cmul(T, ly);
+    d_r.x += tr.x;
+    d_r.y += tr.y;
+    d_y.x += ty.x;
+    d_y.y += ty.y;
+}
+
+template <bool HASY>
+__device__ __forceinline__ void elevation_grad(const ModelConst& K, float k, float r, float y, float2& dl,
+                                               float2& d_r, float2& d_y)
 {
     const float inv_r = rcp_fast(r);
-    const float q = 0.5f * k * (inv_rf - inv_r);
+    const float q = 0.5f * k * (K.inv_rf - inv_r);
     const float ar_i = 0.5f * k * inv_r * inv_r;          // d alpha / dr = i ar_i
     dl = d_r = d_y = make_float2(0.f, 0.f);
+    if (K.ng == 4) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const float bi = G.b[g] + q;
-        const float m2 = fmaf(bi, bi, G.a2[g]);
-        const float inv_mod = rsq_fast(m2);
-        const float mod = m2 * inv_mod;
-        const float x = 0.5f * (mod + G.a[g]);
-        const float rx = rsq_fast(x);
-        const float zr = x * rx * inv_mod, zi = -0.5f * bi * rx * inv_mod;   // alpha^{-1/2}
-        const float2 ia = make_float2(zr * zr - zi * zi, 2.f * zr * zi);     // 1/alpha
-        float2 T = make_float2(G.Ar[g] * zr - G.Ai[g] * zi, G.Ar[g] * zi + G.Ai[g] * zr);
-        // -1/2 (d alpha/dr) / alpha = -1/2 (i ar_i) ia
-        float2 lr = make_float2(0.5f * ar_i * ia.y, -0.5f * ar_i * ia.x);
-        float2 ly = make_float2(0.f, 0.f);
-        if (HASY) {
-            const float b2 = -k * k * y * y * inv_r * inv_r;               // beta^2 (real)
-            const float gam = 0.5f * k * y * y * inv_r;                    // gamma = i gam
-            const float2 phi = make_float2(0.25f * b2 * ia.x, 0.25f * b2 * ia.y + gam);
-            // beta = -i k y / r, dbeta/dr = i k y / r^2, dbeta/dy = -i k / r
-            // 2 beta dbeta/dr = 2 k^2 y^2 / r^3 (real); 2 beta dbeta/dy = -2 k^2 y / r^2
-            const float bbr = 2.f * k * k * y * y * inv_r * inv_r * inv_r;
-            const float bby = -2.f * k * k * y * inv_r * inv_r;
-            // - beta^2 dalpha/dr / (4 alpha^2) = -(b2 / 4) (i ar_i) ia^2
-            const float2 ia2 = cmul(ia, ia);
-            const float2 t2 = make_float2(0.25f * b2 * ar_i * ia2.y, -0.25f * b2 * ar_i * ia2.x);
-            lr.x += 0.25f * bbr * ia.x + t2.x;
-            lr.y += 0.25f * bbr * ia.y + t2.y - 0.5f * k * y * y * inv_r * inv_r;
-            ly = make_float2(0.25f * bby * ia.x, 0.25f * bby * ia.y + k * y * inv_r);
-            float et = phi.y * 0.15915494309189535f;
-            et -= rintf(et);
-            const float mag = exp2_fast(phi.x * 1.4426950408889634f);
-            T = cmul(T, make_float2(mag * cos_turns(et), mag * sin_turns(et)));
+        for (int g = 0; g < 4; ++g)
+            elevation_grad_term<HASY>(K.g.a[g], K.g.a2[g], K.g.b[g], K.g.Ar[g], K.g.Ai[g], q, ar_i, k, y,
+                                      inv_r, dl, d_r, d_y);
+    } else {
+        for (int g = 0; g < K.ng; ++g) {
+            const float4 c = K.gset[g];
+            elevation_grad_term<HASY>(c.x, c.x * c.x, c.y, c.z, c.w, q, ar_i, k, y, inv_r, dl, d_r, d_y);
         }
-        dl.x += T.x;
-        dl.y += T.y;
-        const float2 tr = cmul(T, lr), ty = cmul(T, ly);
-        d_r.x += tr.x;
-        d_r.y += tr.y;
-        d_y.x += ty.x;
-        d_y.y += ty.y;
     }
 }
 
@@ -424,7 +455,7 @@ __device__ __forceinline__ float2 green_grad_next(const ModelConst& K, Geo& g, G
     if (TABLE) {
         dl = delta_table_d(tab, P, jf * g.kap, d_dq);
     } else {
-        elevation_grad<HASY>(K.g, K.inv_rf, k, D.r, D.y, dl, d_r, d_y);
+        elevation_grad<HASY>(K, k, D.r, D.y, dl, d_r, d_y);
     }
     const float2 Gv = cmul(A, dl);
     const float2 Ed = cmul(g.E, dl);
@@ -498,7 +529,7 @@ __device__ __forceinline__ float2 green_next(const ModelConst& K, Geo& g, float 
     const float q = jf * g.kap;
     float2 d;
     if (TABLE) d = delta_table(tab, P, q);
-    else d = elevation<HASY>(K.g, q, jf * K.k_per_bin, g.yr2, g.y2r);
+    else d = elevation<HASY>(K, q, jf * K.k_per_bin, g.yr2, g.y2r);
     g.E = cmul(g.E, g.dE);
     g.d = fmaf(g.lam, g.s, g.d);
     g.s += g.d;

@@ -7,7 +7,8 @@
 
 namespace simus {
 
-// Four-Gaussian elevation constants of Eq. (18), scaled by 1/h^2.
+// Constants of four Gaussians of the elevation aperture (Eq. 12; Eq. 18's
+// by default), scaled by 1/h^2: the unrolled path of four-Gaussian sets.
 struct Gauss4 {
     float a[4];    // Re(B_g) / h^2   (> 0)
     float a2[4];   // a^2
@@ -30,7 +31,9 @@ struct ModelConst {
     float zeta;              // baffle impedance ratio
     int32_t baffle;          // 0 soft, 1 rigid, 2 zeta
     int32_t dim2;            // 2-D acoustics: amplitude 1/sqrt(r), no elevation term
-    Gauss4 g;
+    int32_t ng;              // Gaussians of the elevation aperture (Eq. 12)
+    Gauss4 g;                // the set when ng == 4
+    const float4* gset;      // device [ng]: (Re B/h^2, Im B/h^2, sqrt(pi) Re A, sqrt(pi) Im A)
 };
 
 // The half-angle sinc of the pair set-up, sinc(theta / 2) with |theta / 2| <=
@@ -230,7 +233,9 @@ hipError_t noalloc_scratch(char** ptr);
 hipError_t launch_rrange(uint32_t* rr, const float* x, const float* y, const float* z, int64_t n,
                          const SubGeo& sub, int M, hipStream_t st);
 // unit: every interval holds delta = 1 (2-D acoustics, no elevation term).
+// gset64: device [ng][4] FP64 (Re A, Im A, Re B, Im B) of the Gaussians.
 hipError_t launch_dtable(float4* tab, DeltaParams* par, const uint32_t* rr, const ModelConst& K,
-                         double height, int j_first, int j_last, bool unit, hipStream_t st);
+                         const double* gset64, double height, int j_first, int j_last, bool unit,
+                         hipStream_t st);
 
 }  // namespace simus

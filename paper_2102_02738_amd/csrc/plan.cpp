@@ -1,6 +1,8 @@
 // Host planning for libsimus (see plan.hpp).
 #include "plan.hpp"
 
+#include "eq18.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -54,7 +56,14 @@ Probe make_probe(const simus_probe* p, const simus_medium* m, const simus_option
     require(o->nu >= 0 && o->nu <= 64, "options.nu must be in [0, 64]");
     require(o->nfft >= 0 && o->n_t >= 0, "options.nfft and options.n_t must be >= 0");
     require(o->nfft % 2 == 0, "options.nfft must be even");
-    require(o->tile_bins >= 0 && o->tile_bins <= 32, "options.tile_bins must be in [0, 32]");
+    require(o->n_gauss >= 0 && o->n_gauss <= SIMUS_MAX_GAUSS, "options.n_gauss must be in [0, 32]");
+    require(o->n_gauss == 0 || o->gauss != nullptr, "options.gauss must be non-NULL when n_gauss > 0");
+    for (int g = 0; g < o->n_gauss; ++g) {
+        const double* c = o->gauss + 4 * g;
+        require(std::isfinite(c[0]) && std::isfinite(c[1]) && std::isfinite(c[2]) && std::isfinite(c[3]),
+                "options.gauss must be finite");
+        require(c[2] > 0, "options.gauss: Re B_g must be > 0");
+    }
     require(o->tile_scat >= 0, "options.tile_scat must be >= 0");
     require((o->flags & ~(SIMUS_FLAG_NO_MFMA | SIMUS_FLAG_PERSISTENT | SIMUS_FLAG_NO_DELTA_TABLE |
                           SIMUS_FLAG_2D | SIMUS_FLAG_STATIC | SIMUS_FLAG_ALT_SHAPE)) == 0,
@@ -76,6 +85,19 @@ Probe make_probe(const simus_probe* p, const simus_medium* m, const simus_option
     P.n_cycles = o->n_cycles;
     P.eps = o->spectral_eps;
     P.dim2 = (o->flags & SIMUS_FLAG_2D) != 0;
+    if (o->n_gauss > 0) {
+        for (int g = 0; g < o->n_gauss; ++g) {
+            const double* c = o->gauss + 4 * g;
+            P.gA.emplace_back(c[0], c[1]);
+            P.gB.emplace_back(c[2], c[3]);
+        }
+    } else {
+        // Eq. (18): coefficients 3 and 4 are the conjugates of 1 and 2
+        for (int g = 0; g < 4; ++g) {
+            P.gA.emplace_back(eq18::Ar[g], eq18::Ai[g]);
+            P.gB.emplace_back(eq18::Br[g], eq18::Bi[g]);
+        }
+    }
     P.nu = o->nu > 0 ? o->nu : nu_from_width(P.width, P.fc, P.bandwidth, P.c);
     P.M = P.nu * P.N;
     require(P.M <= 1024, "nu * n_elements must be <= 1024");

@@ -26,6 +26,9 @@ struct Probe {
     double c = 0, alpha_db = 0;
     double fs = 0, n_cycles = 1, eps = 0;
     bool dim2 = false;               // 2-D acoustics (Section V)
+    // Gaussians of the elevation aperture (Eq. 12): A_g, B_g; Eq. (18)'s
+    // four unless the caller gives a set
+    std::vector<std::complex<double>> gA, gB;
     bool convex() const { return radius > 0; }
 };
 

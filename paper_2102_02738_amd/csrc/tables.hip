@@ -6,7 +6,6 @@
 #include <algorithm>
 #include <cmath>
 
-#include "eq18.hpp"
 #include "green.hpp"
 #include "kernels.hpp"
 
@@ -61,14 +60,16 @@ hipError_t launch_rrange(uint32_t* rr, const float* x, const float* y, const flo
     return hipGetLastError();
 }
 
-// delta (without the sqrt(pi) A_g sum's y terms) and d delta / dq at q, FP64.
-__device__ void delta_q(double q, double h, double& dr, double& di, double& gr, double& gi)
+// delta(0, r, k) as a function of q and d delta / dq, FP64, over the
+// Gaussians of the set (gs: [ng][4] = Re A, Im A, Re B, Im B).
+__device__ void delta_q(double q, double h, const double* gs, int ng, double& dr, double& di, double& gr,
+                        double& gi)
 {
     dr = di = gr = gi = 0.0;
     const double sq_pi = 1.7724538509055160273;
-    for (int g = 0; g < 4; ++g) {
-        const double a = eq18::Br[g] / (h * h);
-        const double b = eq18::Bi[g] / (h * h) + q;
+    for (int g = 0; g < ng; ++g) {
+        const double a = gs[4 * g + 2] / (h * h);
+        const double b = gs[4 * g + 3] / (h * h) + q;
         const double mod = hypot(a, b);
         const double s = sqrt(0.5 * (mod + a));
         // alpha^{-1/2} = (s - i b/(2 s)) / |alpha|
@@ -76,7 +77,7 @@ __device__ void delta_q(double q, double h, double& dr, double& di, double& gr, 
         // alpha^{-3/2} = (alpha^{-1/2})^3
         const double z2r = zr * zr - zi * zi, z2i = 2 * zr * zi;
         const double z3r = z2r * zr - z2i * zi, z3i = z2r * zi + z2i * zr;
-        const double Ar = sq_pi * eq18::Ar[g], Ai = sq_pi * eq18::Ai[g];
+        const double Ar = sq_pi * gs[4 * g], Ai = sq_pi * gs[4 * g + 1];
         dr += Ar * zr - Ai * zi;
         di += Ar * zi + Ai * zr;
         // d/dq alpha^{-1/2} = -1/2 alpha^{-3/2} i  ->  (0.5 z3i, -0.5 z3r)
@@ -89,9 +90,9 @@ __device__ void delta_q(double q, double h, double& dr, double& di, double& gr, 
 // One thread per interval: Hermite data at both knots in FP64, converted to
 // the power basis of the local coordinate t in [0, 1).
 __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* par,
-                                                     const uint32_t* rr, double q_per_bin,
-                                                     double inv_rf, double height, int j_first,
-                                                     int j_last, int unit)
+                                                     const uint32_t* rr, const double* gs, int ng,
+                                                     double q_per_bin, double inv_rf, double height,
+                                                     int j_first, int j_last, int unit)
 {
     double rmin = (double)__uint_as_float(rr[0]), rmax = (double)__uint_as_float(rr[1]);
     if (!(rmin <= rmax) || !(rmin > 0.0)) {   // no scatterers
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* p
         const double q = L * w / (1.0 - fabs(w));
         const double dqdw = L / ((1.0 - fabs(w)) * (1.0 - fabs(w)));
         double dr, di, gr, gi;
-        delta_q(q, height, dr, di, gr, gi);
+        delta_q(q, height, gs, ng, dr, di, gr, gi);
         p[e][0] = dr;
         p[e][1] = di;
         m[e][0] = gr * dqdw * dw;
@@ -147,10 +148,11 @@ __global__ __launch_bounds__(DELTA_NT) void k_dtable(float4* tab, DeltaParams* p
 }
 
 hipError_t launch_dtable(float4* tab, DeltaParams* par, const uint32_t* rr, const ModelConst& K,
-                         double height, int j_first, int j_last, bool unit, hipStream_t st)
+                         const double* gset64, double height, int j_first, int j_last, bool unit,
+                         hipStream_t st)
 {
     const double q_per_bin = M_PI * K.turns_per_bin_m;   // pi df / c
-    hipLaunchKernelGGL(k_dtable, dim3(1), dim3(DELTA_NT), 0, st, tab, par, rr, q_per_bin,
+    hipLaunchKernelGGL(k_dtable, dim3(1), dim3(DELTA_NT), 0, st, tab, par, rr, gset64, K.ng, q_per_bin,
                        (double)K.inv_rf, height, j_first, j_last, unit ? 1 : 0);
     return hipGetLastError();
 }

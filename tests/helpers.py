@@ -15,7 +15,8 @@ def oracle_setup(orc, w: dict, nu: int = 0):
     o = w["options"]
     return orc.Setup(**{k: p[k] for k in ORACLE_KEYS}, c=w["medium"]["c"],
                      alpha_db=w["medium"]["alpha_db"], fs=o["fs"], n_cycles=o["n_cycles"],
-                     nu=nu or o.get("nu", 0), dim2=1 if o.get("flags", 0) & 8 else 0)
+                     nu=nu or o.get("nu", 0), dim2=1 if o.get("flags", 0) & 8 else 0,
+                     gauss=o.get("gauss"))
 
 
 def rel_l2(a, b) -> float:

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol(L):
     missing = [s for s in sorted(declared) if not hasattr(lib, s)]
     assert not missing, missing
     assert set(L.EXPORTS) == declared
-    assert lib.simus_version() == 100
+    assert lib.simus_version() == 200
 
 
 @pytest.mark.parametrize("name,scale", [("pw32_s200", 1.0), ("pw128_s50k", 0.01),
@@ -295,3 +295,18 @@ def test_product_and_oracle_share_no_code():
                 if re.search(r"^\s*(from|import)\s+paper_2102_02738_amd\b|#include\s+[\"<][^\">]*(simus\.h|csrc)", src, re.M):
                     bad.append(os.path.join(d, f))
     assert not bad, bad
+
+
+def test_gaussian_set_validation(L):
+    """options.gauss: at most 32 Gaussians, finite, Re B_g > 0; a valid set
+    is accepted by the host planning."""
+    from paper_2102_02738_amd import gaussians as GS
+    w = _base()
+    ok = dict(w["options"], gauss=GS.fit(6))
+    _grid_call(L, options=ok)
+    bad_b = GS.fit(4).copy()
+    bad_b[1, 1] = -1.0 + 2.0j
+    for gset in (bad_b, np.full((2, 2), np.nan + 0j), np.tile(GS.EQ18, (9, 1))):
+        with pytest.raises(L.SimusError) as ei:
+            _grid_call(L, options=dict(w["options"], gauss=gset))
+        assert ei.value.code == -1
