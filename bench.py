@@ -91,10 +91,10 @@ TRANS_ISSUE_COST = 4.0         # a transcendental issues at 1/4 of the FP32 rate
 # (256 CU x 128 FP32 lanes/clk x 2.4 GHz); one "slot" = one lane-instruction.
 VALU_PEAK = 256 * 128 * 2.4e9
 MFMA_FP32_PEAK = 157.3e12      # dense FP32 matrix-core FLOP/s
-# The main workload's synthesis kernel (16-column transmit groups, 128
-# element slots, 4 bins per item, nu = 2, three-product receive sums, y = 0,
+# The main workload's synthesis kernel (one group of 16 transmit columns,
+# 128 element slots, 8 bins per item, nu = 2, (Re, Im) receive sums, y = 0,
 # elevation table).
-MT_KERNEL = "k_synth_mt<128, 1, 4, 2, 3, false, true>"
+MT_KERNEL = "k_synth_mq<128, 2, 2, false, true>"
 
 
 def kernel_sources_digest(files) -> str:

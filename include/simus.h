@@ -144,7 +144,9 @@ typedef struct {
                                         persistent); results are bitwise the same */
 #define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape: matrix-core groups of 16
                                         transmit columns instead of 32 (more than 64
-                                        elements), or for 64 or fewer elements and more
+                                        elements and 16 transmits), four bins per work item
+                                        instead of eight (more than 64 elements, at most 16
+                                        transmits), or for 64 or fewer elements and more
                                         than 32 transmits the other of 32 and 64 columns
                                         (the default takes 64 where it pads no more); vector
                                         path: single transmits instead of pairs, or pairs

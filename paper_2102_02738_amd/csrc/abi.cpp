@@ -424,7 +424,7 @@ struct FwdPlan {
     int n_bt = 0, n_items = 0;
     int64_t slice = 0;
     CommonLayout L{};
-    size_t o_it = 0, o_or = 0, o_pb = 0, o_ns = 0, o_part = 0, o_tk = 0, o_spec = 0;
+    size_t o_it = 0, o_or = 0, o_pb = 0, o_ns = 0, o_part = 0, o_tk = 0, o_spec = 0, o_wt = 0;
     size_t up_size = 0, dv_size = 0;
     std::vector<char> host;
 };
@@ -446,6 +446,9 @@ size_t fwd_layout(FwdPlan& F, int n_items, bool own_spec)
     layout_device(dv, F.L, C);
     F.o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * F.cfg.jt * F.cfg.tt * F.slots);
     F.o_tk = dv.add(sizeof(int32_t) * 4);
+    // the matrix-core kernels' padded weights [n_bins][n_tg][NE][16]
+    const int n_tg16 = (C.n_tx + 15) / 16;
+    F.o_wt = F.cfg.wt ? dv.add(sizeof(float2) * size_t(std::max(C.B.n_bins, 1)) * n_tg16 * F.cfg.ne * 16) : 0;
     const size_t spec_bytes = sizeof(float2) * size_t(C.ph.n) * C.n_tx * C.P.N * std::max(C.B.n_bins, 1);
     F.o_spec = own_spec ? dv.add(spec_bytes) : 0;
     F.up_size = up.size;
@@ -599,6 +602,13 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     const int N = C.P.N, n_tx = C.n_tx, n_ph = C.ph.n;
     float2* spec = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(d, F.o_spec);
     launch_common(d, F.L, C, x, y, z, st);
+    if (cfg.wt)
+        hip_check(timed(K_WTABLE, st, [&] {
+                      return launch_wtable_mt(at<float2>(d, F.o_wt), at<double>(d, F.L.dl), at<float>(d, F.L.ap),
+                                              C.B.n_bins, n_tx, N, cfg.ne, (n_tx + 15) / 16, C.B.j_lo,
+                                              C.B.df, st);
+                  }),
+                  "matrix-core weight table launch");
     SynthArgs A{};
     A.x = x;
     A.y = y;
@@ -606,6 +616,7 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     A.refl = refl;
     A.sub = sub_geo(d, F.L);
     A.W = at<float2>(d, F.L.W);
+    A.WT = cfg.wt ? at<float2>(d, F.o_wt) : nullptr;
     A.items = at<Item>(d, F.o_it);
     A.order = at<int32_t>(d, F.o_or);
     A.n_items = F.n_items;

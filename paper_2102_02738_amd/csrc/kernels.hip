@@ -41,6 +41,43 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
     return hipGetLastError();
 }
 
+__global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ delays,
+                            const float* __restrict__ apod, int n_bins, int n_tx, int N, int ne,
+                            int n_tg, int j_lo, double df)
+{
+    const int64_t total = (int64_t)n_bins * n_tg * ne * 16;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % 16);
+        int64_t r = i / 16;
+        const int e = (int)(r % ne);
+        r /= ne;
+        const int g = (int)(r % n_tg);
+        const int b = (int)(r / n_tg);
+        const int t = 16 * g + c;
+        float2 w = make_float2(0.f, 0.f);
+        if (e < N && t < n_tx) {
+            const int te = t * N + e;
+            const double turns = (double)(j_lo + b) * df * delays[te];
+            const float ph = (float)(turns - rint(turns));
+            const float a = apod ? apod[te] : 1.f;
+            w = make_float2(a * cos_turns(ph), a * sin_turns(ph));
+        }
+        WT[i] = w;
+    }
+}
+
+hipError_t launch_wtable_mt(float2* WT, const double* delays, const float* apod, int n_bins, int n_tx,
+                            int N, int ne, int n_tg, int j_lo, double df, hipStream_t st)
+{
+    const int64_t total = (int64_t)n_bins * n_tg * ne * 16;
+    if (total == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_wtable_mt, dim3(grid), dim3(256), 0, st, WT, delays, apod, n_bins, n_tx, N, ne,
+                       n_tg, j_lo, df);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Synthesis.  One block owns all sub-elements (thread n = sub-element n) and
 // walks the scatterers of one work item in chunks of SC.  For each bin of

@@ -89,6 +89,8 @@ struct SynthArgs {
     const float* refl;
     SubGeo sub;
     const float2* W;    // [n_bins][n_tx][N] transmit weights W e^{i w tau}
+    const float2* WT;   // matrix-core path: [n_bins][n_tg][NE][16] the same weights by
+                        // transmit group, element slot and column, zero-padded
     const Item* items;
     const int32_t* order; // [n_items] draw order: item ids, costliest first
     int32_t n_items;
@@ -114,6 +116,7 @@ struct SynthConfig {
     bool mfma;   // transmit contraction on the matrix cores (synth_mfma.hip)
     int ne;      // matrix-core path: element slots (64 or 128)
     int nx;      // matrix-core path: receive sums per column tile (2 or 3)
+    bool wt;     // matrix-core path: the kernel reads the padded weight table WT
     int grid;    // blocks launched (persistent: resident blocks)
 };
 
@@ -197,6 +200,11 @@ SynthConfig synth_config(int M, int nu, int n_tx, bool has_y, bool table_lds, bo
 
 hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int n_bins, int n_tx,
                          int N, int j_lo, double df, hipStream_t st);
+// The weights in the matrix-core kernels' layout: WT[b][g][e][c] = W of
+// transmit 16 g + c and element e at bin b, zero for e >= N or a transmit
+// past n_tx; ne element slots, n_tg groups of 16 columns.
+hipError_t launch_wtable_mt(float2* WT, const double* delays, const float* apod, int n_bins, int n_tx,
+                            int N, int ne, int n_tg, int j_lo, double df, hipStream_t st);
 // The synthesis kernel instance a configuration runs (nullptr if none), for
 // the launch and for occupancy queries (blocks of cfg.bs threads, or 512 on
 // the matrix-core path).

@@ -37,6 +37,13 @@ namespace simus {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Receive sums of the eight-bin kernel: (Re, Im) pairs.  The three-product
+// form needs 24 more registers per lane and then spills (29 dwords): 16
+// transmits x 11 items of 4 uneven phantoms, quarter size, 329 vs 312 ms.
+#ifndef MQ_NX
+#define MQ_NX 2
+#endif
+
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -369,6 +376,228 @@ __global__ __launch_bounds__(512) void k_synth_mt(SynthArgs A)
     }
 }
 
+
+// One group of 16 transmit columns and 128 or 64 element slots, eight bins
+// per item, two per SIMD: wave w (waves w and w ^ 4 share SIMD w % 4) runs
+// the transmit GEMM of bin w and the receive GEMM of bin w ^ 4.  Per chunk
+// of 16 scatterers:
+//   P1  every thread sets up its pairs once and synthesises the element sums
+//       of all eight bins into LDS;
+//   P2  every wave: transmit GEMM of its bin over all elements (three real
+//       products per complex product, no reduction over waves), the weights
+//       read from the padded table WT in global memory a batch of k-steps
+//       ahead; c = R_s a to LDS;
+//   P3  every wave: receive GEMM of its other bin, X[e][t] += sum_s B[e][s]
+//       c[s][t] over all elements, in its registers; wave 0 loads the next
+//       chunk's scatterers meanwhile.
+// Three barriers per chunk of eight bins, and each pair is set up once per
+// eight bins.
+template <int NE, int NUV, int NX, bool HASY, bool TABLE>
+__global__ __launch_bounds__(512) void k_synth_mq(SynthArgs A)
+{
+    constexpr int NB = 512;
+    constexpr int MS = NE * NUV;            // sub-element slots
+    constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
+    constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
+    constexpr int NSG = NB / MS;            // scatterer groups
+    constexpr int JT = 8;                   // bins per item: two per SIMD
+    constexpr int TPG = 16;                 // transmit columns
+    constexpr int BST = NE + 2;             // row stride of the element sums
+    constexpr int CST = 16;                 // row stride of c[s][t]
+    constexpr int KS = NE / 4;              // transmit-GEMM k-steps (all elements)
+    constexpr int KB = 8;                   // k-steps of weights loaded ahead
+    constexpr int RXE = NE / 16;            // receive element tiles
+    static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
+    static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(NX == 2 || NX == 3, "receive sums: (Re, Im) or three products");
+    static_assert(PPT * NSG == SCH && KS % KB == 0, "threads must cover the chunk");
+
+    __shared__ float4 s_sc[SCH];
+    __shared__ float2 s_B[JT][SCH * BST];
+    __shared__ float2 s_c[JT][SCH * CST];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int gi = lane & 15, gk = lane >> 4;      // MFMA operand lane roles
+    const int btx = wave, brx = wave ^ 4;          // the wave's transmit and receive bins
+    // synthesis role
+    const int n = tid % MS, sh = tid / MS;
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    const int n_tg = (A.n_tx + TPG - 1) / TPG;
+
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
+
+    auto load_chunk = [&](int s0, int s_end) {
+        if (tid < SCH) {
+            const int s = s0 + tid;
+            float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
+            if (s < s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
+            s_sc[tid] = v;
+        }
+    };
+
+    if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+    __syncthreads();
+    int item = s_item;
+    while (item < A.n_items) {
+        const int id = A.order[item];          // costliest first
+        const Item it = A.items[id];
+        const int bt = it.tile & 0xffff, tg = it.tile >> 16;
+        const int jb0 = bt * JT;
+        const int nb = min(JT, A.n_bins - jb0);
+        // this wave's weights: WT[bin][tg][e = 4 k + gk][t = gi], k-step stride 64
+        const int jbw = min(jb0 + btx, A.n_bins - 1);
+        const float2* wg = A.WT + (((int64_t)jbw * n_tg + tg) * NE + gk) * TPG + gi;
+
+        // receive sums of the wave's receive bin: element tiles x ((Re, Im)
+        // or the three products)
+        floatx4 X[RXE][NX];
+#pragma unroll
+        for (int m = 0; m < RXE; ++m)
+#pragma unroll
+            for (int q = 0; q < NX; ++q) X[m][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        load_chunk(it.s_begin, it.s_end);
+        __syncthreads();
+        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+            // ---- P1: set-up, the element sums of the eight bins
+            {
+                Geo g[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const float4 v = s_sc[sh * PPT + k];
+                    g[k] = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+                    if (!active) g[k].E = make_float2(0.f, 0.f);
+                    if (TABLE) g[k].kap *= P.kscale;          // delta_fetch's argument
+                }
+#pragma unroll 1
+                for (int jj = 0; jj < JT; ++jj) {
+                    const float jf = (float)(A.j_lo + jb0 + jj);
+                    float2 G[PPT];
+                    if constexpr (TABLE) {
+                        DeltaFetch fch[2];
+                        fch[0] = delta_fetch(s_tab, P, jf * g[0].kap);
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) {
+                            if (k + 1 < PPT) fch[(k + 1) & 1] = delta_fetch(s_tab, P, jf * g[k + 1].kap);
+                            __builtin_amdgcn_sched_barrier(0);
+                            G[k] = green_next_fetched(g[k], fch[k & 1]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) G[k] = green_next<HASY, TABLE>(A.K, g[k], jf, 1.f, s_tab, P);
+                    }
+                    float2* sB = s_B[jj];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const int s = sh * PPT + k;
+                        if (NUV == 2) {
+                            // both lanes of the pair store the same sum
+                            const float bx = G[k].x + __int_as_float(__builtin_amdgcn_mov_dpp(
+                                                          __float_as_int(G[k].x), 0xB1, 0xF, 0xF, true));
+                            const float by = G[k].y + __int_as_float(__builtin_amdgcn_mov_dpp(
+                                                          __float_as_int(G[k].y), 0xB1, 0xF, 0xF, true));
+                            sB[s * BST + (n >> 1)] = make_float2(bx, by);
+                        } else {
+                            sB[s * BST + n] = G[k];
+                        }
+                    }
+                }
+            }
+            // the first batch of weights, in flight across the barrier
+            float2 wa[2][KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) wa[0][k] = wg[64 * k];
+            __syncthreads();
+            // ---- P2: transmit GEMM of bin btx: rows s = gi, columns t = gi,
+            //      k = element 4 k + gk
+            {
+                const float2* gp = s_B[btx] + gi * BST + gk;
+                floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+#pragma unroll
+                for (int k0 = 0; k0 < KS; k0 += KB) {
+                    const int cur = (k0 / KB) & 1;
+                    if (k0 + KB < KS) {
+#pragma unroll
+                        for (int k = 0; k < KB; ++k) wa[cur ^ 1][k] = wg[64 * (k0 + KB + k)];
+                    }
+                    float2 ga[KB];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) ga[k] = gp[4 * (k0 + k)];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) {
+                        p1 = mfma4(ga[k].x, wa[cur][k].x, p1);
+                        p2 = mfma4(ga[k].y, wa[cur][k].y, p2);
+                        p3 = mfma4(ga[k].x + ga[k].y, wa[cur][k].x + wa[cur][k].y, p3);
+                    }
+                }
+                // D[row][col]: row s = 4 gk + v, col t = gi; c = R_s a
+                float2* sc = s_c[btx];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int s = 4 * gk + v;
+                    const float R = s_sc[s].w;
+                    sc[s * CST + gi] = make_float2(R * (p1[v] - p2[v]), R * (p3[v] - p1[v] - p2[v]));
+                }
+            }
+            __syncthreads();
+            // ---- P3: receive GEMM of bin brx; the next chunk's scatterers
+            {
+                const float2* cb = s_c[brx];
+                const float2* bb = s_B[brx];
+                float2 ca[SCH / 4];
+#pragma unroll
+                for (int k = 0; k < SCH / 4; ++k) ca[k] = cb[(4 * k + gk) * CST + gi];
+#pragma unroll
+                for (int m = 0; m < RXE; ++m) {
+                    float2 ba[SCH / 4];
+#pragma unroll
+                    for (int k = 0; k < SCH / 4; ++k) ba[k] = bb[(4 * k + gk) * BST + 16 * m + gi];
+#pragma unroll
+                    for (int k = 0; k < SCH / 4; ++k) {
+                        if (NX == 3) {
+                            X[m][0] = mfma4(ba[k].x, ca[k].x, X[m][0]);
+                            X[m][1] = mfma4(ba[k].y, ca[k].y, X[m][1]);
+                            X[m][2] = mfma4(ba[k].x + ba[k].y, ca[k].x + ca[k].y, X[m][2]);
+                        } else {
+                            X[m][0] = mfma4(ba[k].x, ca[k].x, X[m][0]);
+                            X[m][0] = mfma4(-ba[k].y, ca[k].y, X[m][0]);
+                            X[m][1] = mfma4(ba[k].x, ca[k].y, X[m][1]);
+                            X[m][1] = mfma4(ba[k].y, ca[k].x, X[m][1]);
+                        }
+                    }
+                }
+            }
+            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end);
+            __syncthreads();
+        }
+        // per-element partials [item][JT][TPG][N] of the wave's receive bin;
+        // D[row][col]: row = element 16 m + 4 gk + v, col = transmit gi
+        if (brx < nb) {
+            float2* out = A.part + ((int64_t)id * JT + brx) * TPG * A.N;
+#pragma unroll
+            for (int m = 0; m < RXE; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int e = 16 * m + 4 * gk + v;
+                    const float x1 = X[m][0][v], x2 = X[m][1][v], x3 = X[m][NX - 1][v];
+                    const float2 xv = NX == 3 ? make_float2(x1 - x2, x3 - x1 - x2) : make_float2(x1, x2);
+                    if (e < A.N) out[(int64_t)gi * A.N + e] = xv;
+                }
+        }
+        if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+        __syncthreads();
+        item = s_item;
+    }
+}
+
 // Shape of a group: element slots NE (64 or 128) and 16-transmit column
 // tiles NTP; bins per item JT and receive sums NX are chosen so that the
 // receive sums (4 NX JT NTP / CS floats per lane) fit the register file.
@@ -383,13 +612,18 @@ static MtShape mt_shape(int N, int n_tx, bool alt)
     // scatterers: 128 transmits 42.5 vs 44.7 ms with 32; 40 and 64 equal; 96
     // transmits 41.9 vs 32.5 ms, so 32 there); the alternative takes the
     // other width.  128 slots: 32 columns above 16 transmits (21 transmits,
-    // 200k scatterers: 215 vs 258 ms with 16), 4 bins per item (5 spill);
-    // alternative: 16 columns.
+    // 200k scatterers: 215 vs 258 ms with 16; the eight-bin kernel over two
+    // groups of 16 columns: 197 vs 189 ms), 4 bins per item (5 spill);
+    // alternative: 16 columns.  Up to 16 transmits: the eight-bin kernel
+    // (curved array, 11 transmits, quarter of the uneven 16-phantom batch:
+    // 312 vs 398 ms; 5 transmits, 100k scatterers: 47.3 vs 62.0 ms), whose
+    // alternative is the four-bin one.
     if (N <= 64) {
         const bool wide = (n_tx + 63) / 64 * 64 == (n_tx + 31) / 32 * 32;
         if (n_tx > 32 && wide != alt) return {64, 4, 6, 2};
         return {64, 2, 6, 3};
     }
+    if (n_tx <= 16 && !alt) return {128, 1, 8, MQ_NX};
     if (n_tx <= 16 || alt) return {128, 1, 4, 3};
     return {128, 2, 4, 2};
 }
@@ -426,6 +660,7 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt)
     c.tt = 16 * sh.ntp;                       // transmits per group
     c.jt = sh.jt;
     c.nx = sh.nx;
+    c.wt = sh.ne == 128 && sh.ntp == 1 && sh.jt == 8;
     c.sc = 16;
     c.pair = M == 2 * N;
     c.has_y = has_y;
@@ -434,8 +669,18 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt)
     return c;
 }
 
+template <int NE, int NX, int NUV>
+static SynthKernel mq_kernel_nuv(const SynthConfig& c)
+{
+    if (c.has_y) return k_synth_mq<NE, NUV, NX, true, false>;
+    if (c.table) return k_synth_mq<NE, NUV, NX, false, true>;
+    return k_synth_mq<NE, NUV, NX, false, false>;
+}
+
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
+    if (c.wt && c.ne == 128 && c.tt == 16 && c.jt == 8)
+        return c.pair ? mq_kernel_nuv<128, MQ_NX, 2>(c) : mq_kernel_nuv<128, MQ_NX, 1>(c);
     if (c.ne == 128 && c.tt == 16) return mt_kernel_shape<128, 1, 4, 3>(c);
     if (c.ne == 128 && c.tt == 32) return mt_kernel_shape<128, 2, 4, 2>(c);
     if (c.ne == 64 && c.tt == 32) return mt_kernel_shape<64, 2, 6, 3>(c);

@@ -220,6 +220,33 @@ def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
     assert rel_l2(rf, ref) <= TOL
 
 
+@pytest.mark.parametrize("n_tx,n_el,nu,with_y,no_table", [
+    (4, 128, 2, False, False), (16, 128, 1, False, False), (13, 96, 2, True, False),
+    (7, 128, 1, True, False), (9, 72, 2, False, True), (15, 128, 1, False, True)])
+def test_eight_bin_matrix_core_kernel(S, orc, n_tx, n_el, nu, with_y, no_table):
+    """The default matrix-core kernel for more than 64 elements and at most 16
+    transmits (eight bins per item, weights from the padded table): every
+    compiled form (nu = 1 and 2; y != 0; the elevation term from the table or
+    evaluated directly), from 4 to 16 transmits, element slots left empty
+    (72, 96), ragged last bin tile and scatterer chunk; full RF against the
+    oracle."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.43)
+    w["probe"] = inputs.linear_probe(n_el)
+    w["options"]["nu"] = nu
+    w["delays"] = inputs.plane_wave_delays(w["probe"], np.linspace(-14, 14, n_tx))
+    w["apod"] = np.random.default_rng(n_tx + n_el).uniform(0.2, 1.0, w["delays"].shape).astype(np.float32)
+    if with_y:
+        w["phantoms"][0]["y"] = np.random.default_rng(2).uniform(
+            -1e-3, 1e-3, w["phantoms"][0]["x"].size).astype(np.float32)
+    g, rf, data = _run(S, w, flags=S.FLAG_NO_DELTA_TABLE if no_table else 0, with_y=with_y)
+    assert g["n_bins"] % 8 != 0 and data[0].size % 16 != 0, "ragged last bin tile and chunk"
+    ref = _oracle_rf(orc, w, g, data, with_y=with_y)
+    print(n_tx, "tx", n_el, "el nu", nu, "y" if with_y else "", "direct" if no_table else "",
+          "bins", g["n_bins"], "rel L2", rel_l2(rf, ref))
+    assert rel_l2(rf, ref) <= TOL
+
+
 def test_many_transmits_full_size_sampled_bins(S, orc):
     """21 plane waves, 200,000 scatterers (the compounding workload) in the
     benchmark's launch configuration: sampled bins against the oracle."""
@@ -323,13 +350,14 @@ def test_coarse_grid_general_half_sinc(S, orc):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("n_tx,n_el,nu", [(21, 100, 0), (40, 48, 0), (5, 200, 0), (6, 64, 3)])
+@pytest.mark.parametrize("n_tx,n_el,nu", [(21, 100, 0), (11, 128, 0), (40, 48, 0), (5, 200, 0), (6, 64, 3)])
 def test_alt_tile_shape(S, orc, n_tx, n_el, nu):
     """The alternative tile shape (SIMUS_FLAG_ALT_SHAPE: matrix-core groups
-    of 16 instead of 32 transmit columns for 100 elements, of 64 instead of
-    32 for 48; on the vector path pairs instead of single transmits for 5,
-    single instead of pairs for 6) matches the oracle and the default shape
-    to rounding order."""
+    of 16 instead of 32 transmit columns for 100 elements, four instead of
+    eight bins per item for 128 elements and 11 transmits, 64 instead of
+    32 columns for 48 elements; on the vector path pairs instead of single
+    transmits for 5, single instead of pairs for 6) matches the oracle and
+    the default shape to rounding order."""
     from paper_2102_02738_amd import inputs
     w = inputs.workload("pw32_s200", scale=0.3)
     w["probe"] = inputs.linear_probe(n_el)
