@@ -321,13 +321,57 @@ def extra_autotune(steps: int, name: str) -> dict:
                 gain=d_ms / t_ms, rel_l2_autotuned_vs_default=_rel(out, first))
 
 
-def extra_pfield(steps: int) -> dict:
-    """simus_pfield on a Fig. 9-like field: 64-element 2.7 MHz phased array
-    focused at (10, 60) mm, 256 x 256 points over x in [-40, 40] mm, z in
-    [5, 100] mm."""
+# Algorithmic work of the field (Eqs. 22 and 42), in the same lane issue
+# slots: per (point, sub-element, frequency) one Green's term (28, as above)
+# and its complex MAC with the transmit weight (4); per (point, frequency)
+# the product with P_Tx (4), |.|^2 (2) and the 1/j^2 scaling (1).
+PF_TERM_SLOTS = G_EVAL_SLOTS + 4.0
+PF_POINT_BIN_SLOTS = 7.0
+
+
+def _pfield_case(workload: str, probe: dict, dl, X, Z, steps: int) -> dict:
     import numpy as np
     import torch
-    from paper_2102_02738_amd import pfield, pfield_nf
+    from paper_2102_02738_amd import _lib, grid, pfield, pfield_nf
+    medium = dict(c=1540.0, alpha_db=0.5)
+    options = dict(fs=4 * probe["fc"], n_cycles=1.0, nu=0, spectral_eps=1e-7, nfft=0, n_t=0)
+    nf = pfield_nf(probe, medium, options, dl, X, None, Z)
+    dX, dZ = (torch.from_numpy(a).cuda() for a in (X, Z))
+    apod = np.ones(probe["n_elements"], np.float32)
+    out = {}
+
+    def call():
+        out["p"] = pfield(probe, medium, options, nf, dl, apod, dX, None, dZ)
+
+    ms = _median_ms(call, max(steps, 5))
+    # the field kernel alone: HIP events around its launches, on its stream
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    for _ in range(max(steps, 5)):
+        call()
+    torch.cuda.synchronize()
+    _lib.profile_enable(False)
+    k_ms, k_n = _lib.profile_read("pfield")
+    k_ms /= max(k_n, 1)
+    nu = grid(probe, medium, options, dl[None, :], X[:1], None, Z[:1])["nu"]
+    M = nu * probe["n_elements"]
+    evals = float(X.size) * M * nf                  # j = 1 .. N_f (j = 0 adds nothing)
+    alg = evals * PF_TERM_SLOTS + float(X.size) * nf * PF_POINT_BIN_SLOTS
+    return dict(workload=workload, n_points=int(X.size), n_f=int(nf), nu=int(nu),
+                ms_per_call=ms, points_per_s=X.size / (ms * 1e-3),
+                point_subelement_freq_evals_per_s=evals / (ms * 1e-3),
+                kernel_ms=k_ms,
+                roofline=dict(bound="alu", achieved=alg / (k_ms * 1e-3) / 1e12, peak=VALU_PEAK / 1e12,
+                              unit="TOP/s", frac=alg / (k_ms * 1e-3) / VALU_PEAK, traffic=None,
+                              kernel="k_pfield<16, false, true>",
+                              work_per_unit=dict(term=PF_TERM_SLOTS, point_bin=PF_POINT_BIN_SLOTS)),
+                finite=bool(torch.isfinite(out["p"]).all()))
+
+
+def extra_pfield_fig9(steps: int) -> dict:
+    """Fig. 9-like field: 64-element 2.7 MHz phased array focused at (10, 60)
+    mm, 256 x 256 points over x in [-40, 40] mm, z in [5, 100] mm."""
+    import numpy as np
     probe = dict(n_elements=64, fc=2.7e6, pitch=0.3e-3, width=0.25e-3, height=14e-3,
                  elev_focus=60e-3, bandwidth=0.74, radius=0.0, baffle=0, zeta=1.75)
     xe = 0.3e-3 * (np.arange(64) - 31.5)
@@ -335,24 +379,27 @@ def extra_pfield(steps: int) -> dict:
     dl = d.max() - d
     X, Z = np.meshgrid(np.linspace(-40e-3, 40e-3, 256), np.linspace(5e-3, 100e-3, 256))
     X, Z = X.ravel().astype(np.float32), Z.ravel().astype(np.float32)
-    medium = dict(c=1540.0, alpha_db=0.5)
-    options = dict(fs=4 * probe["fc"], n_cycles=1.0, nu=0, spectral_eps=1e-7, nfft=0, n_t=0)
-    nf = pfield_nf(probe, medium, options, dl, X, None, Z)
-    dX, dZ = (torch.from_numpy(a).cuda() for a in (X, Z))
-    apod = np.ones(64, np.float32)
-    out = {}
+    return _pfield_case("phased64 focused field 256x256", probe, dl, X, Z, steps)
 
-    def call():
-        out["p"] = pfield(probe, medium, options, nf, dl, apod, dX, None, dZ)
 
-    ms = _median_ms(call, max(steps, 5))
-    from paper_2102_02738_amd import grid
-    nu = grid(probe, medium, options, dl[None, :], X[:1], None, Z[:1])["nu"]
-    evals = float(X.size) * 64 * nu * (nf + 1)
-    return dict(workload="phased64 focused field 256x256", n_points=int(X.size), n_f=int(nf), nu=int(nu),
-                ms_per_call=ms, points_per_s=X.size / (ms * 1e-3),
-                point_subelement_freq_evals_per_s=evals / (ms * 1e-3),
-                finite=bool(torch.isfinite(out["p"]).all()))
+def extra_pfield_fig10(steps: int) -> dict:
+    """Fig. 10-like field: 128-element 7.6 MHz linear array (pitch 0.27 mm,
+    kerf 30 um), one plane wave tilted by 10 degrees, 256 x 256 points over x
+    in [-25, 25] mm, z in [1, 50] mm."""
+    import numpy as np
+    from paper_2102_02738_amd import inputs
+    lin = dict(inputs.linear_probe(128), pitch=0.27e-3, width=0.24e-3)
+    dl = inputs.plane_wave_delays(lin, [10.0])[0]
+    X, Z = np.meshgrid(np.linspace(-25e-3, 25e-3, 256), np.linspace(1e-3, 50e-3, 256))
+    X, Z = X.ravel().astype(np.float32), Z.ravel().astype(np.float32)
+    return _pfield_case("linear128 plane-wave field 256x256", lin, dl, X, Z, steps)
+
+
+def extra_pfield(steps: int) -> dict:
+    """simus_pfield on the two field shapes above (the Fig. 9 one first)."""
+    res = extra_pfield_fig9(steps)
+    res["linear128_plane_wave"] = extra_pfield_fig10(steps)
+    return res
 
 
 def extra_forward_adjoint(steps: int) -> dict:
@@ -541,7 +588,8 @@ def main():
                "single_transmit": lambda k: extra_single_transmit(max(k, 5)),
                "batched_transmits": extra_batched_transmits, "uneven_phantoms": extra_uneven_phantoms,
                "forward_adjoint": extra_forward_adjoint, "large_t": extra_large_t,
-               "pfield": extra_pfield,
+               "pfield": extra_pfield, "pfield_fig9": extra_pfield_fig9,
+               "pfield_fig10": extra_pfield_fig10,
                "two_d": lambda k: extra_two_d(k, float("nan"))}
         if args.only_extra not in fns:
             print(f"unknown extra {args.only_extra!r}; one of {sorted(fns)}", file=sys.stderr)

@@ -822,13 +822,12 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     C.table = C.P.dim2 || (!C.has_y && !(opt->flags & SIMUS_FLAG_NO_DELTA_TABLE));
     C.ph.n = 1;
     C.ph.total = n_pts;
-    const int JT = PFIELD_JT;
-    // frequency ranges: about 2000 blocks
+    // frequency ranges of nearly equal size, each split into tiles of at
+    // most PFIELD_JT bins: as many ranges as tiles, up to about 6 rounds of
+    // resident blocks (5 per CU) over the point blocks
     const int64_t n_pb = (n_pts + 255) / 256;
-    int64_t rb = (int64_t(n_f) * n_pb + 1999) / 2000;
-    rb = std::max<int64_t>(JT, (rb + JT - 1) / JT * JT);
-    const int range_bins = (int)std::min<int64_t>(rb, n_f);
-    const int n_ranges = (n_f + range_bins - 1) / range_bins;
+    const int64_t n_tl = (n_f + PFIELD_JT - 1) / PFIELD_JT;
+    const int n_ranges = (int)std::max<int64_t>(1, std::min<int64_t>(n_tl, (6 * 1280 + n_pb - 1) / n_pb));
     if (n_pb > 0x7fffffff || n_ranges > 65535) throw Error{SIMUS_EINVAL, "too many field points"};
 
     Layout up;
@@ -866,7 +865,7 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     F.N = C.P.N;
     F.n_bins = n_f;
     F.j_lo = 1;
-    F.range_bins = range_bins;
+    F.n_ranges = n_ranges;
     F.K = dev_consts(C, d, L);
     hip_check(timed(K_PFIELD, st, [&] { return launch_pfield(F, C.has_y, C.table, n_ranges, st); }),
               "field launch");

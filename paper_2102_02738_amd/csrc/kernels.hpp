@@ -178,14 +178,15 @@ struct FieldArgs {
     const float4* dtab;
     const DeltaParams* dpar;
     int64_t n_pts;
-    int32_t M, nu, N, n_bins, j_lo, range_bins;
+    int32_t M, nu, N, n_bins, j_lo, n_ranges;
     ModelConst K;
 };
 
-// Frequencies per (point, sub-element) set-up of the field kernel; frequency
-// ranges are a multiple of it.  Timed on the 64-element, 256 x 256-point,
-// 402-frequency field: 8 -> 1.74 ms, 16 -> 1.58 ms, 32 -> 1.66 ms (registers
-// halve the occupancy).
+// Frequencies per (point, sub-element) set-up of the field kernel, at most:
+// a block's frequency range is split into tiles of nearly equal size.  Timed
+// on the 64-element, 256 x 256-point, 402-frequency field: 8 -> 1.74 ms,
+// 16 -> 1.58 ms, 32 -> 1.66 ms (registers halve the occupancy); with the
+// balanced ranges and tiles, 16 -> 1.48 ms, 24 -> 1.49 ms, 32 -> 1.70 ms.
 constexpr int PFIELD_JT = 16;
 hipError_t launch_pfield(const FieldArgs& a, bool has_y, bool table, int n_ranges, hipStream_t st);
 hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, float dw, float* out,

@@ -5,9 +5,11 @@
 // The j = 0 node contributes nothing (S_P(0) = 0).
 //
 // One thread owns one field point and loops over all sub-elements for a tile
-// of JT frequencies, so that each (point, sub-element) set-up, with its FP64
-// distance, serves JT terms; blocks cover (256 points, frequency range) and a
-// second kernel sums the ranges in a fixed order.  The tile accumulates j P
+// of up to JT frequencies, so that each (point, sub-element) set-up, with its
+// FP64 distance, serves up to JT terms; blocks cover (256 points, frequency
+// range), the ranges and their tiles of nearly equal size (no short tail
+// tile pays a whole set-up), and a second kernel sums the ranges in a fixed
+// order.  The tile accumulates j P
 // (terms j G, as in the synthesis), and 1/j^2 is applied to |j P|^2 once per
 // point and frequency.
 #include <hip/hip_runtime.h>
@@ -35,10 +37,14 @@ __global__ __launch_bounds__(256) void k_pfield(FieldArgs A)
     const float px = live ? A.X[pt] : 0.f;
     const float py = (HASY && live) ? A.Y[pt] : 0.f;
     const float pz = live ? A.Z[pt] : 1.f;
-    const int b_begin = range * A.range_bins;
-    const int b_end = min(A.n_bins, b_begin + A.range_bins);
+    // the range's bins, then tiles of at most JT bins of nearly equal size
+    const int b_begin = (int)((int64_t)range * A.n_bins / A.n_ranges);
+    const int b_len = (int)((int64_t)(range + 1) * A.n_bins / A.n_ranges) - b_begin;
+    const int n_tiles = (b_len + JT - 1) / JT;
     float sum = 0.f;
-    for (int jb0 = b_begin; jb0 < b_end; jb0 += JT) {
+    for (int t = 0; t < n_tiles; ++t) {
+        const int jb0 = b_begin + t * b_len / n_tiles;
+        const int b_end = b_begin + (t + 1) * b_len / n_tiles;
         float2 acc[JT];
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) acc[jj] = make_float2(0.f, 0.f);
