@@ -277,9 +277,10 @@ def extra_uneven_phantoms(steps: int) -> dict:
 
     g_ms = _median_ms(graph, steps)
     first = out.clone()
-    t0 = time.perf_counter()
-    chosen = plan.autotune(c.x, None, c.z, c.R)
-    tune_s = time.perf_counter() - t0
+    plan.close()
+    plan, info = _autotune_cached(
+        lambda: rf_plan(w["probe"], w["medium"], c.o, w["delays"], w["apod"], offsets=c.off),
+        lambda p: p.autotune(c.x, None, c.z, c.R))
     gt_ms = _median_ms(graph, steps)
     tuned = out.clone()
     po = dict(c.o, flags=FLAG_NO_MFMA)
@@ -296,28 +297,59 @@ def extra_uneven_phantoms(steps: int) -> dict:
     p_ms = _median_ms(loop, 1, warmup=0)
     plan.close()
     return dict(workload=c.name, graph_ms=g_ms, plain_ms=p_ms, speedup_vs_plain=p_ms / g_ms,
-                autotune=dict(chosen=chosen, tuning_s=tune_s, graph_ms_default=g_ms,
-                              graph_ms_autotuned=gt_ms, rel_l2_autotuned_vs_plain=_rel(tuned, plain)),
+                autotune=dict(**info, graph_ms_default=g_ms, graph_ms_autotuned=gt_ms,
+                              gain=g_ms / gt_ms, rel_l2_autotuned_vs_plain=_rel(tuned, plain)),
                 rel_l2_graph_vs_plain=_rel(first, plain))
 
 
+AUTOTUNE_SPACE = ("the distinct tile shapes of the default rule, SIMUS_FLAG_ALT_SHAPE and "
+                  "SIMUS_FLAG_EIGHT_BIN (kernel, element slots, transmit columns, bins per item) x "
+                  "scatterers per item 0.5/1/2x the default (vector path also 1.5x, and static or "
+                  "persistent launch)")
+
+
+def _autotune_cached(make_plan, tune):
+    """Tunes a first plan with an empty file cache (timed), then a second plan
+    of the same problem class (answered from the cache)."""
+    import tempfile
+    import paper_2102_02738_amd as S
+    with tempfile.TemporaryDirectory() as td:
+        S.tune_cache(os.path.join(td, "tune.txt"))
+        try:
+            plan = make_plan()
+            t0 = time.perf_counter()
+            chosen = tune(plan)
+            tune_s = time.perf_counter() - t0
+            hits = S.tune_cache_hits()
+            plan2 = make_plan()
+            t0 = time.perf_counter()
+            chosen2 = tune(plan2)
+            cached_s = time.perf_counter() - t0
+            assert S.tune_cache_hits() == hits + 1 and chosen2 == chosen
+            plan2.close()
+        finally:
+            S.tune_cache(None)
+    return plan, dict(chosen=chosen, tuning_s=tune_s, cached_tuning_s=cached_s, search_space=AUTOTUNE_SPACE)
+
+
 def extra_autotune(steps: int, name: str) -> dict:
-    """A plan for the workload with the default launch shape against the
-    same plan after simus_rf_plan_autotune."""
+    """A plan for the workload with the default launch shape against a plan
+    after simus_rf_plan_autotune (with the file cache: the tuning time, then
+    the time of a second plan's autotune answered from the cache)."""
     import torch
     from paper_2102_02738_amd import rf_plan
     c = Case(name)
     w = c.w
-    plan = rf_plan(w["probe"], w["medium"], c.o, w["delays"], w["apod"], offsets=c.off)
+    make = lambda: rf_plan(w["probe"], w["medium"], c.o, w["delays"], w["apod"], offsets=c.off)
+    plan0 = make()
     out = torch.empty((c.P, c.T, c.N, c.n_t), device="cuda")
-    d_ms = _median_ms(lambda: plan.execute_into(out, c.x, None, c.z, c.R), steps)
+    d_ms = _median_ms(lambda: plan0.execute_into(out, c.x, None, c.z, c.R), steps)
     first = out.clone()
-    t0 = time.perf_counter()
-    chosen = plan.autotune(c.x, None, c.z, c.R, c.n_t)
-    tune_s = time.perf_counter() - t0
+    plan0.close()
+    plan, info = _autotune_cached(make, lambda p: p.autotune(c.x, None, c.z, c.R, c.n_t))
     t_ms = _median_ms(lambda: plan.execute_into(out, c.x, None, c.z, c.R), steps)
     plan.close()
-    return dict(workload=name, chosen=chosen, tuning_s=tune_s, default_ms=d_ms, autotuned_ms=t_ms,
+    return dict(workload=name, **info, default_ms=d_ms, autotuned_ms=t_ms,
                 gain=d_ms / t_ms, rel_l2_autotuned_vs_default=_rel(out, first))
 
 
@@ -585,6 +617,7 @@ def main():
 
     if args.only_extra:
         fns = {"autotune": lambda k: extra_autotune(max(k, 5), "pw128_s50k"),
+               "autotune_batched": lambda k: extra_autotune(max(k, 3), "pw128x21_s200k"),
                "single_transmit": lambda k: extra_single_transmit(max(k, 5)),
                "batched_transmits": extra_batched_transmits, "uneven_phantoms": extra_uneven_phantoms,
                "forward_adjoint": extra_forward_adjoint, "large_t": extra_large_t,
@@ -687,6 +720,7 @@ def main():
         res["extras"] = {
             "single_transmit": st,
             "autotune": extra_autotune(max(args.extra_steps, 5), "pw128_s50k"),
+            "autotune_batched": extra_autotune(max(args.extra_steps, 3), "pw128x21_s200k"),
             "batched_transmits": extra_batched_transmits(args.extra_steps),
             "uneven_phantoms": extra_uneven_phantoms(args.extra_steps),
             "forward_adjoint": extra_forward_adjoint(args.extra_steps),

@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define SIMUS_VERSION 200
+#define SIMUS_VERSION 201
 
 #define SIMUS_OK 0
 #define SIMUS_EINVAL (-1)   /* invalid argument (NULL pointer, bad size, bad parameter) */
@@ -142,18 +142,25 @@ typedef struct {
 #define SIMUS_FLAG_STATIC       16   /* vector path: one block per work item instead of the
                                         persistent launch (the matrix-core path is always
                                         persistent); results are bitwise the same */
-#define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape: matrix-core groups of 16
-                                        transmit columns instead of 32 (more than 64
-                                        elements and 16 transmits), four bins per work item
-                                        instead of eight (more than 64 elements, at most 16
-                                        transmits), or for 64 or fewer elements and more
-                                        than 32 transmits the other of 32 and 64 columns
-                                        (the default takes 64 where it pads no more); vector
-                                        path: single transmits instead of pairs, or pairs
-                                        instead of single transmits.  The autotuner tries
-                                        it.  simus_rf_backward: the other of its two kernels
-                                        (matrix-core or vector) where both apply.  The
-                                        results agree to rounding order */
+#define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape.  Matrix-core path, at
+                                        most 16 transmits: four bins per work item instead of
+                                        eight (more than 64 elements), or groups of 32
+                                        transmit columns and six bins instead of 16 and eight
+                                        (64 or fewer); more transmits: groups of 16 columns
+                                        instead of 32 (more than 64 elements), or the other of
+                                        32 and 64 columns (64 or fewer elements, more than 32
+                                        transmits; the default takes 64 where it pads no
+                                        more).  Vector path: single transmits instead of
+                                        pairs, or pairs instead of single transmits.  The
+                                        autotuner tries it.  simus_rf_backward: the other of
+                                        its two kernels (matrix-core or vector) where both
+                                        apply.  The results agree to rounding order */
+#define SIMUS_FLAG_EIGHT_BIN    64   /* matrix-core path, more than 16 transmits: the kernel
+                                        that synthesises eight bins per pair set-up, over
+                                        groups of 16 transmit columns (the default for at most
+                                        16 transmits; ignored there and on the vector path).
+                                        The autotuner tries it.  Results agree to rounding
+                                        order */
 /* Other bits of options.flags are rejected with SIMUS_EINVAL. */
 
 /* Frequency grid of one call. */
@@ -325,6 +332,27 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
 int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y,
                            const float* z, const float* refl, float* rf, void* hip_stream,
                            int64_t* tile_scat, int32_t* flags);
+
+/* Process-wide file cache of simus_rf_plan_autotune's choices (native, text,
+ * one line per choice: problem class, shape flags, scatterers per item as a
+ * multiple of the default rule's count, time).  With a path set, the
+ * autotuner first looks up the plan's problem class in the file: the path
+ * (matrix-core or vector), sub-elements, elements, transmits, y given or
+ * not, elevation table, 2-D, the flags other than SIMUS_FLAG_ALT_SHAPE,
+ * SIMUS_FLAG_EIGHT_BIN and SIMUS_FLAG_STATIC, the library version, and the
+ * binary logarithms of the bins, scatterers and phantoms.  If a line is
+ * there (the last one counts), it applies that choice without timing;
+ * otherwise it tunes as described above and appends its choice.  Lines are
+ * written whole; several processes may share one file.  path NULL or ""
+ * switches the cache off (the default).  The path is copied.
+ * Errors: EINVAL for a path longer than 4095 bytes; simus_rf_plan_autotune
+ * returns EINVAL if it cannot append to the file (the plan keeps the tuned
+ * configuration). */
+int simus_tune_cache(const char* path);
+
+/* Number of simus_rf_plan_autotune calls of this process answered from the
+ * cache. */
+int64_t simus_tune_cache_hits(void);
 
 /* Waits for the device, then frees the plan's graph, stream and workspace.
  * NULL is ignored. */

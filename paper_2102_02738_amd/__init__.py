@@ -14,10 +14,11 @@ call raises if the library has not been built.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import SimusError, FLAG_NO_MFMA, FLAG_PERSISTENT, FLAG_NO_DELTA_TABLE, FLAG_2D, FLAG_STATIC, FLAG_ALT_SHAPE  # noqa: F401
+from ._lib import SimusError, FLAG_NO_MFMA, FLAG_PERSISTENT, FLAG_NO_DELTA_TABLE, FLAG_2D, FLAG_STATIC, FLAG_ALT_SHAPE, FLAG_EIGHT_BIN  # noqa: F401
 
 __all__ = ["grid", "rf", "rf_spectrum", "spectrum_to_rf", "rf_backward", "pfield", "pfield_nf",
-           "RFPlan", "rf_plan", "SimusRF", "simus_rf_autograd", "release_workspace", "SimusError"]
+           "RFPlan", "rf_plan", "SimusRF", "simus_rf_autograd", "release_workspace", "tune_cache",
+           "tune_cache_hits", "SimusError"]
 
 
 def _opts_with_grid(options: dict, g: dict) -> dict:
@@ -144,6 +145,15 @@ def rf_plan(probe, medium, options, delays, apod, n_scat=None, offsets=None, has
 
 def release_workspace():
     _lib.release_workspace()
+
+
+def tune_cache(path):
+    """File cache of the autotuner's choices per problem class (None: off)."""
+    _lib.tune_cache(path)
+
+
+def tune_cache_hits() -> int:
+    return _lib.tune_cache_hits()
 
 
 def __getattr__(name):

@@ -23,14 +23,15 @@ FLAG_NO_DELTA_TABLE = 4
 FLAG_2D = 8
 FLAG_STATIC = 16
 FLAG_ALT_SHAPE = 32
+FLAG_EIGHT_BIN = 64
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",
            "simus_rf_noalloc",
            "simus_spectrum_to_rf", "simus_rf_backward", "simus_pfield_nf", "simus_pfield",
            "simus_rf_plan_create", "simus_rf_plan_execute", "simus_rf_plan_graph_launch",
-           "simus_rf_plan_autotune", "simus_rf_plan_destroy", "simus_release_workspace", "simus_profile_enable",
-           "simus_profile_read", "simus_profile_reset"]
+           "simus_rf_plan_autotune", "simus_tune_cache", "simus_tune_cache_hits", "simus_rf_plan_destroy",
+           "simus_release_workspace", "simus_profile_enable", "simus_profile_read", "simus_profile_reset"]
 
 
 class SimusError(RuntimeError):
@@ -96,6 +97,8 @@ def lib():
             "simus_rf_plan_execute": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "simus_rf_plan_graph_launch": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "simus_rf_plan_autotune": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pi64, pi32]),
+            "simus_tune_cache": (C.c_int, [C.c_char_p]),
+            "simus_tune_cache_hits": (C.c_int64, []),
             "simus_rf_plan_destroy": (None, [vp]),
             "simus_release_workspace": (None, []),
             "simus_profile_enable": (C.c_int, [C.c_int]),
@@ -400,6 +403,16 @@ class RFPlan:
 
 def release_workspace():
     lib().simus_release_workspace()
+
+
+def tune_cache(path):
+    """Sets (or, with None, clears) the autotuner's file cache of choices."""
+    check(lib().simus_tune_cache(os.fsencode(path) if path else None))
+
+
+def tune_cache_hits() -> int:
+    """Autotuner calls of this process answered from the cache."""
+    return int(lib().simus_tune_cache_hits())
 
 
 def profile_enable(on: bool = True):

@@ -497,7 +497,8 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
                Cc.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
     SynthConfig& cfg = F.cfg;
     const bool alt = (opt->flags & SIMUS_FLAG_ALT_SHAPE) != 0;
-    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y, alt)
+    const bool eight = (opt->flags & SIMUS_FLAG_EIGHT_BIN) != 0;
+    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y, alt, eight)
                    : synth_config(M, Cc.P.nu, n_tx, Cc.has_y, Cc.table && !Cc.P.dim2, alt);
     cfg.table = Cc.table;
     cfg.dim2 = Cc.P.dim2;   // the vector path skips the (unit) table in 2-D
@@ -1145,6 +1146,85 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
     });
 }
 
+// ---- the autotuner's file cache: one text line per problem class,
+// "<key> <shape flags> <scatterers per item / default x 1000> <ms>"
+namespace {
+std::mutex g_tune_mu;
+std::string g_tune_path;
+int64_t g_tune_hits = 0;
+
+int ilog2(int64_t v)
+{
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// The problem class of a plan: path, sub-elements, elements, transmits, y,
+// elevation table, 2-D, the caller's flags other than the shape ones, and the
+// binary logarithms of the bins, scatterers and phantoms.
+std::string tune_key(const FwdPlan& F, int32_t flags)
+{
+    const Common& C = F.C;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "simus%d/%s/M%d/N%d/T%d/y%d/tab%d/2d%d/fl%d/b%d/s%d/p%d", SIMUS_VERSION,
+                  F.use_mt ? "mt" : "vec", C.P.M, C.P.N, C.n_tx, C.has_y ? 1 : 0, C.table ? 1 : 0,
+                  C.P.dim2 ? 1 : 0, flags, ilog2(std::max(C.B.n_bins, 1)),
+                  ilog2(std::max<int64_t>(C.ph.total, 1)), ilog2(std::max(C.ph.n, 1)));
+    return buf;
+}
+
+// The last line of the cache file for `key`, if any (false if the file does
+// not exist or holds no such line).  Caller holds g_tune_mu.
+bool tune_lookup(const std::string& key, int32_t* shape_flags, int32_t* mult_permille)
+{
+    FILE* f = std::fopen(g_tune_path.c_str(), "r");
+    if (!f) return false;
+    bool found = false;
+    char line[512], k[300];
+    while (std::fgets(line, sizeof line, f)) {
+        int32_t fl = 0, mu = 0;
+        double ms = 0;
+        if (std::sscanf(line, "%299s %d %d %lf", k, &fl, &mu, &ms) == 4 && key == k && mu > 0) {
+            *shape_flags = fl;
+            *mult_permille = mu;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+// Appends one line (written whole); caller holds g_tune_mu.
+void tune_store(const std::string& key, int32_t shape_flags, int32_t mult_permille, double ms)
+{
+    FILE* f = std::fopen(g_tune_path.c_str(), "a");
+    if (!f) throw Error{SIMUS_EINVAL, "cannot append to the autotuner cache " + g_tune_path};
+    char line[512];
+    const int n = std::snprintf(line, sizeof line, "%s %d %d %.4f\n", key.c_str(), shape_flags, mult_permille, ms);
+    const bool ok = n > 0 && std::fwrite(line, 1, (size_t)n, f) == (size_t)n;
+    if (std::fclose(f) != 0 || !ok) throw Error{SIMUS_EINVAL, "cannot append to the autotuner cache " + g_tune_path};
+}
+}  // namespace
+
+int simus_tune_cache(const char* path)
+{
+    return guarded([&] {
+        if (path && std::strlen(path) > 4095) throw Error{SIMUS_EINVAL, "cache path longer than 4095 bytes"};
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_path = path ? path : "";
+    });
+}
+
+int64_t simus_tune_cache_hits(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_hits;
+}
+
 int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, const float* z,
                            const float* refl, float* rf, void* hip_stream, int64_t* tile_scat,
                            int32_t* flags)
@@ -1187,23 +1267,65 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
             upload(F);
             return F;
         };
-        // candidates: the tile shape of the default rule and, where it differs,
-        // the alternative one (SIMUS_FLAG_ALT_SHAPE); 0.5x .. 2x the
-        // default scatterers per item; on the vector path with and without
-        // the persistent launch
-        const int64_t base = plan->F.slice;
-        std::vector<int32_t> shapes = {plan->opt.flags & ~SIMUS_FLAG_ALT_SHAPE};
+        // candidates: the distinct tile shapes of the default rule and of
+        // SIMUS_FLAG_ALT_SHAPE and SIMUS_FLAG_EIGHT_BIN (kernel, element
+        // slots, transmit columns, bins per item); 0.5x .. 2x the default
+        // scatterers per item (0.5x, 1x, 2x on the matrix-core path, whose
+        // runs are long); on the vector path with and without the persistent
+        // launch
+        // scatterers per item are tried, and cached, as multiples of the
+        // default rule's count for the plan's flags
+        const int64_t base = [&] {
+            simus_options o = plan->opt;
+            o.tile_scat = 0;
+            return make_fwd_plan(Common(plan->F.C), &o, dl, ap, true).slice;
+        }();
+        const int32_t shape_bits = SIMUS_FLAG_ALT_SHAPE | SIMUS_FLAG_EIGHT_BIN;
+        std::vector<int32_t> shapes;
+        std::vector<SynthConfig> seen;
+        std::vector<bool> seen_mt;
+        for (const int32_t bits : {0, SIMUS_FLAG_ALT_SHAPE, SIMUS_FLAG_EIGHT_BIN, shape_bits}) {
+            simus_options o = plan->opt;
+            o.flags = (o.flags & ~shape_bits) | bits;
+            const FwdPlan Fo = make_fwd_plan(Common(plan->F.C), &o, dl, ap, true);
+            bool dup = false;
+            for (size_t i = 0; i < seen.size(); ++i) {
+                const SynthConfig& q = seen[i];
+                dup = dup || (seen_mt[i] == Fo.use_mt && q.ne == Fo.cfg.ne && q.tt == Fo.cfg.tt &&
+                              q.jt == Fo.cfg.jt && q.bs == Fo.cfg.bs && q.nx == Fo.cfg.nx &&
+                              q.groups == Fo.cfg.groups && q.pair == Fo.cfg.pair && q.wt == Fo.cfg.wt);
+            }
+            if (dup) continue;
+            seen.push_back(Fo.cfg);
+            seen_mt.push_back(Fo.use_mt);
+            shapes.push_back(o.flags);
+        }
+        // a choice stored for this problem class
+        const int32_t user_flags = plan->opt.flags & ~(shape_bits | SIMUS_FLAG_STATIC);
+        const std::string key = tune_key(plan->F, user_flags);
         {
-            simus_options w = plan->opt, n = plan->opt;
-            w.flags &= ~SIMUS_FLAG_ALT_SHAPE;
-            n.flags |= SIMUS_FLAG_ALT_SHAPE;
-            const FwdPlan Fw = make_fwd_plan(Common(plan->F.C), &w, dl, ap, true);
-            const FwdPlan Fn = make_fwd_plan(Common(plan->F.C), &n, dl, ap, true);
-            if (Fn.cfg.tt != Fw.cfg.tt || Fn.use_mt != Fw.use_mt) shapes.push_back(n.flags);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            int32_t cf = 0, mu = 0;
+            if (!g_tune_path.empty() && tune_lookup(key, &cf, &mu)) {
+                simus_options o = plan->opt;
+                o.flags = user_flags | (cf & (shape_bits | SIMUS_FLAG_STATIC));
+                o.tile_scat = (int32_t)std::min<int64_t>(
+                    std::max<int64_t>(1, std::llround(base * (mu / 1000.0))), int64_t(1) << 30);
+                FwdPlan F = make_fwd_plan(Common(plan->F.C), &o, dl, ap, true);
+                o.tile_scat = (int32_t)F.slice;
+                upload(F);
+                plan->F = std::move(F);
+                plan->opt = o;
+                ++g_tune_hits;
+                if (tile_scat) *tile_scat = o.tile_scat;
+                if (flags) *flags = o.flags;
+                return;
+            }
         }
         std::vector<simus_options> cands;
         for (const int32_t shape_flags : shapes)
             for (double m : {0.5, 1.0, 1.5, 2.0}) {
+                if (plan->F.use_mt && m == 1.5) continue;
                 for (int persist = 0; persist < 2; ++persist) {
                     if (plan->F.use_mt && !persist) continue;   // always persistent there
                     simus_options o = plan->opt;
@@ -1268,6 +1390,11 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
         plan->opt = best;
         if (tile_scat) *tile_scat = best.tile_scat;
         if (flags) *flags = best.flags;
+        std::lock_guard<std::mutex> lk_cache(g_tune_mu);
+        if (!g_tune_path.empty())
+            tune_store(key, best.flags & (shape_bits | SIMUS_FLAG_STATIC),
+                       (int32_t)std::llround(1000.0 * (double)best.tile_scat / (double)std::max<int64_t>(base, 1)),
+                       best_ms);
     });
 }
 

@@ -215,7 +215,7 @@ hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t 
 bool mt_supported(int M, int N, int n_tx);
 // alt: the alternative group width (16 instead of 32 transmit columns for
 // 128 element slots, 64 instead of 32 for 64), which the autotuner tries
-SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt = false);
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt = false, bool eight = false);
 SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 // inv_j2: the partials are of j G terms (both synthesis paths) and are

@@ -37,12 +37,15 @@ namespace simus {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Receive sums of the eight-bin kernel: (Re, Im) pairs.  The three-product
-// form needs 24 more registers per lane and then spills (29 dwords): 16
-// transmits x 11 items of 4 uneven phantoms, quarter size, 329 vs 312 ms.
+// Receive sums of the eight-bin kernel with 128 element slots: (Re, Im)
+// pairs.  The three-product form needs 24 more registers per lane and then
+// spills (29 dwords): 16 transmits x 11 items of 4 uneven phantoms, quarter
+// size, 329 vs 312 ms.  With 64 slots the three products fit (155 VGPRs):
+// 64-element phased array, 16 transmits, 40k scatterers 5.20 vs 5.66 ms.
 #ifndef MQ_NX
 #define MQ_NX 2
 #endif
+constexpr int MQ_NX64 = 3;
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
 {
@@ -605,7 +608,7 @@ struct MtShape {
     int ne, ntp, jt, nx;
 };
 
-static MtShape mt_shape(int N, int n_tx, bool alt)
+static MtShape mt_shape(int N, int n_tx, bool alt, bool eight)
 {
     // 64 element slots, 6 bins per item: above 32 transmits, groups of 64
     // transmit columns where they pad no more than groups of 32 (40k
@@ -617,14 +620,20 @@ static MtShape mt_shape(int N, int n_tx, bool alt)
     // alternative: 16 columns.  Up to 16 transmits: the eight-bin kernel
     // (curved array, 11 transmits, quarter of the uneven 16-phantom batch:
     // 312 vs 398 ms; 5 transmits, 100k scatterers: 47.3 vs 62.0 ms), whose
-    // alternative is the four-bin one.
+    // alternative is the four-bin one.  With 64 element slots and up to 16
+    // transmits, the eight-bin kernel too (64-element phased array, 16
+    // transmits, 40k scatterers: 5.20 vs 10.39 ms with 32 columns and 6 bins;
+    // 64-element linear array, 8 transmits, 100k scatterers: 20.5 vs 36.8 ms).
+    // More than 16 transmits with SIMUS_FLAG_EIGHT_BIN: the eight-bin kernel
+    // over groups of 16 columns.
+    const bool few = n_tx <= 16;
+    if ((few && !alt) || (!few && eight)) return {N <= 64 ? 64 : 128, 1, 8, N <= 64 ? MQ_NX64 : MQ_NX};
     if (N <= 64) {
         const bool wide = (n_tx + 63) / 64 * 64 == (n_tx + 31) / 32 * 32;
         if (n_tx > 32 && wide != alt) return {64, 4, 6, 2};
         return {64, 2, 6, 3};
     }
-    if (n_tx <= 16 && !alt) return {128, 1, 8, MQ_NX};
-    if (n_tx <= 16 || alt) return {128, 1, 4, 3};
+    if (few || alt) return {128, 1, 4, 3};
     return {128, 2, 4, 2};
 }
 
@@ -650,9 +659,9 @@ bool mt_supported(int M, int N, int n_tx)
     return n_tx >= 4 && N >= 1 && N <= 128 && (nu == 1 || nu == 2) && M == nu * N;
 }
 
-SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt)
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool eight)
 {
-    const MtShape sh = mt_shape(N, n_tx, alt);
+    const MtShape sh = mt_shape(N, n_tx, alt, eight);
     SynthConfig c{};
     c.bs = 512;
     c.groups = 1;
@@ -660,7 +669,7 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt)
     c.tt = 16 * sh.ntp;                       // transmits per group
     c.jt = sh.jt;
     c.nx = sh.nx;
-    c.wt = sh.ne == 128 && sh.ntp == 1 && sh.jt == 8;
+    c.wt = sh.ntp == 1 && sh.jt == 8;
     c.sc = 16;
     c.pair = M == 2 * N;
     c.has_y = has_y;
@@ -679,8 +688,10 @@ static SynthKernel mq_kernel_nuv(const SynthConfig& c)
 
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
-    if (c.wt && c.ne == 128 && c.tt == 16 && c.jt == 8)
+    if (c.wt && c.ne == 128 && c.tt == 16 && c.jt == 8 && c.nx == MQ_NX)
         return c.pair ? mq_kernel_nuv<128, MQ_NX, 2>(c) : mq_kernel_nuv<128, MQ_NX, 1>(c);
+    if (c.wt && c.ne == 64 && c.tt == 16 && c.jt == 8 && c.nx == MQ_NX64)
+        return c.pair ? mq_kernel_nuv<64, MQ_NX64, 2>(c) : mq_kernel_nuv<64, MQ_NX64, 1>(c);
     if (c.ne == 128 && c.tt == 16) return mt_kernel_shape<128, 1, 4, 3>(c);
     if (c.ne == 128 && c.tt == 32) return mt_kernel_shape<128, 2, 4, 2>(c);
     if (c.ne == 64 && c.tt == 32) return mt_kernel_shape<64, 2, 6, 3>(c);

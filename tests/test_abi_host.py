@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol(L):
     missing = [s for s in sorted(declared) if not hasattr(lib, s)]
     assert not missing, missing
     assert set(L.EXPORTS) == declared
-    assert lib.simus_version() == 200
+    assert lib.simus_version() == 201
 
 
 @pytest.mark.parametrize("name,scale", [("pw32_s200", 1.0), ("pw128_s50k", 0.01),
@@ -88,7 +88,7 @@ def test_invalid_probe_rejected(L, field, value, code):
 
 
 @pytest.mark.parametrize("field,value", [("fs", 1e6), ("spectral_eps", 1.5), ("nfft", 1001),
-                                         ("nu", -2), ("n_cycles", 0.0), ("flags", 64),
+                                         ("nu", -2), ("n_cycles", 0.0), ("flags", 128),
                                          ("flags", -1)])
 def test_invalid_options_rejected(L, field, value):
     w = _base()
@@ -310,3 +310,17 @@ def test_gaussian_set_validation(L):
         with pytest.raises(L.SimusError) as ei:
             _grid_call(L, options=dict(w["options"], gauss=gset))
         assert ei.value.code == -1
+
+
+def test_tune_cache_arguments():
+    """The autotuner's cache takes a path (copied), None or "" to switch it
+    off, and refuses paths over 4095 bytes; its hit counter starts at zero
+    in a process that never tuned."""
+    import paper_2102_02738_amd as S
+    from paper_2102_02738_amd._lib import SimusError
+    assert S.tune_cache_hits() == 0
+    S.tune_cache("/tmp/simus_tune_cache_test.txt")
+    S.tune_cache("")
+    S.tune_cache(None)
+    with pytest.raises(SimusError, match="EINVAL"):
+        S.tune_cache("a" * 4096)

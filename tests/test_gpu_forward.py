@@ -350,14 +350,16 @@ def test_coarse_grid_general_half_sinc(S, orc):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("n_tx,n_el,nu", [(21, 100, 0), (11, 128, 0), (40, 48, 0), (5, 200, 0), (6, 64, 3)])
+@pytest.mark.parametrize("n_tx,n_el,nu", [(21, 100, 0), (11, 128, 0), (11, 48, 0), (40, 48, 0), (5, 200, 0),
+                                         (6, 64, 3)])
 def test_alt_tile_shape(S, orc, n_tx, n_el, nu):
     """The alternative tile shape (SIMUS_FLAG_ALT_SHAPE: matrix-core groups
     of 16 instead of 32 transmit columns for 100 elements, four instead of
-    eight bins per item for 128 elements and 11 transmits, 64 instead of
-    32 columns for 48 elements; on the vector path pairs instead of single
-    transmits for 5, single instead of pairs for 6) matches the oracle and
-    the default shape to rounding order."""
+    eight bins per item for 128 elements and 11 transmits, 32 columns and
+    six bins instead of 16 and eight for 48 elements and 11 transmits, 64
+    instead of 32 columns for 48 elements and 40 transmits; on the vector
+    path pairs instead of single transmits for 5, single instead of pairs
+    for 6) matches the oracle and the default shape to rounding order."""
     from paper_2102_02738_amd import inputs
     w = inputs.workload("pw32_s200", scale=0.3)
     w["probe"] = inputs.linear_probe(n_el)
@@ -368,6 +370,26 @@ def test_alt_tile_shape(S, orc, n_tx, n_el, nu):
     _, rf0, _ = _run(S, w)
     ref = _oracle_rf(orc, w, g, data)
     print(n_tx, "tx", n_el, "el alternative shape rel L2", rel_l2(rf, ref), "vs default", rel_l2(rf, rf0))
+    assert rel_l2(rf, ref) <= TOL
+    assert rel_l2(rf, rf0) <= 1e-5
+
+
+@pytest.mark.parametrize("n_tx,n_el,nu", [(21, 128, 0), (24, 48, 0), (40, 100, 1)])
+def test_eight_bin_flag(S, orc, n_tx, n_el, nu):
+    """SIMUS_FLAG_EIGHT_BIN: more than 16 transmits on the eight-bin kernel,
+    over two or three groups of 16 columns (the last one ragged), with 128
+    and 64 element slots, matches the oracle and the default shape to
+    rounding order."""
+    from paper_2102_02738_amd import inputs
+    w = inputs.workload("pw32_s200", scale=0.3)
+    w["probe"] = inputs.linear_probe(n_el)
+    w["options"]["nu"] = nu
+    w["delays"] = inputs.plane_wave_delays(w["probe"], np.linspace(-12, 12, n_tx))
+    w["apod"] = np.random.default_rng(n_tx + 1).uniform(0.2, 1.0, w["delays"].shape).astype(np.float32)
+    g, rf, data = _run(S, w, flags=S.FLAG_EIGHT_BIN)
+    _, rf0, _ = _run(S, w)
+    ref = _oracle_rf(orc, w, g, data)
+    print(n_tx, "tx", n_el, "el eight-bin rel L2", rel_l2(rf, ref), "vs default", rel_l2(rf, rf0))
     assert rel_l2(rf, ref) <= TOL
     assert rel_l2(rf, rf0) <= 1e-5
 

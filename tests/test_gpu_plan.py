@@ -159,3 +159,36 @@ def test_autotune_keeps_results(S, path):
     print(path, "rel L2 vs default shape", e)
     assert e <= 1e-5
     plan.close()
+
+
+def test_autotune_cache(S, tmp_path):
+    """With a cache file, the first autotune of a problem class appends one
+    line; a second plan of the class takes the stored choice without timing
+    (one more cache hit, no new line) and gives simus_rf's results for it,
+    bit for bit."""
+    import torch
+    w = _convex_uneven(7)
+    g, o, (dx, dy, dz, dR), (_, _, _, _, off) = _prep(S, w)
+    path = tmp_path / "tune.txt"
+    S.tune_cache(str(path))
+    try:
+        plan = S.rf_plan(w["probe"], w["medium"], o, w["delays"], w["apod"], offsets=off)
+        ch = plan.autotune(dx, None, dz, dR, g["n_t"])
+        plan.close()
+        lines = path.read_text().splitlines()
+        print("cache:", lines)
+        assert len(lines) == 1 and lines[0].startswith("simus")
+        hits = S.tune_cache_hits()
+        plan2 = S.rf_plan(w["probe"], w["medium"], o, w["delays"], w["apod"], offsets=off)
+        ch2 = plan2.autotune(dx, None, dz, dR, g["n_t"])
+        assert S.tune_cache_hits() == hits + 1
+        assert ch2 == ch
+        assert len(path.read_text().splitlines()) == 1
+        ref = S.rf(w["probe"], w["medium"], dict(o, **ch2), w["delays"], w["apod"], dx, None, dz, dR,
+                   offsets=off)
+        got = plan2.rf(dx, None, dz, dR, g["n_t"])
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        plan2.close()
+    finally:
+        S.tune_cache(None)
