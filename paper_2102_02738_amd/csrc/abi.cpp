@@ -711,13 +711,19 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     const int64_t target = use_mt ? 4000 : 3000;
     int64_t rb = (int64_t(std::max(C.B.n_bins, 1)) * n_sb + target - 1) / target;
     rb = std::max<int64_t>(rb, cfg.jt);
+    // k_adjoint_mq reads its columns (16 KiB per bin) from a table in global
+    // memory: ranges of at most 96 bins, drawn range by range, keep the
+    // table's part that resident blocks share within an XCD's L2 (5 plane
+    // waves, 100k scatterers: 87.5 ms with 384-bin ranges drawn slice by
+    // slice, 83.3 range by range, 82.8 with 96-bin ranges, 83.3 with 64)
+    if (use_mt && cfg.wl) rb = std::min<int64_t>(rb, 96);
     rb = (rb + cfg.jt - 1) / cfg.jt * cfg.jt;
     const int range_bins = (int)std::min<int64_t>(rb, std::max(C.B.n_bins, 1));
     const int n_ranges = (std::max(C.B.n_bins, 1) + range_bins - 1) / range_bins;
     std::vector<AdjItem> items;
-    for (int p = 0; p < n_ph; ++p)
-        for (int64_t s0 = C.ph.off[p]; s0 < C.ph.off[p + 1]; s0 += slice)
-            for (int r = 0; r < n_ranges; ++r)
+    for (int r = 0; r < n_ranges; ++r)
+        for (int p = 0; p < n_ph; ++p)
+            for (int64_t s0 = C.ph.off[p]; s0 < C.ph.off[p + 1]; s0 += slice)
                 items.push_back(AdjItem{p, (int32_t)s0,
                                         (int32_t)std::min<int64_t>(s0 + slice, C.ph.off[p + 1]), r});
     const int n_items = (int)items.size();
@@ -731,6 +737,8 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     const size_t o_lam =
         dv.add(sizeof(float2) * size_t(n_ph) * std::max(C.B.n_bins, 1) * n_tx * N);
     const size_t o_part = dv.add(sizeof(float4) * size_t(n_ranges) * C.ph.total);
+    const bool wl = use_mt && cfg.wl;
+    const size_t o_wl = wl ? dv.add(sizeof(float2) * size_t(n_ph) * std::max(C.B.n_bins, 1) * 128 * 16) : 0;
 
     Arena& a = arena_for(st, dv.size, up.size);
     fill_upload(a.host, L, C, delays, apod);
@@ -752,6 +760,7 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     A.W = at<float2>(d, L.W);
     A.lam = at<float2>(d, o_lam);
     A.pw = at<float2>(d, L.pw);
+    A.WL = wl ? at<float2>(d, o_wl) : nullptr;
     A.items = at<AdjItem>(d, o_it);
     A.part = at<float4>(d, o_part);
     A.dtab = C.table ? at<float4>(d, L.dt) : nullptr;
@@ -769,6 +778,9 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
         std::fprintf(stderr, "[simus] adjoint S=%lld T=%d bins=%d TT=%d JT=%d range=%d items=%d y=%d table=%d mfma=%d\n",
                      (long long)C.ph.total, n_tx, C.B.n_bins, cfg.tt, cfg.jt, range_bins, n_items,
                      (int)C.has_y, (int)C.table, (int)use_mt);
+    if (wl)
+        hip_check(launch_wltable(at<float2>(d, o_wl), A.W, A.lam, n_ph, C.B.n_bins, n_tx, N, st),
+                  "adjoint column table launch");
     hip_check(timed(K_ADJ, st, [&] {
                   return use_mt ? launch_adjoint_mt(cfg, A, n_items, st) : launch_adjoint(cfg, A, n_items, st);
               }),

@@ -1,4 +1,6 @@
-// Adjoint on the matrix cores (up to 16 transmits, N <= 128, nu in {1, 2}).
+// Adjoint on the matrix cores (up to 16 transmits, N <= 128, nu in {1, 2}):
+// k_adjoint_mq for up to 8 transmits (four bins per step, below), k_adjoint_mt
+// for 9 to 16.
 //
 // The gradients of the misfit need, per scatterer s, bin j and transmit t,
 // four sums over the sub-elements n (see adjoint.hip):
@@ -16,8 +18,8 @@
 // accumulated per bin, so each (sub-element, scatterer) pair is set up once
 // per 32 bins and stepped across them (green.hpp).
 //
-// Block: 512 threads (8 waves), chunks of 8 scatterers (32 rows, two row
-// tiles); work item = (phantom, scatterer slice, bin range).  With y = 0 the
+// k_adjoint_mt.  Block: 512 threads (8 waves), chunks of 8 scatterers (32
+// rows, two row tiles); work item = (phantom, scatterer slice, bin range).  With y = 0 the
 // rows dB/dy are zero, and for nu = 2 a chunk takes 10 scatterers of three
 // rows instead (30 of the 32 rows), so that one GEMM serves 25 % more
 // scatterers.
@@ -282,6 +284,242 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
     }
 }
 
+// Up to 8 transmits: four bins per step, two barriers per step.  The
+// columns [W_0 .. W_7 | Lam_0 .. Lam_7] come from a padded table WL in global
+// memory ([phantom][bin][element slot][16], zero outside N x n_tx), read by
+// each wave a batch of k-steps ahead, so nothing is staged or reduced in LDS:
+//   P1  every thread: the gradient terms of the previous step's four bins
+//       (lane = (scatterer, transmit, bin)), then G and its gradient for its
+//       pairs and four bins -> element sums, rows (s, L), one LDS tile per bin;
+//   P2  wave w: the GEMM of bin w / 2, row tile w % 2, over all 128 element
+//       slots (three products per complex product) -> V of that bin in LDS.
+// Lanes of a scatterer are summed once per chunk (transmits and bins, in a
+// fixed order).
+template <int NUV, bool HASY, bool TABLE>
+__global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
+{
+    constexpr int NB = 512;
+    constexpr int NE = 128;                 // element slots
+    constexpr int MS = NE * NUV;            // sub-element slots
+    constexpr int SCH = adj_mt_chunk(NUV, HASY);   // scatterers per chunk
+    constexpr int NL = SCH == 10 ? 3 : 4;   // rows per scatterer: B, dB/dx, dB/dz(, dB/dy)
+    constexpr int ROWS = 32;                // SCH NL rows, the rest zero
+    constexpr int LST = NE + 2;             // row stride of the element sums
+    constexpr int TG = 8;                   // transmits
+    constexpr int NC = 2 * TG;              // columns: W, then Lam
+    constexpr int VST = NC + 2;             // row stride of V
+    constexpr int JB = 4;                   // bins per step: wave = (bin, row tile)
+    constexpr int JS = 32;                  // bins per set-up, a multiple of JB
+    constexpr int KS = NE / 4;              // k-steps (all element slots)
+    constexpr int KB = 8;                   // k-steps of columns loaded ahead
+    constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
+    constexpr int NX = HASY ? 3 : 2;        // coordinates: X, Z (, Y)
+    constexpr int GL = SCH * TG * JB;       // gradient lanes
+    static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(PPT * (NB / MS) == SCH, "synthesis threads must cover the chunk");
+    static_assert(SCH * NL <= ROWS && GL <= NB && JS % JB == 0 && KS % KB == 0, "shape");
+    static_assert(TG * JB == 32, "a scatterer's gradient lanes are 32 consecutive lanes");
+
+    __shared__ float4 s_sc[SCH];
+    __shared__ float2 s_L[JB][ROWS * LST];
+    __shared__ float2 s_V[JB][ROWS * VST];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int gi = lane & 15, gk = lane >> 4;
+    // synthesis role
+    const int n = tid % MS, sp = tid / MS;
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    // GEMM role: bin wj of the step, row tile rt
+    const int wj = wave >> 1, rt = wave & 1;
+    // gradient role: lane = (scatterer gs, transmit gt, bin gj)
+    const bool glane = tid < GL;
+    const int gs = tid >> 5, gt = (tid >> 2) & 7, gj = tid & 3;
+
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
+    // rows that no scatterer fills stay zero
+    for (int i = tid; i < JB * ROWS * LST; i += NB) (&s_L[0][0])[i] = make_float2(0.f, 0.f);
+
+    const AdjItem it = A.items[blockIdx.x];
+    const int b_begin = it.range * A.range_bins;
+    const int b_end = min(A.n_bins, b_begin + A.range_bins);
+    const int p = it.phantom;
+    const float2* wl_p = A.WL + (int64_t)p * A.n_bins * NE * NC;
+
+    for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+        if (tid < SCH) {
+            const int s = s0 + tid;
+            float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding
+            if (s < it.s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], 0.f);
+            s_sc[tid] = v;
+        }
+        __syncthreads();
+        float gR = 0.f, gX[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) gX[i] = 0.f;
+
+        // gradient terms of the step's bin j0 + gj for lane (gs, gt)
+        auto gradient = [&](int j0) {
+            const int jb = j0 + gj;
+            if (!glane || jb >= b_end) return;
+            const float2 pw = A.pw[jb];
+            const float2* V = s_V[gj];
+            const float2 a = V[gs * NL * VST + gt], b = V[gs * NL * VST + TG + gt];
+            gR += cmul(pw, cmul(a, b)).x;
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                const float2 da = V[(gs * NL + 1 + i) * VST + gt], db = V[(gs * NL + 1 + i) * VST + TG + gt];
+                gX[i] += cmul(pw, cfma(da, b, cmul(a, db))).x;
+            }
+        };
+        bool pend = false;                     // uniform: a step awaits its gradient terms
+        int pend_j0 = 0;
+        for (int jb0 = b_begin; jb0 < b_end; jb0 += JS) {
+            Geo g[PPT];
+            GeoD D[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const float4 v = s_sc[sp * PPT + k];
+                g[k] = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0, &D[k]);
+                if (!active) g[k].E = make_float2(0.f, 0.f);
+            }
+            const int nb = min(JS, b_end - jb0);
+            for (int jq = 0; jq < nb; jq += JB) {
+                // ---- P1: the previous step's gradient terms; G and its
+                //      gradient for the step's four bins (past the range's
+                //      end they are stepped but not used)
+                if (pend) gradient(pend_j0);
+#pragma unroll 1
+                for (int jj = 0; jj < JB; ++jj) {
+                    const float jf = (float)(A.j_lo + jb0 + jq + jj);
+                    const float inv_j = rcp_fast(jf);
+                    float2* sL = s_L[jj];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const int s = sp * PPT + k;
+                        float2 dG[NX];
+                        float2 v[NX + 1];
+                        v[0] = green_grad_next<HASY, TABLE, NX>(A.K, g[k], D[k], jf, inv_j, s_tab, P, dG);
+#pragma unroll
+                        for (int i = 0; i < NX; ++i) v[1 + i] = dG[i];
+#pragma unroll
+                        for (int L = 0; L <= NX; ++L) {
+                            float2 b = v[L];
+                            if (NUV == 2) {
+                                b.x += dpp_xor1(b.x);
+                                b.y += dpp_xor1(b.y);
+                            }
+                            sL[(s * NL + L) * LST + (NUV == 2 ? (n >> 1) : n)] = b;
+                        }
+                    }
+                }
+                // this wave's columns: WL[p][bin][e = 4 k + gk][col = gi],
+                // k-step stride 64; the first batch in flight across the barrier
+                const int jbw = min(jb0 + jq + wj, b_end - 1);
+                const float2* wg = wl_p + ((int64_t)jbw * NE + gk) * NC + gi;
+                float2 wa[2][KB];
+#pragma unroll
+                for (int k = 0; k < KB; ++k) wa[0][k] = wg[64 * k];
+                __syncthreads();
+                // ---- P2: GEMM of bin wj, row tile rt: rows rt 16 + gi,
+                //      k = element 4 k + gk, columns gi
+                {
+                    const float2* lp = s_L[wj] + (rt * 16 + gi) * LST + gk;
+                    floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+#pragma unroll
+                    for (int k0 = 0; k0 < KS; k0 += KB) {
+                        const int cur = (k0 / KB) & 1;
+                        if (k0 + KB < KS) {
+#pragma unroll
+                            for (int k = 0; k < KB; ++k) wa[cur ^ 1][k] = wg[64 * (k0 + KB + k)];
+                        }
+                        float2 la[KB];
+#pragma unroll
+                        for (int k = 0; k < KB; ++k) la[k] = lp[4 * (k0 + k)];
+#pragma unroll
+                        for (int k = 0; k < KB; ++k) {
+                            p1 = mfma_a(la[k].x, wa[cur][k].x, p1);
+                            p2 = mfma_a(la[k].y, wa[cur][k].y, p2);
+                            p3 = mfma_a(la[k].x + la[k].y, wa[cur][k].x + wa[cur][k].y, p3);
+                        }
+                    }
+                    // D[row][col]: row rt 16 + 4 gk + v, col gi
+                    float2* V = s_V[wj];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        V[(rt * 16 + 4 * gk + v) * VST + gi] = make_float2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+                }
+                __syncthreads();
+                pend = true;
+                pend_j0 = jb0 + jq;
+            }
+        }
+        if (pend) gradient(pend_j0);
+        // sum a scatterer's 32 lanes (transmits, bins); layout [range][s] of
+        // (dR, dX, dY, dZ) before the R_s factor
+        if (glane) {
+#pragma unroll
+            for (int m = 1; m < 32; m <<= 1) {
+                gR += __shfl_xor(gR, m);
+#pragma unroll
+                for (int i = 0; i < NX; ++i) gX[i] += __shfl_xor(gX[i], m);
+            }
+            const int s = s0 + gs;
+            if ((tid & 31) == 0 && s < it.s_end)
+                A.part[(int64_t)it.range * A.S_total + s] = make_float4(gR, gX[0], HASY ? gX[NX - 1] : 0.f, gX[1]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int NUV>
+static hipError_t launch_adj_mq_nuv(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
+{
+    if (c.has_y)
+        hipLaunchKernelGGL((k_adjoint_mq<NUV, true, false>), dim3(n_items), dim3(512), 0, st, a);
+    else if (c.table)
+        hipLaunchKernelGGL((k_adjoint_mq<NUV, false, true>), dim3(n_items), dim3(512), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_adjoint_mq<NUV, false, false>), dim3(n_items), dim3(512), 0, st, a);
+    return hipGetLastError();
+}
+
+// WL[p][bin][e][16] for k_adjoint_mq: W of transmit c (c < 8), then Lam of
+// transmit c - 8, zero outside N x n_tx.
+__global__ void k_wltable(float2* __restrict__ WL, const float2* __restrict__ W,
+                          const float2* __restrict__ lam, int n_ph, int n_bins, int n_tx, int N)
+{
+    const int64_t total = (int64_t)n_ph * n_bins * 128 * 16;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i & 15);
+        const int e = (int)((i >> 4) & 127);
+        const int64_t pb = i >> 11;                 // p n_bins + bin
+        const int b = (int)(pb % n_bins);
+        const int t = c & 7;
+        float2 w = make_float2(0.f, 0.f);
+        if (e < N && t < n_tx)
+            w = c < 8 ? W[((int64_t)b * n_tx + t) * N + e] : lam[(pb * n_tx + t) * N + e];
+        WL[i] = w;
+    }
+}
+
+hipError_t launch_wltable(float2* WL, const float2* W, const float2* lam, int n_ph, int n_bins, int n_tx,
+                          int N, hipStream_t st)
+{
+    const int64_t total = (int64_t)n_ph * n_bins * 128 * 16;
+    if (total == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_wltable, dim3(grid), dim3(256), 0, st, WL, W, lam, n_ph, n_bins, n_tx, N);
+    return hipGetLastError();
+}
+
 template <int NTC, int NUV>
 static hipError_t launch_adj_mt_nuv(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
 {
@@ -305,6 +543,7 @@ AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y)
     AdjConfig c{};
     c.mfma = true;
     c.tt = n_tx <= 8 ? 8 : 16;
+    c.wl = n_tx <= 8;         // k_adjoint_mq, columns from the padded table WL
     c.jt = 32;                // bins per set-up (JS), the bin-range granule
     c.pair = M == 2 * N;
     // scatterers per item, a multiple of the chunk
@@ -316,7 +555,10 @@ AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y)
 hipError_t launch_adjoint_mt(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    if (c.tt == 8) return c.pair ? launch_adj_mt_nuv<1, 2>(c, a, n_items, st) : launch_adj_mt_nuv<1, 1>(c, a, n_items, st);
+    if (c.tt == 8 && c.wl) {
+        if (!a.WL) return hipErrorInvalidValue;
+        return c.pair ? launch_adj_mq_nuv<2>(c, a, n_items, st) : launch_adj_mq_nuv<1>(c, a, n_items, st);
+    }
     if (c.tt == 16) return c.pair ? launch_adj_mt_nuv<2, 2>(c, a, n_items, st) : launch_adj_mt_nuv<2, 1>(c, a, n_items, st);
     return hipErrorInvalidValue;
 }

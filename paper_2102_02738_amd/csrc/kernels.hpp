@@ -138,6 +138,7 @@ struct AdjArgs {
     const float2* W;     // [n_bins][n_tx][N]
     const float2* lam;   // [n_ph][n_bins][n_tx][N] residual spectra
     const float2* pw;    // [n_bins] S_P S_T
+    const float2* WL;    // k_adjoint_mq: [n_ph][n_bins][128][16] W of 8 transmits, then Lam, zero-padded
     const AdjItem* items;
     float4* part;        // [n_ranges][S_total] (dR, dX, dY, dZ) before R_s
     const float4* dtab;
@@ -155,6 +156,7 @@ struct AdjConfig {
     bool table;
     bool mfma;       // matrix-core adjoint (adjoint_mfma.hip)
     bool pair;       // matrix-core path: nu = 2
+    bool wl;         // matrix-core path: k_adjoint_mq (four bins per step, columns from WL)
 };
 
 AdjConfig adjoint_config(int n_tx, bool has_y);
@@ -162,6 +164,8 @@ hipError_t launch_adjoint(const AdjConfig& c, const AdjArgs& a, int n_items, hip
 bool adjoint_mt_supported(int M, int N, int n_tx);
 AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y);
 hipError_t launch_adjoint_mt(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st);
+hipError_t launch_wltable(float2* WL, const float2* W, const float2* lam, int n_ph, int n_bins, int n_tx,
+                          int N, hipStream_t st);
 hipError_t launch_adjoint_reduce(const float4* part, int n_ranges, int64_t S, const float* refl,
                                  float* dR, float* dX, float* dY, float* dZ, hipStream_t st);
 hipError_t launch_dft_t(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo, int nfft,
