@@ -58,17 +58,23 @@ G_EVAL_SLOTS = 28.0
 #   Element sum of Eqs. 32-33 for nu = 2: one complex add per element, i.e.
 #   one slot per G term ((nu - 1) / nu * 2 in general).
 #   The two contractions (Eq. 29 over elements after the sum, Eq. 33): two
-#   complex MACs per (element, scatterer, transmit, bin): 3 real MACs each on
-#   the matrix cores (three-product form), 4 FMAs each on the VALU.
-CMAC_SLOTS_MFMA = 3.0
+#   complex MACs per (element, scatterer, transmit, bin).  On the matrix
+#   cores each takes 12 bf16 MACs: 4 real products in FP32 accuracy, as three
+#   products of bf16 high and low parts each; at the dense bf16 peak (2.5
+#   PFLOP/s = 1.25e15 MAC/s) a bf16 MAC costs 78.64e12 / 1.25e15 = 0.0629
+#   slots, so 0.755 slots per complex MAC.  With FP32 matrix-core products
+#   (three-product form, SIMUS_FLAG_FP32_PRODUCTS): 3 slots; on the VALU: 4.
+BF16_MAC_SLOTS = 256 * 128 * 2.4e9 / 1.25e15
+CMAC_SLOTS_MFMA = 12 * BF16_MAC_SLOTS
+CMAC_SLOTS_MFMA_FP32 = 3.0
 CMAC_SLOTS_VALU = 4.0
 
 
-def alg_slots(S: float, M: int, N: int, T: int, n_bins: int, nu: int, mfma: bool) -> float:
+def alg_slots(S: float, M: int, N: int, T: int, n_bins: int, nu: int, mfma: bool, cmac: float = None) -> float:
     """Algorithmic issue slots of one synthesis over S scatterers (see above)."""
     g_terms = S * M * n_bins
     per_g = G_EVAL_SLOTS + 2.0 * (nu - 1) / nu
-    cm = CMAC_SLOTS_MFMA if mfma else CMAC_SLOTS_VALU
+    cm = cmac if cmac is not None else CMAC_SLOTS_MFMA if mfma else CMAC_SLOTS_VALU
     return g_terms * per_g + 2.0 * S * N * T * n_bins * cm + 2.0 * S * T * n_bins
 
 
@@ -92,9 +98,9 @@ TRANS_ISSUE_COST = 4.0         # a transcendental issues at 1/4 of the FP32 rate
 VALU_PEAK = 256 * 128 * 2.4e9
 MFMA_FP32_PEAK = 157.3e12      # dense FP32 matrix-core FLOP/s
 # The main workload's synthesis kernel (one group of 16 transmit columns,
-# 128 element slots, 8 bins per item, nu = 2, (Re, Im) receive sums, y = 0,
+# 128 element slots, 8 bins per item, split-bf16 products, nu = 2, y = 0,
 # elevation table).
-MT_KERNEL = "k_synth_mq<128, 2, 2, false, true>"
+MT_KERNEL = "k_synth_mb<128, 2, false, true>"
 
 
 def kernel_sources_digest(files) -> str:
@@ -302,8 +308,8 @@ def extra_uneven_phantoms(steps: int) -> dict:
                 rel_l2_graph_vs_plain=_rel(first, plain))
 
 
-AUTOTUNE_SPACE = ("the distinct tile shapes of the default rule, SIMUS_FLAG_ALT_SHAPE and "
-                  "SIMUS_FLAG_EIGHT_BIN (kernel, element slots, transmit columns, bins per item) x "
+AUTOTUNE_SPACE = ("the distinct tile shapes of the default rule and SIMUS_FLAG_ALT_SHAPE (kernel, "
+                  "element slots, transmit columns, bins per item) x "
                   "scatterers per item 0.5/1/2x the default (vector path also 1.5x, and static or "
                   "persistent launch)")
 
@@ -684,6 +690,7 @@ def main():
     # time less the other kernels' (measured eagerly; < 0.1 %)
     synth_ms = graph_ms - (kern["wtable"] + kern["finalize"] + kern["idft"])
     alg = alg_slots(c.S, M, c.N, c.T, c.g["n_bins"], c.g["nu"], True)
+    alg_fp32 = alg_slots(c.S, M, c.N, c.T, c.g["n_bins"], c.g["nu"], True, CMAC_SLOTS_MFMA_FP32)
     achieved = alg / (synth_ms * 1e-3)
     counters = profile_summary("synth_mt_cvx128x11_p16_counters.txt", MT_SOURCES)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="TOP/s",
@@ -694,9 +701,12 @@ def main():
                 work_per_unit=dict(g_term=G_EVAL_SLOTS + 2.0 * (c.g["nu"] - 1) / c.g["nu"],
                                    cmac_pair=2 * CMAC_SLOTS_MFMA),
                 work_def="algorithmic lane issue slots: Green's term by recurrence and table, element "
-                         "sum, two complex MACs per (element, scatterer, transmit, bin) on the matrix "
-                         "cores (3 real MACs each); no set-up, padding or address arithmetic",
-                op_def="lane issue slot: full-rate FP32 VALU 1, transcendental 4, FP32 MFMA lane-MAC 1",
+                         "sum, two complex MACs per (element, scatterer, transmit, bin) on the bf16 "
+                         "matrix cores (12 bf16 MACs each: FP32 accuracy from high and low parts); no "
+                         "set-up, padding or address arithmetic",
+                op_def="lane issue slot: full-rate FP32 VALU 1, transcendental 4, bf16 MFMA MAC "
+                       "78.64e12 / 1.25e15 = 0.0629 (dense peaks)",
+                frac_fp32_products_model=alg_fp32 / (synth_ms * 1e-3) / VALU_PEAK,
                 issue_counters={k: float(counters[k]) for k in ("valu_busy", "mfma_busy", "issue_busy")
                                 if k in counters} or None)
     res = {

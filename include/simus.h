@@ -142,25 +142,23 @@ typedef struct {
 #define SIMUS_FLAG_STATIC       16   /* vector path: one block per work item instead of the
                                         persistent launch (the matrix-core path is always
                                         persistent); results are bitwise the same */
-#define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape.  Matrix-core path, at
-                                        most 16 transmits: four bins per work item instead of
-                                        eight (more than 64 elements), or groups of 32
-                                        transmit columns and six bins instead of 16 and eight
-                                        (64 or fewer); more transmits: groups of 16 columns
-                                        instead of 32 (more than 64 elements), or the other of
-                                        32 and 64 columns (64 or fewer elements, more than 32
-                                        transmits; the default takes 64 where it pads no
-                                        more).  Vector path: single transmits instead of
-                                        pairs, or pairs instead of single transmits.  The
+#define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape.  Matrix-core path: the
+                                        kernels that set a pair up every four bins (more
+                                        than 64 elements; groups of 16 transmit columns up
+                                        to 16 transmits, else 32) or six bins (64 or fewer;
+                                        groups of 32 columns, or 64 above 32 transmits where
+                                        they pad no more) instead of every eight bins over
+                                        groups of 16.  Vector path: single transmits instead
+                                        of pairs, or pairs instead of single transmits.  The
                                         autotuner tries it.  simus_rf_backward: the other of
                                         its two kernels (matrix-core or vector) where both
                                         apply.  The results agree to rounding order */
-#define SIMUS_FLAG_EIGHT_BIN    64   /* matrix-core path, more than 16 transmits: the kernel
-                                        that synthesises eight bins per pair set-up, over
-                                        groups of 16 transmit columns (the default for at most
-                                        16 transmits; ignored there and on the vector path).
-                                        The autotuner tries it.  Results agree to rounding
-                                        order */
+#define SIMUS_FLAG_FP32_PRODUCTS 64  /* matrix-core path, default shape: the two
+                                        contractions with FP32 matrix-core products instead
+                                        of products of operands split into bf16 high and low
+                                        parts (three bf16 products per real product, FP32
+                                        accumulation: about 2^-16 of each product, 5e-6
+                                        relative L2 on RF against the FP32 products) */
 /* Other bits of options.flags are rejected with SIMUS_EINVAL. */
 
 /* Frequency grid of one call. */
@@ -338,8 +336,8 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y,
  * multiple of the default rule's count, time).  With a path set, the
  * autotuner first looks up the plan's problem class in the file: the path
  * (matrix-core or vector), sub-elements, elements, transmits, y given or
- * not, elevation table, 2-D, the flags other than SIMUS_FLAG_ALT_SHAPE,
- * SIMUS_FLAG_EIGHT_BIN and SIMUS_FLAG_STATIC, the library version, and the
+ * not, elevation table, 2-D, the flags other than SIMUS_FLAG_ALT_SHAPE and
+ * SIMUS_FLAG_STATIC, the library version, and the
  * binary logarithms of the bins, scatterers and phantoms.  If a line is
  * there (the last one counts), it applies that choice without timing;
  * otherwise it tunes as described above and appends its choice.  Lines are

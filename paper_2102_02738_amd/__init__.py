@@ -14,7 +14,7 @@ call raises if the library has not been built.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import SimusError, FLAG_NO_MFMA, FLAG_PERSISTENT, FLAG_NO_DELTA_TABLE, FLAG_2D, FLAG_STATIC, FLAG_ALT_SHAPE, FLAG_EIGHT_BIN  # noqa: F401
+from ._lib import SimusError, FLAG_NO_MFMA, FLAG_PERSISTENT, FLAG_NO_DELTA_TABLE, FLAG_2D, FLAG_STATIC, FLAG_ALT_SHAPE, FLAG_FP32_PRODUCTS  # noqa: F401
 
 __all__ = ["grid", "rf", "rf_spectrum", "spectrum_to_rf", "rf_backward", "pfield", "pfield_nf",
            "RFPlan", "rf_plan", "SimusRF", "simus_rf_autograd", "release_workspace", "tune_cache",

@@ -23,7 +23,7 @@ FLAG_NO_DELTA_TABLE = 4
 FLAG_2D = 8
 FLAG_STATIC = 16
 FLAG_ALT_SHAPE = 32
-FLAG_EIGHT_BIN = 64
+FLAG_FP32_PRODUCTS = 64
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["simus_version", "simus_last_error", "simus_rf_grid", "simus_rf_spectrum", "simus_rf",

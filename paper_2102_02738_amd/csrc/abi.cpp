@@ -497,8 +497,8 @@ FwdPlan make_fwd_plan(Common C, const simus_options* opt, const double* delays, 
                Cc.K.sinc_per_bin < SINC_TAYLOR_LIMIT;
     SynthConfig& cfg = F.cfg;
     const bool alt = (opt->flags & SIMUS_FLAG_ALT_SHAPE) != 0;
-    const bool eight = (opt->flags & SIMUS_FLAG_EIGHT_BIN) != 0;
-    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y, alt, eight)
+    const bool fp32 = (opt->flags & SIMUS_FLAG_FP32_PRODUCTS) != 0;
+    cfg = F.use_mt ? mt_config(M, N, n_tx, Cc.has_y, alt, fp32)
                    : synth_config(M, Cc.P.nu, n_tx, Cc.has_y, Cc.table && !Cc.P.dim2, alt);
     cfg.table = Cc.table;
     cfg.dim2 = Cc.P.dim2;   // the vector path skips the (unit) table in 2-D
@@ -607,7 +607,7 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
         hip_check(timed(K_WTABLE, st, [&] {
                       return launch_wtable_mt(at<float2>(d, F.o_wt), at<double>(d, F.L.dl), at<float>(d, F.L.ap),
                                               C.B.n_bins, n_tx, N, cfg.ne, (n_tx + 15) / 16, C.B.j_lo,
-                                              C.B.df, st);
+                                              C.B.df, cfg.bf, st);
                   }),
                   "matrix-core weight table launch");
     SynthArgs A{};
@@ -1280,8 +1280,8 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
             return F;
         };
         // candidates: the distinct tile shapes of the default rule and of
-        // SIMUS_FLAG_ALT_SHAPE and SIMUS_FLAG_EIGHT_BIN (kernel, element
-        // slots, transmit columns, bins per item); 0.5x .. 2x the default
+        // SIMUS_FLAG_ALT_SHAPE (kernel, element slots, transmit columns, bins
+        // per item, product precision); 0.5x .. 2x the default
         // scatterers per item (0.5x, 1x, 2x on the matrix-core path, whose
         // runs are long); on the vector path with and without the persistent
         // launch
@@ -1292,11 +1292,11 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
             o.tile_scat = 0;
             return make_fwd_plan(Common(plan->F.C), &o, dl, ap, true).slice;
         }();
-        const int32_t shape_bits = SIMUS_FLAG_ALT_SHAPE | SIMUS_FLAG_EIGHT_BIN;
+        const int32_t shape_bits = SIMUS_FLAG_ALT_SHAPE;
         std::vector<int32_t> shapes;
         std::vector<SynthConfig> seen;
         std::vector<bool> seen_mt;
-        for (const int32_t bits : {0, SIMUS_FLAG_ALT_SHAPE, SIMUS_FLAG_EIGHT_BIN, shape_bits}) {
+        for (const int32_t bits : {0, SIMUS_FLAG_ALT_SHAPE}) {
             simus_options o = plan->opt;
             o.flags = (o.flags & ~shape_bits) | bits;
             const FwdPlan Fo = make_fwd_plan(Common(plan->F.C), &o, dl, ap, true);
@@ -1305,7 +1305,8 @@ int simus_rf_plan_autotune(simus_rf_plan plan, const float* x, const float* y, c
                 const SynthConfig& q = seen[i];
                 dup = dup || (seen_mt[i] == Fo.use_mt && q.ne == Fo.cfg.ne && q.tt == Fo.cfg.tt &&
                               q.jt == Fo.cfg.jt && q.bs == Fo.cfg.bs && q.nx == Fo.cfg.nx &&
-                              q.groups == Fo.cfg.groups && q.pair == Fo.cfg.pair && q.wt == Fo.cfg.wt);
+                              q.groups == Fo.cfg.groups && q.pair == Fo.cfg.pair && q.wt == Fo.cfg.wt &&
+                              q.bf == Fo.cfg.bf);
             }
             if (dup) continue;
             seen.push_back(Fo.cfg);

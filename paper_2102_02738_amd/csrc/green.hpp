@@ -25,6 +25,18 @@
 
 namespace simus {
 
+// bf16 pairs packed in a 32-bit word, round to nearest even: (a | b << 16)
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+// the float values of a packed pair's low and high halves
+__device__ __forceinline__ float bf16_lo(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
 // sin(2 pi x), cos(2 pi x) with x in turns (hardware v_sin/v_cos, |x| <= 256).
 __device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float cos_turns(float x) { return __builtin_amdgcn_cosf(x); }

@@ -41,17 +41,30 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
     return hipGetLastError();
 }
 
+// bf16 == false: float2 WT[bin][group][e][16 columns];
+// bf16 == true:  uint2  WT[bin][group][16 columns][e], the weight split into
+//   bf16 high and low parts, packed (Re, Im): x = (Re_h | Im_h << 16),
+//   y = (Re_l | Im_l << 16), with Re = Re_h + Re_l to 16 significant bits.
 __global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ delays,
                             const float* __restrict__ apod, int n_bins, int n_tx, int N, int ne,
-                            int n_tg, int j_lo, double df)
+                            int n_tg, int j_lo, double df, bool bf16)
 {
     const int64_t total = (int64_t)n_bins * n_tg * ne * 16;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % 16);
-        int64_t r = i / 16;
-        const int e = (int)(r % ne);
-        r /= ne;
+        int c, e;
+        int64_t r;
+        if (bf16) {
+            e = (int)(i % ne);
+            r = i / ne;
+            c = (int)(r % 16);
+            r /= 16;
+        } else {
+            c = (int)(i % 16);
+            r = i / 16;
+            e = (int)(r % ne);
+            r /= ne;
+        }
         const int g = (int)(r % n_tg);
         const int b = (int)(r / n_tg);
         const int t = 16 * g + c;
@@ -63,18 +76,24 @@ __global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ 
             const float a = apod ? apod[te] : 1.f;
             w = make_float2(a * cos_turns(ph), a * sin_turns(ph));
         }
-        WT[i] = w;
+        if (bf16) {
+            const uint32_t h = pack_bf16(w.x, w.y);
+            const uint32_t l = pack_bf16(w.x - bf16_lo(h), w.y - bf16_hi(h));
+            WT[i] = make_float2(__uint_as_float(h), __uint_as_float(l));
+        } else {
+            WT[i] = w;
+        }
     }
 }
 
 hipError_t launch_wtable_mt(float2* WT, const double* delays, const float* apod, int n_bins, int n_tx,
-                            int N, int ne, int n_tg, int j_lo, double df, hipStream_t st)
+                            int N, int ne, int n_tg, int j_lo, double df, bool bf16, hipStream_t st)
 {
     const int64_t total = (int64_t)n_bins * n_tg * ne * 16;
     if (total == 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_wtable_mt, dim3(grid), dim3(256), 0, st, WT, delays, apod, n_bins, n_tx, N, ne,
-                       n_tg, j_lo, df);
+                       n_tg, j_lo, df, bf16);
     return hipGetLastError();
 }
 

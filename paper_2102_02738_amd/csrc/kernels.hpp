@@ -117,6 +117,7 @@ struct SynthConfig {
     int ne;      // matrix-core path: element slots (64 or 128)
     int nx;      // matrix-core path: receive sums per column tile (2 or 3)
     bool wt;     // matrix-core path: the kernel reads the padded weight table WT
+    bool bf;     // matrix-core path: products in bf16 high/low parts (k_synth_mb)
     int grid;    // blocks launched (persistent: resident blocks)
 };
 
@@ -209,7 +210,7 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 // transmit 16 g + c and element e at bin b, zero for e >= N or a transmit
 // past n_tx; ne element slots, n_tg groups of 16 columns.
 hipError_t launch_wtable_mt(float2* WT, const double* delays, const float* apod, int n_bins, int n_tx,
-                            int N, int ne, int n_tg, int j_lo, double df, hipStream_t st);
+                            int N, int ne, int n_tg, int j_lo, double df, bool bf16, hipStream_t st);
 // The synthesis kernel instance a configuration runs (nullptr if none), for
 // the launch and for occupancy queries (blocks of cfg.bs threads, or 512 on
 // the matrix-core path).
@@ -219,7 +220,7 @@ hipError_t launch_synth(const SynthConfig& cfg, const SynthArgs& a, hipStream_t 
 bool mt_supported(int M, int N, int n_tx);
 // alt: the alternative group width (16 instead of 32 transmit columns for
 // 128 element slots, 64 instead of 32 for 64), which the autotuner tries
-SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt = false, bool eight = false);
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt = false, bool fp32 = false);
 SynthKernel synth_mt_kernel(const SynthConfig& cfg);
 hipError_t launch_synth_mt(const SynthConfig& cfg, const SynthArgs& a, hipStream_t st);
 // inv_j2: the partials are of j G terms (both synthesis paths) and are

@@ -67,7 +67,7 @@ Probe make_probe(const simus_probe* p, const simus_medium* m, const simus_option
     require(o->tile_scat >= 0, "options.tile_scat must be >= 0");
     require((o->flags & ~(SIMUS_FLAG_NO_MFMA | SIMUS_FLAG_PERSISTENT | SIMUS_FLAG_NO_DELTA_TABLE |
                           SIMUS_FLAG_2D | SIMUS_FLAG_STATIC | SIMUS_FLAG_ALT_SHAPE |
-                          SIMUS_FLAG_EIGHT_BIN)) == 0,
+                          SIMUS_FLAG_FP32_PRODUCTS)) == 0,
             "options.flags has unknown bits");
 
     P.N = p->n_elements;

@@ -608,32 +608,31 @@ struct MtShape {
     int ne, ntp, jt, nx;
 };
 
-static MtShape mt_shape(int N, int n_tx, bool alt, bool eight)
+static MtShape mt_shape(int N, int n_tx, bool alt)
 {
-    // 64 element slots, 6 bins per item: above 32 transmits, groups of 64
-    // transmit columns where they pad no more than groups of 32 (40k
+    // Default: the eight-bin kernel over groups of 16 transmit columns, 64 or
+    // 128 element slots (products in split bf16, k_synth_mb; in FP32 with
+    // SIMUS_FLAG_FP32_PRODUCTS, k_synth_mq).  Measured against the four- and
+    // six-bin kernels (k_synth_mt), the alternative shape: curved array, 11
+    // transmits, a quarter of the uneven 16-phantom batch 255 ms (bf16) / 312
+    // (FP32) vs 398 with 4 bins; 5 plane waves, 100k scatterers 38.7 / 47.4
+    // vs 62.0; 21 plane waves, 200k scatterers 161 / 197 vs 188 (32 columns,
+    // 4 bins; 258 with 16 columns); 128 focused transmits on a 64-element
+    // array, 40k scatterers 30.7 / 38.6 vs 40.7 (64 columns, 6 bins);
+    // 64-element arrays with up to 16 transmits about half the time of 32
+    // columns and 6 bins.
+    if (!alt) return {N <= 64 ? 64 : 128, 1, 8, N <= 64 ? MQ_NX64 : MQ_NX};
+    // the alternative, k_synth_mt: 64 element slots, 6 bins per item, groups
+    // of 64 transmit columns where they pad no more than groups of 32 (40k
     // scatterers: 128 transmits 42.5 vs 44.7 ms with 32; 40 and 64 equal; 96
-    // transmits 41.9 vs 32.5 ms, so 32 there); the alternative takes the
-    // other width.  128 slots: 32 columns above 16 transmits (21 transmits,
-    // 200k scatterers: 215 vs 258 ms with 16; the eight-bin kernel over two
-    // groups of 16 columns: 197 vs 189 ms), 4 bins per item (5 spill);
-    // alternative: 16 columns.  Up to 16 transmits: the eight-bin kernel
-    // (curved array, 11 transmits, quarter of the uneven 16-phantom batch:
-    // 312 vs 398 ms; 5 transmits, 100k scatterers: 47.3 vs 62.0 ms), whose
-    // alternative is the four-bin one.  With 64 element slots and up to 16
-    // transmits, the eight-bin kernel too (64-element phased array, 16
-    // transmits, 40k scatterers: 5.20 vs 10.39 ms with 32 columns and 6 bins;
-    // 64-element linear array, 8 transmits, 100k scatterers: 20.5 vs 36.8 ms).
-    // More than 16 transmits with SIMUS_FLAG_EIGHT_BIN: the eight-bin kernel
-    // over groups of 16 columns.
-    const bool few = n_tx <= 16;
-    if ((few && !alt) || (!few && eight)) return {N <= 64 ? 64 : 128, 1, 8, N <= 64 ? MQ_NX64 : MQ_NX};
+    // transmits 41.9 vs 32.5 ms, so 32 there); 128 slots, 4 bins per item (5
+    // spill): 16 columns up to 16 transmits, else 32
     if (N <= 64) {
         const bool wide = (n_tx + 63) / 64 * 64 == (n_tx + 31) / 32 * 32;
-        if (n_tx > 32 && wide != alt) return {64, 4, 6, 2};
+        if (n_tx > 32 && wide) return {64, 4, 6, 2};
         return {64, 2, 6, 3};
     }
-    if (few || alt) return {128, 1, 4, 3};
+    if (n_tx <= 16) return {128, 1, 4, 3};
     return {128, 2, 4, 2};
 }
 
@@ -659,9 +658,9 @@ bool mt_supported(int M, int N, int n_tx)
     return n_tx >= 4 && N >= 1 && N <= 128 && (nu == 1 || nu == 2) && M == nu * N;
 }
 
-SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool eight)
+SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
 {
-    const MtShape sh = mt_shape(N, n_tx, alt, eight);
+    const MtShape sh = mt_shape(N, n_tx, alt);
     SynthConfig c{};
     c.bs = 512;
     c.groups = 1;
@@ -670,12 +669,264 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool eight)
     c.jt = sh.jt;
     c.nx = sh.nx;
     c.wt = sh.ntp == 1 && sh.jt == 8;
+    c.bf = c.wt && !fp32;
     c.sc = 16;
     c.pair = M == 2 * N;
     c.has_y = has_y;
     c.mfma = true;
     c.persistent = true;
     return c;
+}
+
+// The eight-bin kernel with its two GEMMs on bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Every operand x is split
+// into bf16 parts x = x_h + x_l (x_h = x rounded, x_l = x - x_h rounded), and
+// a product takes three bf16 products, x_h y_h + x_h y_l + x_l y_h: the
+// dropped x_l y_l and the rounding of x_l leave about 2^-16 of |x y|.  A
+// complex value (re, im) is stored as two packed words, (re_h, im_h) and
+// (re_l, im_l); a complex product's real part pairs (re, im) with (W_re,
+// -W_im) and its imaginary part with (W_im, W_re) along k, so each MFMA
+// contracts 16 complex values (K = 32):
+//   P1  element sums, split, into two LDS planes per bin (h and l);
+//   P2  wave w, bin w: a[s][t] = sum_e B[s][e] W[e][t], 8 (NE = 128) or 4
+//       k-steps of 16 elements, 6 MFMAs each; weights from the split table
+//       WT[bin][group][t][e] (uint2: h, l); c = R_s a, split, to LDS;
+//   P3  wave w, bin w ^ 4: X[e][t] += sum_s B[e][s] c[s][t], one k-step per
+//       element tile (16 scatterers), 6 MFMAs.
+// FP32 16x16x4 MFMAs contract 4 real values in 32 cycles, bf16 16x16x32 ones
+// 32 in about 16-20; per complex product this takes 6 x 2 bf16 products
+// instead of 3 (or 4) FP32 ones.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma_bf(u32x4 a, u32x4 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+// (re, im) -> (re, -im) and (im, re) of a packed pair
+__device__ __forceinline__ uint32_t bf_conj(uint32_t p) { return p ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t bf_swap(uint32_t p) { return (p >> 16) | (p << 16); }
+
+template <int NE, int NUV, bool HASY, bool TABLE>
+__global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
+{
+    constexpr int NB = 512;
+    constexpr int MS = NE * NUV;            // sub-element slots
+    constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
+    constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
+    constexpr int NSG = NB / MS;            // scatterer groups
+    constexpr int JT = 8;                   // bins per item: two per SIMD
+    constexpr int TPG = 16;                 // transmit columns
+    constexpr int BPS = NE + 4;             // row stride (words) of the element-sum planes
+    constexpr int CS = SCH + 2;             // row stride (uint2) of c[t][s]
+    constexpr int KS = NE / 16;             // transmit-GEMM k-steps (16 elements each)
+    constexpr int RXE = NE / 16;            // receive element tiles
+    static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
+    static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(PPT * NSG == SCH, "threads must cover the chunk");
+
+    __shared__ float4 s_sc[SCH];
+    __shared__ __align__(16) uint32_t s_Bh[JT][SCH * BPS];
+    __shared__ __align__(16) uint32_t s_Bl[JT][SCH * BPS];
+    __shared__ __align__(16) uint2 s_c[JT][TPG * CS];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int gi = lane & 15, gk = lane >> 4;      // MFMA lane roles: row/column, k block
+    const int btx = wave, brx = wave ^ 4;          // the wave's transmit and receive bins
+    const int n = tid % MS, sh = tid / MS;
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    const int n_tg = (A.n_tx + TPG - 1) / TPG;
+    const uint2* WTb = reinterpret_cast<const uint2*>(A.WT);
+
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
+
+    auto load_chunk = [&](int s0, int s_end) {
+        if (tid < SCH) {
+            const int s = s0 + tid;
+            float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
+            if (s < s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
+            s_sc[tid] = v;
+        }
+    };
+
+    if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+    __syncthreads();
+    int item = s_item;
+    while (item < A.n_items) {
+        const int id = A.order[item];          // costliest first
+        const Item it = A.items[id];
+        const int bt = it.tile & 0xffff, tg = it.tile >> 16;
+        const int jb0 = bt * JT;
+        const int nb = min(JT, A.n_bins - jb0);
+        // this wave's weights: WT[bin][tg][t = gi][e = 16 k + 4 gk .. + 3]
+        const int jbw = min(jb0 + btx, A.n_bins - 1);
+        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + gi) * NE + 4 * gk;
+
+        // receive sums of the wave's receive bin: element tiles x (Re, Im)
+        floatx4 X[RXE][2];
+#pragma unroll
+        for (int m = 0; m < RXE; ++m) X[m][0] = X[m][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        load_chunk(it.s_begin, it.s_end);
+        __syncthreads();
+        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+            // ---- P1: set-up, the element sums of the eight bins, split
+            {
+                Geo g[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const float4 v = s_sc[sh * PPT + k];
+                    g[k] = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+                    if (!active) g[k].E = make_float2(0.f, 0.f);
+                    if (TABLE) g[k].kap *= P.kscale;          // delta_fetch's argument
+                }
+#pragma unroll 1
+                for (int jj = 0; jj < JT; ++jj) {
+                    const float jf = (float)(A.j_lo + jb0 + jj);
+                    float2 G[PPT];
+                    if constexpr (TABLE) {
+                        DeltaFetch fch[2];
+                        fch[0] = delta_fetch(s_tab, P, jf * g[0].kap);
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) {
+                            if (k + 1 < PPT) fch[(k + 1) & 1] = delta_fetch(s_tab, P, jf * g[k + 1].kap);
+                            __builtin_amdgcn_sched_barrier(0);
+                            G[k] = green_next_fetched(g[k], fch[k & 1]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) G[k] = green_next<HASY, TABLE>(A.K, g[k], jf, 1.f, s_tab, P);
+                    }
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const int s = sh * PPT + k;
+                        float bx = G[k].x, by = G[k].y;
+                        if (NUV == 2) {
+                            bx += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bx), 0xB1, 0xF, 0xF, true));
+                            by += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(by), 0xB1, 0xF, 0xF, true));
+                        }
+                        const uint32_t h = pack_bf16(bx, by);
+                        const uint32_t l = pack_bf16(bx - bf16_lo(h), by - bf16_hi(h));
+                        const int e = NUV == 2 ? (n >> 1) : n;
+                        if (NUV == 2) {
+                            // the pair's even lane stores the high part, the odd one the low part
+                            uint32_t* plane = (n & 1) ? s_Bl[jj] : s_Bh[jj];
+                            plane[s * BPS + e] = (n & 1) ? l : h;
+                        } else {
+                            s_Bh[jj][s * BPS + e] = h;
+                            s_Bl[jj][s * BPS + e] = l;
+                        }
+                    }
+                }
+            }
+            // the wave's split weights of k-steps 0 .. KS - 1: 4 elements each
+            uint4 wr[KS][2];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
+                wr[k][0] = q[0];
+                wr[k][1] = q[1];
+            }
+            __syncthreads();
+            // ---- P2: transmit GEMM of bin btx: rows s = gi, columns t = gi,
+            //      k = (element 16 k + 4 gk + q, Re/Im)
+            {
+                const uint32_t* bh = s_Bh[btx] + gi * BPS + 4 * gk;
+                const uint32_t* bl = s_Bl[btx] + gi * BPS + 4 * gk;
+                floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const uint4 ah4 = *reinterpret_cast<const uint4*>(bh + 16 * k);
+                    const uint4 al4 = *reinterpret_cast<const uint4*>(bl + 16 * k);
+                    const u32x4 ah = {ah4.x, ah4.y, ah4.z, ah4.w}, al = {al4.x, al4.y, al4.z, al4.w};
+                    // weights of elements q = 0..3: (h, l) words
+                    const uint32_t wh[4] = {wr[k][0].x, wr[k][0].z, wr[k][1].x, wr[k][1].z};
+                    const uint32_t wl[4] = {wr[k][0].y, wr[k][0].w, wr[k][1].y, wr[k][1].w};
+                    const u32x4 rh = {bf_conj(wh[0]), bf_conj(wh[1]), bf_conj(wh[2]), bf_conj(wh[3])};
+                    const u32x4 rl = {bf_conj(wl[0]), bf_conj(wl[1]), bf_conj(wl[2]), bf_conj(wl[3])};
+                    const u32x4 ih = {bf_swap(wh[0]), bf_swap(wh[1]), bf_swap(wh[2]), bf_swap(wh[3])};
+                    const u32x4 il = {bf_swap(wl[0]), bf_swap(wl[1]), bf_swap(wl[2]), bf_swap(wl[3])};
+                    re = mfma_bf(ah, rh, re);
+                    re = mfma_bf(ah, rl, re);
+                    re = mfma_bf(al, rh, re);
+                    im = mfma_bf(ah, ih, im);
+                    im = mfma_bf(ah, il, im);
+                    im = mfma_bf(al, ih, im);
+                }
+                // D[row][col]: row s = 4 gk + v, col t = gi; c = R_s a, split
+                uint2* sc = s_c[btx];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int s = 4 * gk + v;
+                    const float R = s_sc[s].w;
+                    const float cx = R * re[v], cy = R * im[v];
+                    const uint32_t h = pack_bf16(cx, cy);
+                    sc[gi * CS + s] = make_uint2(h, pack_bf16(cx - bf16_lo(h), cy - bf16_hi(h)));
+                }
+            }
+            __syncthreads();
+            // ---- P3: receive GEMM of bin brx: rows e, columns t = gi,
+            //      k = (scatterer 4 gk + q, Re/Im); the next chunk's scatterers
+            {
+                const uint2* cp = s_c[brx] + gi * CS + 4 * gk;
+                const uint4 c01 = *reinterpret_cast<const uint4*>(cp);
+                const uint4 c23 = *reinterpret_cast<const uint4*>(cp + 2);
+                const uint32_t ch[4] = {c01.x, c01.z, c23.x, c23.z};
+                const uint32_t cl[4] = {c01.y, c01.w, c23.y, c23.w};
+                const u32x4 rh = {bf_conj(ch[0]), bf_conj(ch[1]), bf_conj(ch[2]), bf_conj(ch[3])};
+                const u32x4 rl = {bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
+                const u32x4 ih = {bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
+                const u32x4 il = {bf_swap(cl[0]), bf_swap(cl[1]), bf_swap(cl[2]), bf_swap(cl[3])};
+                const uint32_t* bh = s_Bh[brx] + 4 * gk * BPS + gi;
+                const uint32_t* bl = s_Bl[brx] + 4 * gk * BPS + gi;
+#pragma unroll
+                for (int m = 0; m < RXE; ++m) {
+                    const u32x4 ah = {bh[16 * m], bh[BPS + 16 * m], bh[2 * BPS + 16 * m], bh[3 * BPS + 16 * m]};
+                    const u32x4 al = {bl[16 * m], bl[BPS + 16 * m], bl[2 * BPS + 16 * m], bl[3 * BPS + 16 * m]};
+                    X[m][0] = mfma_bf(ah, rh, X[m][0]);
+                    X[m][0] = mfma_bf(ah, rl, X[m][0]);
+                    X[m][0] = mfma_bf(al, rh, X[m][0]);
+                    X[m][1] = mfma_bf(ah, ih, X[m][1]);
+                    X[m][1] = mfma_bf(ah, il, X[m][1]);
+                    X[m][1] = mfma_bf(al, ih, X[m][1]);
+                }
+            }
+            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end);
+            __syncthreads();
+        }
+        // per-element partials [item][JT][TPG][N] of the wave's receive bin;
+        // D[row][col]: row = element 16 m + 4 gk + v, col = transmit gi
+        if (brx < nb) {
+            float2* out = A.part + ((int64_t)id * JT + brx) * TPG * A.N;
+#pragma unroll
+            for (int m = 0; m < RXE; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int e = 16 * m + 4 * gk + v;
+                    if (e < A.N) out[(int64_t)gi * A.N + e] = make_float2(X[m][0][v], X[m][1][v]);
+                }
+        }
+        if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+        __syncthreads();
+        item = s_item;
+    }
+}
+
+template <int NE, int NUV>
+static SynthKernel mb_kernel_nuv(const SynthConfig& c)
+{
+    if (c.has_y) return k_synth_mb<NE, NUV, true, false>;
+    if (c.table) return k_synth_mb<NE, NUV, false, true>;
+    return k_synth_mb<NE, NUV, false, false>;
 }
 
 template <int NE, int NX, int NUV>
@@ -688,6 +939,10 @@ static SynthKernel mq_kernel_nuv(const SynthConfig& c)
 
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
+    if (c.bf && c.wt && c.tt == 16 && c.jt == 8) {
+        if (c.ne == 128) return c.pair ? mb_kernel_nuv<128, 2>(c) : mb_kernel_nuv<128, 1>(c);
+        if (c.ne == 64) return c.pair ? mb_kernel_nuv<64, 2>(c) : mb_kernel_nuv<64, 1>(c);
+    }
     if (c.wt && c.ne == 128 && c.tt == 16 && c.jt == 8 && c.nx == MQ_NX)
         return c.pair ? mq_kernel_nuv<128, MQ_NX, 2>(c) : mq_kernel_nuv<128, MQ_NX, 1>(c);
     if (c.wt && c.ne == 64 && c.tt == 16 && c.jt == 8 && c.nx == MQ_NX64)

@@ -157,7 +157,7 @@ def test_autotune_keeps_results(S, path):
     assert torch.equal(gr, ref)
     e = rel_l2(got.cpu().numpy(), first.cpu().numpy())
     print(path, "rel L2 vs default shape", e)
-    assert e <= 1e-5
+    assert e <= 3e-5     # shapes with FP32 or split-bf16 matrix-core products
     plan.close()
 
 
