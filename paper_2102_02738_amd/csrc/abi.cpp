@@ -703,6 +703,7 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
     const bool use_mt = mt_ok && (((opt->flags & SIMUS_FLAG_ALT_SHAPE) != 0) != mt_pref);
     AdjConfig cfg = use_mt ? adjoint_mt_config(C.P.M, N, n_tx, C.has_y) : adjoint_config(n_tx, C.has_y);
     cfg.table = C.table;
+    cfg.bf = cfg.wl && !(opt->flags & SIMUS_FLAG_FP32_PRODUCTS);
     // items: (phantom, scatterer slice, bin range); about 3000 items (matrix-core
     // path: 4000), bin ranges a multiple of the bin tile
     const int slice = cfg.scatterers;
@@ -779,7 +780,7 @@ void backward(const simus_probe* probe, const simus_medium* medium, const simus_
                      (long long)C.ph.total, n_tx, C.B.n_bins, cfg.tt, cfg.jt, range_bins, n_items,
                      (int)C.has_y, (int)C.table, (int)use_mt);
     if (wl)
-        hip_check(launch_wltable(at<float2>(d, o_wl), A.W, A.lam, n_ph, C.B.n_bins, n_tx, N, st),
+        hip_check(launch_wltable(at<float2>(d, o_wl), A.W, A.lam, n_ph, C.B.n_bins, n_tx, N, cfg.bf, st),
                   "adjoint column table launch");
     hip_check(timed(K_ADJ, st, [&] {
                   return use_mt ? launch_adjoint_mt(cfg, A, n_items, st) : launch_adjoint(cfg, A, n_items, st);

@@ -41,7 +41,6 @@
 
 namespace simus {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ floatx4 mfma_a(float a, float b, floatx4 c)
 {
@@ -286,16 +285,22 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
 
 // Up to 8 transmits: four bins per step, two barriers per step.  The
 // columns [W_0 .. W_7 | Lam_0 .. Lam_7] come from a padded table WL in global
-// memory ([phantom][bin][element slot][16], zero outside N x n_tx), read by
-// each wave a batch of k-steps ahead, so nothing is staged or reduced in LDS:
+// memory (zero outside N x n_tx), read by each wave ahead of its GEMM, so
+// nothing is staged or reduced in LDS:
 //   P1  every thread: the gradient terms of the previous step's four bins
 //       (lane = (scatterer, transmit, bin)), then G and its gradient for its
 //       pairs and four bins -> element sums, rows (s, L), one LDS tile per bin;
 //   P2  wave w: the GEMM of bin w / 2, row tile w % 2, over all 128 element
-//       slots (three products per complex product) -> V of that bin in LDS.
+//       slots -> V of that bin in LDS.
+// BF: the GEMM's products as three products of bf16 high and low parts
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation, about 2^-16 of each
+// product, as in k_synth_mb): the element sums are split into two LDS planes
+// of packed (re, im) words and the table holds WL[p][bin][col][e] as (h, l)
+// words; otherwise FP32 16x16x4 MFMAs with three products per complex
+// product and WL[p][bin][e][col] as float2.
 // Lanes of a scatterer are summed once per chunk (transmits and bins, in a
 // fixed order).
-template <int NUV, bool HASY, bool TABLE>
+template <int NUV, bool HASY, bool TABLE, bool BF>
 __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
 {
     constexpr int NB = 512;
@@ -304,24 +309,27 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
     constexpr int SCH = adj_mt_chunk(NUV, HASY);   // scatterers per chunk
     constexpr int NL = SCH == 10 ? 3 : 4;   // rows per scatterer: B, dB/dx, dB/dz(, dB/dy)
     constexpr int ROWS = 32;                // SCH NL rows, the rest zero
-    constexpr int LST = NE + 2;             // row stride of the element sums
+    constexpr int LST = BF ? NE + 4 : NE + 2;   // row stride of the element sums (words / float2)
     constexpr int TG = 8;                   // transmits
     constexpr int NC = 2 * TG;              // columns: W, then Lam
     constexpr int VST = NC + 2;             // row stride of V
     constexpr int JB = 4;                   // bins per step: wave = (bin, row tile)
     constexpr int JS = 32;                  // bins per set-up, a multiple of JB
-    constexpr int KS = NE / 4;              // k-steps (all element slots)
-    constexpr int KB = 8;                   // k-steps of columns loaded ahead
+    constexpr int KS = NE / 4;              // FP32 k-steps (4 elements)
+    constexpr int KB = 8;                   // FP32 k-steps of columns loaded ahead
+    constexpr int KSB = NE / 16;            // bf16 k-steps (16 elements)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int NX = HASY ? 3 : 2;        // coordinates: X, Z (, Y)
     constexpr int GL = SCH * TG * JB;       // gradient lanes
+    constexpr int NPL = BF ? 2 : 1;         // LDS planes of the element sums
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * (NB / MS) == SCH, "synthesis threads must cover the chunk");
     static_assert(SCH * NL <= ROWS && GL <= NB && JS % JB == 0 && KS % KB == 0, "shape");
     static_assert(TG * JB == 32, "a scatterer's gradient lanes are 32 consecutive lanes");
 
     __shared__ float4 s_sc[SCH];
-    __shared__ float2 s_L[JB][ROWS * LST];
+    // BF: planes [h, l] of packed words; else one plane of float2 (two words each)
+    __shared__ __align__(16) uint32_t s_L[JB][NPL][ROWS * LST * (BF ? 1 : 2)];
     __shared__ float2 s_V[JB][ROWS * VST];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
 
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
         P = *A.dpar;
     }
     // rows that no scatterer fills stay zero
-    for (int i = tid; i < JB * ROWS * LST; i += NB) (&s_L[0][0])[i] = make_float2(0.f, 0.f);
+    for (int i = tid; i < (int)(sizeof(s_L) / 4); i += NB) (&s_L[0][0][0])[i] = 0u;
 
     const AdjItem it = A.items[blockIdx.x];
     const int b_begin = it.range * A.range_bins;
@@ -399,7 +407,6 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
                 for (int jj = 0; jj < JB; ++jj) {
                     const float jf = (float)(A.j_lo + jb0 + jq + jj);
                     const float inv_j = rcp_fast(jf);
-                    float2* sL = s_L[jj];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
                         const int s = sp * PPT + k;
@@ -415,22 +422,73 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
                                 b.x += dpp_xor1(b.x);
                                 b.y += dpp_xor1(b.y);
                             }
-                            sL[(s * NL + L) * LST + (NUV == 2 ? (n >> 1) : n)] = b;
+                            const int e = NUV == 2 ? (n >> 1) : n;
+                            const int at = (s * NL + L) * LST + e;
+                            if constexpr (BF) {
+                                const uint32_t h = pack_bf16(b.x, b.y);
+                                const uint32_t l = pack_bf16(b.x - bf16_lo(h), b.y - bf16_hi(h));
+                                if (NUV == 2) {
+                                    // the pair's even lane stores the high part, the odd one the low part
+                                    s_L[jj][n & 1][at] = (n & 1) ? l : h;
+                                } else {
+                                    s_L[jj][0][at] = h;
+                                    s_L[jj][1][at] = l;
+                                }
+                            } else {
+                                reinterpret_cast<float2*>(s_L[jj][0])[at] = b;
+                            }
                         }
                     }
                 }
-                // this wave's columns: WL[p][bin][e = 4 k + gk][col = gi],
-                // k-step stride 64; the first batch in flight across the barrier
                 const int jbw = min(jb0 + jq + wj, b_end - 1);
-                const float2* wg = wl_p + ((int64_t)jbw * NE + gk) * NC + gi;
-                float2 wa[2][KB];
+                if constexpr (BF) {
+                    // this wave's split columns WL[p][bin][col = gi][e = 16 k + 4 gk .. + 3]
+                    const uint2* wg = reinterpret_cast<const uint2*>(wl_p) + ((int64_t)jbw * NC + gi) * NE + 4 * gk;
+                    uint4 wr[KSB][2];
 #pragma unroll
-                for (int k = 0; k < KB; ++k) wa[0][k] = wg[64 * k];
-                __syncthreads();
-                // ---- P2: GEMM of bin wj, row tile rt: rows rt 16 + gi,
-                //      k = element 4 k + gk, columns gi
-                {
-                    const float2* lp = s_L[wj] + (rt * 16 + gi) * LST + gk;
+                    for (int k = 0; k < KSB; ++k) {
+                        const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
+                        wr[k][0] = q[0];
+                        wr[k][1] = q[1];
+                    }
+                    __syncthreads();
+                    // ---- P2: GEMM of bin wj, row tile rt: rows rt 16 + gi,
+                    //      k = (element 16 k + 4 gk + q, Re/Im), columns gi
+                    const uint32_t* lh = s_L[wj][0] + (rt * 16 + gi) * LST + 4 * gk;
+                    const uint32_t* ll = s_L[wj][1] + (rt * 16 + gi) * LST + 4 * gk;
+                    floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
+#pragma unroll
+                    for (int k = 0; k < KSB; ++k) {
+                        const uint4 ah4 = *reinterpret_cast<const uint4*>(lh + 16 * k);
+                        const uint4 al4 = *reinterpret_cast<const uint4*>(ll + 16 * k);
+                        const u32x4 ah = {ah4.x, ah4.y, ah4.z, ah4.w}, al = {al4.x, al4.y, al4.z, al4.w};
+                        const uint32_t wh[4] = {wr[k][0].x, wr[k][0].z, wr[k][1].x, wr[k][1].z};
+                        const uint32_t wlo[4] = {wr[k][0].y, wr[k][0].w, wr[k][1].y, wr[k][1].w};
+                        const u32x4 rh = {bf_conj(wh[0]), bf_conj(wh[1]), bf_conj(wh[2]), bf_conj(wh[3])};
+                        const u32x4 rl = {bf_conj(wlo[0]), bf_conj(wlo[1]), bf_conj(wlo[2]), bf_conj(wlo[3])};
+                        const u32x4 ih = {bf_swap(wh[0]), bf_swap(wh[1]), bf_swap(wh[2]), bf_swap(wh[3])};
+                        const u32x4 il = {bf_swap(wlo[0]), bf_swap(wlo[1]), bf_swap(wlo[2]), bf_swap(wlo[3])};
+                        re = mfma_bf(ah, rh, re);
+                        re = mfma_bf(ah, rl, re);
+                        re = mfma_bf(al, rh, re);
+                        im = mfma_bf(ah, ih, im);
+                        im = mfma_bf(ah, il, im);
+                        im = mfma_bf(al, ih, im);
+                    }
+                    float2* V = s_V[wj];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) V[(rt * 16 + 4 * gk + v) * VST + gi] = make_float2(re[v], im[v]);
+                } else {
+                    // this wave's columns: WL[p][bin][e = 4 k + gk][col = gi],
+                    // k-step stride 64; the first batch in flight across the barrier
+                    const float2* wg = wl_p + ((int64_t)jbw * NE + gk) * NC + gi;
+                    float2 wa[2][KB];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) wa[0][k] = wg[64 * k];
+                    __syncthreads();
+                    // ---- P2: GEMM of bin wj, row tile rt: rows rt 16 + gi,
+                    //      k = element 4 k + gk, columns gi
+                    const float2* lp = reinterpret_cast<const float2*>(s_L[wj][0]) + (rt * 16 + gi) * LST + gk;
                     floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
 #pragma unroll
                     for (int k0 = 0; k0 < KS; k0 += KB) {
@@ -478,45 +536,52 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
     }
 }
 
-template <int NUV>
+template <int NUV, bool BF>
 static hipError_t launch_adj_mq_nuv(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st)
 {
     if (c.has_y)
-        hipLaunchKernelGGL((k_adjoint_mq<NUV, true, false>), dim3(n_items), dim3(512), 0, st, a);
+        hipLaunchKernelGGL((k_adjoint_mq<NUV, true, false, BF>), dim3(n_items), dim3(512), 0, st, a);
     else if (c.table)
-        hipLaunchKernelGGL((k_adjoint_mq<NUV, false, true>), dim3(n_items), dim3(512), 0, st, a);
+        hipLaunchKernelGGL((k_adjoint_mq<NUV, false, true, BF>), dim3(n_items), dim3(512), 0, st, a);
     else
-        hipLaunchKernelGGL((k_adjoint_mq<NUV, false, false>), dim3(n_items), dim3(512), 0, st, a);
+        hipLaunchKernelGGL((k_adjoint_mq<NUV, false, false, BF>), dim3(n_items), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 
-// WL[p][bin][e][16] for k_adjoint_mq: W of transmit c (c < 8), then Lam of
-// transmit c - 8, zero outside N x n_tx.
+// WL for k_adjoint_mq: column c is W of transmit c (c < 8), then Lam of
+// transmit c - 8, zero outside N x n_tx.  bf16 == false: float2
+// WL[p][bin][e][16]; bf16 == true: WL[p][bin][16][e] as packed split words
+// (x = (re_h, im_h), y = (re_l, im_l)).
 __global__ void k_wltable(float2* __restrict__ WL, const float2* __restrict__ W,
-                          const float2* __restrict__ lam, int n_ph, int n_bins, int n_tx, int N)
+                          const float2* __restrict__ lam, int n_ph, int n_bins, int n_tx, int N, bool bf16)
 {
     const int64_t total = (int64_t)n_ph * n_bins * 128 * 16;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i & 15);
-        const int e = (int)((i >> 4) & 127);
+        const int c = bf16 ? (int)((i >> 7) & 15) : (int)(i & 15);
+        const int e = bf16 ? (int)(i & 127) : (int)((i >> 4) & 127);
         const int64_t pb = i >> 11;                 // p n_bins + bin
         const int b = (int)(pb % n_bins);
         const int t = c & 7;
         float2 w = make_float2(0.f, 0.f);
         if (e < N && t < n_tx)
             w = c < 8 ? W[((int64_t)b * n_tx + t) * N + e] : lam[(pb * n_tx + t) * N + e];
+        if (bf16) {
+            const uint32_t h = pack_bf16(w.x, w.y);
+            const uint32_t l = pack_bf16(w.x - bf16_lo(h), w.y - bf16_hi(h));
+            w = make_float2(__uint_as_float(h), __uint_as_float(l));
+        }
         WL[i] = w;
     }
 }
 
 hipError_t launch_wltable(float2* WL, const float2* W, const float2* lam, int n_ph, int n_bins, int n_tx,
-                          int N, hipStream_t st)
+                          int N, bool bf16, hipStream_t st)
 {
     const int64_t total = (int64_t)n_ph * n_bins * 128 * 16;
     if (total == 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_wltable, dim3(grid), dim3(256), 0, st, WL, W, lam, n_ph, n_bins, n_tx, N);
+    hipLaunchKernelGGL(k_wltable, dim3(grid), dim3(256), 0, st, WL, W, lam, n_ph, n_bins, n_tx, N, bf16);
     return hipGetLastError();
 }
 
@@ -557,7 +622,8 @@ hipError_t launch_adjoint_mt(const AdjConfig& c, const AdjArgs& a, int n_items, 
     if (n_items <= 0) return hipSuccess;
     if (c.tt == 8 && c.wl) {
         if (!a.WL) return hipErrorInvalidValue;
-        return c.pair ? launch_adj_mq_nuv<2>(c, a, n_items, st) : launch_adj_mq_nuv<1>(c, a, n_items, st);
+        if (c.bf) return c.pair ? launch_adj_mq_nuv<2, true>(c, a, n_items, st) : launch_adj_mq_nuv<1, true>(c, a, n_items, st);
+        return c.pair ? launch_adj_mq_nuv<2, false>(c, a, n_items, st) : launch_adj_mq_nuv<1, false>(c, a, n_items, st);
     }
     if (c.tt == 16) return c.pair ? launch_adj_mt_nuv<2, 2>(c, a, n_items, st) : launch_adj_mt_nuv<2, 1>(c, a, n_items, st);
     return hipErrorInvalidValue;

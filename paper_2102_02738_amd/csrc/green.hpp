@@ -37,6 +37,20 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
 __device__ __forceinline__ float bf16_lo(uint32_t p) { return __uint_as_float(p << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
 
+// Matrix-core operands: 4 FP32 accumulators; 8 bf16 values as 4 packed words.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma_bf(u32x4 a, u32x4 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+// (re, im) -> (re, -im) and (im, re) of a packed pair
+__device__ __forceinline__ uint32_t bf_conj(uint32_t p) { return p ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t bf_swap(uint32_t p) { return (p >> 16) | (p << 16); }
+
 // sin(2 pi x), cos(2 pi x) with x in turns (hardware v_sin/v_cos, |x| <= 256).
 __device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float cos_turns(float x) { return __builtin_amdgcn_cosf(x); }

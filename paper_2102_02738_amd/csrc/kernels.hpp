@@ -158,6 +158,7 @@ struct AdjConfig {
     bool mfma;       // matrix-core adjoint (adjoint_mfma.hip)
     bool pair;       // matrix-core path: nu = 2
     bool wl;         // matrix-core path: k_adjoint_mq (four bins per step, columns from WL)
+    bool bf;         // k_adjoint_mq: products in bf16 high/low parts
 };
 
 AdjConfig adjoint_config(int n_tx, bool has_y);
@@ -166,7 +167,7 @@ bool adjoint_mt_supported(int M, int N, int n_tx);
 AdjConfig adjoint_mt_config(int M, int N, int n_tx, bool has_y);
 hipError_t launch_adjoint_mt(const AdjConfig& c, const AdjArgs& a, int n_items, hipStream_t st);
 hipError_t launch_wltable(float2* WL, const float2* W, const float2* lam, int n_ph, int n_bins, int n_tx,
-                          int N, hipStream_t st);
+                          int N, bool bf16, hipStream_t st);
 hipError_t launch_adjoint_reduce(const float4* part, int n_ranges, int64_t S, const float* refl,
                                  float* dR, float* dX, float* dY, float* dZ, hipStream_t st);
 hipError_t launch_dft_t(float2* lam, const float* rho, int64_t n_chan, int n_bins, int j_lo, int nfft,

@@ -35,7 +35,6 @@
 
 namespace simus {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // Receive sums of the eight-bin kernel with 128 element slots: (Re, Im)
 // pairs.  The three-product form needs 24 more registers per lane and then
@@ -696,17 +695,6 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
 // FP32 16x16x4 MFMAs contract 4 real values in 32 cycles, bf16 16x16x32 ones
 // 32 in about 16-20; per complex product this takes 6 x 2 bf16 products
 // instead of 3 (or 4) FP32 ones.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ floatx4 mfma_bf(u32x4 a, u32x4 b, floatx4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
-}
-// (re, im) -> (re, -im) and (im, re) of a packed pair
-__device__ __forceinline__ uint32_t bf_conj(uint32_t p) { return p ^ 0x80000000u; }
-__device__ __forceinline__ uint32_t bf_swap(uint32_t p) { return (p >> 16) | (p << 16); }
 
 template <int NE, int NUV, bool HASY, bool TABLE>
 __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)

@@ -72,8 +72,13 @@ def _check(got, ref, keys):
 
 
 # "alt" runs the other adjoint kernel (SIMUS_FLAG_ALT_SHAPE): these small
-# probes take the vector kernel by default, the matrix-core one with it
-PATHS = ["default", "alt"]
+# probes take the vector kernel by default, the matrix-core one with it (up
+# to 8 transmits with split-bf16 products; "alt_fp32" with FP32 products)
+PATHS = ["default", "alt", "alt_fp32"]
+
+
+def _path_flags(S, path):
+    return {"default": 0, "alt": S.FLAG_ALT_SHAPE, "alt_fp32": S.FLAG_ALT_SHAPE | S.FLAG_FP32_PRODUCTS}[path]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -82,8 +87,7 @@ PATHS = ["default", "alt"]
     (False, False, 1, 0)])
 def test_adjoint_matches_oracle_adjoint(S, orc, with_y, convex, baffle, flags, path):
     w = small(with_y=with_y, convex=convex, baffle=baffle)
-    if path == "alt":
-        flags |= S.FLAG_ALT_SHAPE
+    flags |= _path_flags(S, path)
     x, y, z, R, off = concat_phantoms(w["phantoms"])
     g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, y if with_y else None, z)
     rho = np.random.default_rng(7).standard_normal((1, len(w["delays"]), w["probe"]["n_elements"],
@@ -103,7 +107,7 @@ def test_adjoint_ragged_chunks(S, orc, n_scat, path):
     x, y, z, R, off = concat_phantoms(w["phantoms"])
     g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
     rho = np.random.default_rng(n_scat).standard_normal((1, 3, 8, g0["n_t"])).astype(np.float32)
-    g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    g, got = gpu_grads(S, w, rho, flags=_path_flags(S, path))
     ref = oracle_grads(orc, w, g, rho[0])
     _check(got, ref, ["refl", "x", "z"])
 
@@ -115,7 +119,7 @@ def test_adjoint_transmit_groups(S, orc, n_tx, path):
     x, y, z, R, off = concat_phantoms(w["phantoms"])
     g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
     rho = np.random.default_rng(n_tx).standard_normal((1, n_tx, 8, g0["n_t"])).astype(np.float32)
-    g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    g, got = gpu_grads(S, w, rho, flags=_path_flags(S, path))
     ref = oracle_grads(orc, w, g, rho[0])
     _check(got, ref, ["refl", "x", "z"])
 
@@ -231,7 +235,7 @@ def test_adjoint_single_scatterer(S, orc, path):
     x, y, z, R, off = concat_phantoms(w["phantoms"])
     g0 = S.grid(w["probe"], w["medium"], w["options"], w["delays"], x, None, z)
     rho = np.random.default_rng(5).standard_normal((1, 3, 8, g0["n_t"])).astype(np.float32)
-    g, got = gpu_grads(S, w, rho, flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    g, got = gpu_grads(S, w, rho, flags=_path_flags(S, path))
     ref = oracle_grads(orc, w, g, rho[0])
     _check(got, ref, ["refl", "x", "z"])
 
@@ -259,7 +263,7 @@ def test_adjoint_out_of_domain_scatterers(S, path):
     w = small(n_tx=3, n_scat=40, seed=13)
     ph = w["phantoms"][0]
     g = S.grid(w["probe"], w["medium"], w["options"], w["delays"], ph["x"], None, ph["z"])
-    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"], flags=S.FLAG_ALT_SHAPE if path == "alt" else 0)
+    o = dict(w["options"], nfft=g["nfft"], n_t=g["n_t"], flags=_path_flags(S, path))
     rng = np.random.default_rng(14)
     xo = np.concatenate([ph["x"], rng.uniform(-3e-3, 3e-3, 10)]).astype(np.float32)
     zo = np.concatenate([ph["z"], -rng.uniform(0, 2e-3, 10)]).astype(np.float32)
