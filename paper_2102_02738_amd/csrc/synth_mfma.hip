@@ -759,6 +759,20 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
         const int jbw = min(jb0 + btx, A.n_bins - 1);
         const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + gi) * NE + 4 * gk;
 
+        // the wave's split weights are the same for every chunk of the item:
+        // those of the first KH k-steps stay in registers (all of them for 64
+        // element slots; the first half for 128, where all would spill 72
+        // dwords; none with y, which then spills 19): 128 focused transmits
+        // on a 64-element array 30.7 -> 26.3 ms, a quarter of the uneven
+        // 16-phantom batch 255.7 -> 251.2 ms
+        constexpr int KH = NE == 64 ? KS : HASY ? 0 : KS / 2;
+        uint4 wr[KS][2];
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+            const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
+            wr[k][0] = q[0];
+            wr[k][1] = q[1];
+        }
         // receive sums of the wave's receive bin: element tiles x (Re, Im)
         floatx4 X[RXE][2];
 #pragma unroll
@@ -816,10 +830,9 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                     }
                 }
             }
-            // the wave's split weights of k-steps 0 .. KS - 1: 4 elements each
-            uint4 wr[KS][2];
+            // the rest of the wave's split weights, per chunk
 #pragma unroll
-            for (int k = 0; k < KS; ++k) {
+            for (int k = KH; k < KS; ++k) {
                 const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
                 wr[k][0] = q[0];
                 wr[k][1] = q[1];
