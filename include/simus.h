@@ -143,22 +143,26 @@ typedef struct {
                                         persistent launch (the matrix-core path is always
                                         persistent); results are bitwise the same */
 #define SIMUS_FLAG_ALT_SHAPE    32   /* the alternative tile shape.  Matrix-core path: the
-                                        kernels that set a pair up every four bins (more
-                                        than 64 elements; groups of 16 transmit columns up
-                                        to 16 transmits, else 32) or six bins (64 or fewer;
-                                        groups of 32 columns, or 64 above 32 transmits where
-                                        they pad no more) instead of every eight bins over
-                                        groups of 16.  Vector path: single transmits instead
+                                        kernels with FP32 products that set a pair up every
+                                        four bins (more than 64 elements; groups of 16
+                                        transmit columns up to 16 transmits, else 32) or six
+                                        bins (64 or fewer; groups of 32 columns, or 64 above
+                                        32 transmits where they pad no more) instead of the
+                                        default split-bf16 ones (every eight bins over groups
+                                        of 16 up to 16 transmits, every four bins over groups
+                                        of 32 above).  Vector path: single transmits instead
                                         of pairs, or pairs instead of single transmits.  The
                                         autotuner tries it.  simus_rf_backward: the other of
                                         its two kernels (matrix-core or vector) where both
                                         apply.  The results agree to rounding order */
 #define SIMUS_FLAG_FP32_PRODUCTS 64  /* matrix-core path, default shape: the two
-                                        contractions with FP32 matrix-core products instead
-                                        of products of operands split into bf16 high and low
-                                        parts (three bf16 products per real product, FP32
-                                        accumulation: about 2^-16 of each product, 5e-6
-                                        relative L2 on RF against the FP32 products) */
+                                        contractions with FP32 matrix-core products (eight
+                                        bins per set-up over groups of 16 transmit columns)
+                                        instead of products of operands split into bf16 high
+                                        and low parts (three bf16 products per real product,
+                                        FP32 accumulation: about 2^-16 of each product, 5e-6
+                                        relative L2 on RF against the FP32 products).  Also
+                                        the matrix-core adjoint's GEMM (up to 8 transmits) */
 /* Other bits of options.flags are rejected with SIMUS_EINVAL. */
 
 /* Frequency grid of one call. */

@@ -446,9 +446,10 @@ size_t fwd_layout(FwdPlan& F, int n_items, bool own_spec)
     layout_device(dv, F.L, C);
     F.o_part = dv.add(sizeof(float2) * size_t(std::max(n_items, 1)) * F.cfg.jt * F.cfg.tt * F.slots);
     F.o_tk = dv.add(sizeof(int32_t) * 4);
-    // the matrix-core kernels' padded weights [n_bins][n_tg][NE][16]
-    const int n_tg16 = (C.n_tx + 15) / 16;
-    F.o_wt = F.cfg.wt ? dv.add(sizeof(float2) * size_t(std::max(C.B.n_bins, 1)) * n_tg16 * F.cfg.ne * 16) : 0;
+    // the matrix-core kernels' padded weights [n_bins][n_tg][NE][TT] (or
+    // [n_bins][n_tg][TT][NE] split)
+    const int n_tgw = (C.n_tx + F.cfg.tt - 1) / F.cfg.tt;
+    F.o_wt = F.cfg.wt ? dv.add(sizeof(float2) * size_t(std::max(C.B.n_bins, 1)) * n_tgw * F.cfg.ne * F.cfg.tt) : 0;
     const size_t spec_bytes = sizeof(float2) * size_t(C.ph.n) * C.n_tx * C.P.N * std::max(C.B.n_bins, 1);
     F.o_spec = own_spec ? dv.add(spec_bytes) : 0;
     F.up_size = up.size;
@@ -606,8 +607,8 @@ void enqueue_fwd(const FwdPlan& F, char* d, const float* x, const float* y, cons
     if (cfg.wt)
         hip_check(timed(K_WTABLE, st, [&] {
                       return launch_wtable_mt(at<float2>(d, F.o_wt), at<double>(d, F.L.dl), at<float>(d, F.L.ap),
-                                              C.B.n_bins, n_tx, N, cfg.ne, (n_tx + 15) / 16, C.B.j_lo,
-                                              C.B.df, cfg.bf, st);
+                                              C.B.n_bins, n_tx, N, cfg.ne, cfg.tt, (n_tx + cfg.tt - 1) / cfg.tt,
+                                              C.B.j_lo, C.B.df, cfg.bf, st);
                   }),
                   "matrix-core weight table launch");
     SynthArgs A{};

@@ -47,9 +47,9 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 //   y = (Re_l | Im_l << 16), with Re = Re_h + Re_l to 16 significant bits.
 __global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ delays,
                             const float* __restrict__ apod, int n_bins, int n_tx, int N, int ne,
-                            int n_tg, int j_lo, double df, bool bf16)
+                            int tpg, int n_tg, int j_lo, double df, bool bf16)
 {
-    const int64_t total = (int64_t)n_bins * n_tg * ne * 16;
+    const int64_t total = (int64_t)n_bins * n_tg * ne * tpg;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         int c, e;
@@ -57,8 +57,8 @@ __global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ 
         if (bf16) {
             e = (int)(i % ne);
             r = i / ne;
-            c = (int)(r % 16);
-            r /= 16;
+            c = (int)(r % tpg);
+            r /= tpg;
         } else {
             c = (int)(i % 16);
             r = i / 16;
@@ -67,7 +67,7 @@ __global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ 
         }
         const int g = (int)(r % n_tg);
         const int b = (int)(r / n_tg);
-        const int t = 16 * g + c;
+        const int t = tpg * g + c;
         float2 w = make_float2(0.f, 0.f);
         if (e < N && t < n_tx) {
             const int te = t * N + e;
@@ -87,13 +87,14 @@ __global__ void k_wtable_mt(float2* __restrict__ WT, const double* __restrict__ 
 }
 
 hipError_t launch_wtable_mt(float2* WT, const double* delays, const float* apod, int n_bins, int n_tx,
-                            int N, int ne, int n_tg, int j_lo, double df, bool bf16, hipStream_t st)
+                            int N, int ne, int tpg, int n_tg, int j_lo, double df, bool bf16, hipStream_t st)
 {
-    const int64_t total = (int64_t)n_bins * n_tg * ne * 16;
+    if (!bf16 && tpg != 16) return hipErrorInvalidValue;
+    const int64_t total = (int64_t)n_bins * n_tg * ne * tpg;
     if (total == 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_wtable_mt, dim3(grid), dim3(256), 0, st, WT, delays, apod, n_bins, n_tx, N, ne,
-                       n_tg, j_lo, df, bf16);
+                       tpg, n_tg, j_lo, df, bf16);
     return hipGetLastError();
 }
 

@@ -211,7 +211,7 @@ hipError_t launch_wtable(float2* W, const double* delays, const float* apod, int
 // transmit 16 g + c and element e at bin b, zero for e >= N or a transmit
 // past n_tx; ne element slots, n_tg groups of 16 columns.
 hipError_t launch_wtable_mt(float2* WT, const double* delays, const float* apod, int n_bins, int n_tx,
-                            int N, int ne, int n_tg, int j_lo, double df, bool bf16, hipStream_t st);
+                            int N, int ne, int tpg, int n_tg, int j_lo, double df, bool bf16, hipStream_t st);
 // The synthesis kernel instance a configuration runs (nullptr if none), for
 // the launch and for occupancy queries (blocks of cfg.bs threads, or 512 on
 // the matrix-core path).

@@ -607,7 +607,7 @@ struct MtShape {
     int ne, ntp, jt, nx;
 };
 
-static MtShape mt_shape(int N, int n_tx, bool alt)
+static MtShape mt_shape(int N, int n_tx, bool alt, bool fp32)
 {
     // Default: the eight-bin kernel over groups of 16 transmit columns, 64 or
     // 128 element slots (products in split bf16, k_synth_mb; in FP32 with
@@ -620,6 +620,12 @@ static MtShape mt_shape(int N, int n_tx, bool alt)
     // array, 40k scatterers 30.7 / 38.6 vs 40.7 (64 columns, 6 bins);
     // 64-element arrays with up to 16 transmits about half the time of 32
     // columns and 6 bins.
+    // More than 16 transmits (split bf16): groups of 32 columns, four bins per
+    // set-up (k_synth_mw), which synthesises G once per 32 transmits: 21
+    // plane waves, 200k scatterers 112 vs 158 ms over two groups of 16; 128
+    // focused transmits on 64 elements 19.8 vs 26.1 ms; 40 plane waves, 100k
+    // scatterers 119 vs 122 ms.
+    if (!alt && n_tx > 16 && !fp32) return {N <= 64 ? 64 : 128, 2, 4, 2};
     if (!alt) return {N <= 64 ? 64 : 128, 1, 8, N <= 64 ? MQ_NX64 : MQ_NX};
     // the alternative, k_synth_mt: 64 element slots, 6 bins per item, groups
     // of 64 transmit columns where they pad no more than groups of 32 (40k
@@ -659,7 +665,7 @@ bool mt_supported(int M, int N, int n_tx)
 
 SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
 {
-    const MtShape sh = mt_shape(N, n_tx, alt);
+    const MtShape sh = mt_shape(N, n_tx, alt, fp32);
     SynthConfig c{};
     c.bs = 512;
     c.groups = 1;
@@ -667,7 +673,9 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
     c.tt = 16 * sh.ntp;                       // transmits per group
     c.jt = sh.jt;
     c.nx = sh.nx;
-    c.wt = sh.ntp == 1 && sh.jt == 8;
+    // the kernels that read the padded weight table: eight bins over 16
+    // columns (split bf16 or FP32 products), four bins over 32 (split bf16)
+    c.wt = !alt;
     c.bf = c.wt && !fp32;
     c.sc = 16;
     c.pair = M == 2 * N;
@@ -922,6 +930,257 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     }
 }
 
+// More than 16 transmits: groups of 32 transmit columns, four bins per item,
+// split-bf16 products as in k_synth_mb.  The Green's terms of a pair are
+// synthesised once per 32 transmits (twice over two groups of 16 in
+// k_synth_mb), at the price of a set-up every four bins.  Wave w = (bin
+// w / 2, half w % 2):
+//   P1  every thread: set-up and the element sums of the four bins, split;
+//   P2  the transmit GEMM of its bin for column tile w % 2 (16 transmits);
+//   P3  the receive GEMM of its bin for element half w % 2, both column
+//       tiles, into its registers.
+template <int NE, int NUV, bool HASY, bool TABLE>
+__global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
+{
+    constexpr int NB = 512;
+    constexpr int MS = NE * NUV;            // sub-element slots
+    constexpr int SCH = 16;                 // scatterers per chunk (MFMA rows)
+    constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
+    constexpr int NSG = NB / MS;            // scatterer groups
+    constexpr int JT = 4;                   // bins per item: two waves per bin
+    constexpr int TPG = 32;                 // transmit columns: two tiles of 16
+    constexpr int BPS = NE + 4;             // row stride (words) of the element-sum planes
+    constexpr int CS = SCH + 2;             // row stride (uint2) of c[t][s]
+    constexpr int KS = NE / 16;             // transmit-GEMM k-steps (16 elements each)
+    constexpr int RXH = NE / 32;            // receive element tiles per wave (half of them)
+    static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
+    static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
+    static_assert(PPT * NSG == SCH, "threads must cover the chunk");
+
+    __shared__ float4 s_sc[SCH];
+    __shared__ __align__(16) uint32_t s_Bh[JT][SCH * BPS];
+    __shared__ __align__(16) uint32_t s_Bl[JT][SCH * BPS];
+    __shared__ __align__(16) uint2 s_c[JT][TPG * CS];
+    __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int gi = lane & 15, gk = lane >> 4;      // MFMA lane roles: row/column, k block
+    const int wj = wave >> 1, wh = wave & 1;       // the wave's bin and half
+    const int n = tid % MS, sh = tid / MS;
+    const bool active = n < A.M;
+    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    const int n_tg = (A.n_tx + TPG - 1) / TPG;
+    const uint2* WTb = reinterpret_cast<const uint2*>(A.WT);
+
+    DeltaParams P{};
+    if (TABLE) {
+        for (int i = tid; i < 2 * DELTA_NT; i += NB) s_tab[i] = A.dtab[i];
+        P = *A.dpar;
+    }
+
+    auto load_chunk = [&](int s0, int s_end) {
+        if (tid < SCH) {
+            const int s = s0 + tid;
+            float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
+            if (s < s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
+            s_sc[tid] = v;
+        }
+    };
+
+    if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+    __syncthreads();
+    int item = s_item;
+    while (item < A.n_items) {
+        const int id = A.order[item];          // costliest first
+        const Item it = A.items[id];
+        const int bt = it.tile & 0xffff, tg = it.tile >> 16;
+        const int jb0 = bt * JT;
+        const int nb = min(JT, A.n_bins - jb0);
+        // this wave's weights: WT[bin][tg][t = 16 wh + gi][e = 16 k + 4 gk .. + 3]
+        const int jbw = min(jb0 + wj, A.n_bins - 1);
+        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + 16 * wh + gi) * NE + 4 * gk;
+        // the weights of the first KH k-steps stay in registers for the item
+        // (all of them for 64 element slots; none for 128, where half of them
+        // spill 12 dwords)
+        constexpr int KH = NE == 64 ? KS : 0;
+        uint4 wr[KS][2];
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+            const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
+            wr[k][0] = q[0];
+            wr[k][1] = q[1];
+        }
+        // receive sums of the wave's bin, element half wh: tiles x column
+        // tiles x (Re, Im)
+        floatx4 X[RXH][2][2];
+#pragma unroll
+        for (int m = 0; m < RXH; ++m)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) X[m][ct][0] = X[m][ct][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        load_chunk(it.s_begin, it.s_end);
+        __syncthreads();
+        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+            // ---- P1: set-up, the element sums of the four bins, split
+            {
+                Geo g[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const float4 v = s_sc[sh * PPT + k];
+                    g[k] = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+                    if (!active) g[k].E = make_float2(0.f, 0.f);
+                    if (TABLE) g[k].kap *= P.kscale;          // delta_fetch's argument
+                }
+#pragma unroll 1
+                for (int jj = 0; jj < JT; ++jj) {
+                    const float jf = (float)(A.j_lo + jb0 + jj);
+                    float2 G[PPT];
+                    if constexpr (TABLE) {
+                        DeltaFetch fch[2];
+                        fch[0] = delta_fetch(s_tab, P, jf * g[0].kap);
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) {
+                            if (k + 1 < PPT) fch[(k + 1) & 1] = delta_fetch(s_tab, P, jf * g[k + 1].kap);
+                            __builtin_amdgcn_sched_barrier(0);
+                            G[k] = green_next_fetched(g[k], fch[k & 1]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) G[k] = green_next<HASY, TABLE>(A.K, g[k], jf, 1.f, s_tab, P);
+                    }
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const int s = sh * PPT + k;
+                        float bx = G[k].x, by = G[k].y;
+                        if (NUV == 2) {
+                            bx += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bx), 0xB1, 0xF, 0xF, true));
+                            by += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(by), 0xB1, 0xF, 0xF, true));
+                        }
+                        const uint32_t h = pack_bf16(bx, by);
+                        const uint32_t l = pack_bf16(bx - bf16_lo(h), by - bf16_hi(h));
+                        const int e = NUV == 2 ? (n >> 1) : n;
+                        if (NUV == 2) {
+                            uint32_t* plane = (n & 1) ? s_Bl[jj] : s_Bh[jj];
+                            plane[s * BPS + e] = (n & 1) ? l : h;
+                        } else {
+                            s_Bh[jj][s * BPS + e] = h;
+                            s_Bl[jj][s * BPS + e] = l;
+                        }
+                    }
+                }
+            }
+            // the rest of the wave's split weights, per chunk
+#pragma unroll
+            for (int k = KH; k < KS; ++k) {
+                const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
+                wr[k][0] = q[0];
+                wr[k][1] = q[1];
+            }
+            __syncthreads();
+            // ---- P2: transmit GEMM of bin wj, column tile wh: rows s = gi,
+            //      columns t = 16 wh + gi, k = (element 16 k + 4 gk + q, Re/Im)
+            {
+                const uint32_t* bh = s_Bh[wj] + gi * BPS + 4 * gk;
+                const uint32_t* bl = s_Bl[wj] + gi * BPS + 4 * gk;
+                floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const uint4 ah4 = *reinterpret_cast<const uint4*>(bh + 16 * k);
+                    const uint4 al4 = *reinterpret_cast<const uint4*>(bl + 16 * k);
+                    const u32x4 ah = {ah4.x, ah4.y, ah4.z, ah4.w}, al = {al4.x, al4.y, al4.z, al4.w};
+                    const uint32_t wh4[4] = {wr[k][0].x, wr[k][0].z, wr[k][1].x, wr[k][1].z};
+                    const uint32_t wl4[4] = {wr[k][0].y, wr[k][0].w, wr[k][1].y, wr[k][1].w};
+                    const u32x4 rh = {bf_conj(wh4[0]), bf_conj(wh4[1]), bf_conj(wh4[2]), bf_conj(wh4[3])};
+                    const u32x4 rl = {bf_conj(wl4[0]), bf_conj(wl4[1]), bf_conj(wl4[2]), bf_conj(wl4[3])};
+                    const u32x4 ih = {bf_swap(wh4[0]), bf_swap(wh4[1]), bf_swap(wh4[2]), bf_swap(wh4[3])};
+                    const u32x4 il = {bf_swap(wl4[0]), bf_swap(wl4[1]), bf_swap(wl4[2]), bf_swap(wl4[3])};
+                    re = mfma_bf(ah, rh, re);
+                    re = mfma_bf(ah, rl, re);
+                    re = mfma_bf(al, rh, re);
+                    im = mfma_bf(ah, ih, im);
+                    im = mfma_bf(ah, il, im);
+                    im = mfma_bf(al, ih, im);
+                }
+                // D[row][col]: row s = 4 gk + v, col t = 16 wh + gi; c = R_s a, split
+                uint2* sc = s_c[wj] + (16 * wh + gi) * CS;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int s = 4 * gk + v;
+                    const float R = s_sc[s].w;
+                    const float cx = R * re[v], cy = R * im[v];
+                    const uint32_t h = pack_bf16(cx, cy);
+                    sc[s] = make_uint2(h, pack_bf16(cx - bf16_lo(h), cy - bf16_hi(h)));
+                }
+            }
+            __syncthreads();
+            // ---- P3: receive GEMM of bin wj, element tiles wh RXH .. + RXH - 1,
+            //      both column tiles, k = (scatterer 4 gk + q, Re/Im); the next
+            //      chunk's scatterers
+            {
+                u32x4 rh[2], rl[2], ih[2], il[2];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    const uint2* cp = s_c[wj] + (16 * ct + gi) * CS + 4 * gk;
+                    const uint4 c01 = *reinterpret_cast<const uint4*>(cp);
+                    const uint4 c23 = *reinterpret_cast<const uint4*>(cp + 2);
+                    const uint32_t ch[4] = {c01.x, c01.z, c23.x, c23.z};
+                    const uint32_t cl[4] = {c01.y, c01.w, c23.y, c23.w};
+                    rh[ct] = u32x4{bf_conj(ch[0]), bf_conj(ch[1]), bf_conj(ch[2]), bf_conj(ch[3])};
+                    rl[ct] = u32x4{bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
+                    ih[ct] = u32x4{bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
+                    il[ct] = u32x4{bf_swap(cl[0]), bf_swap(cl[1]), bf_swap(cl[2]), bf_swap(cl[3])};
+                }
+                const uint32_t* bh = s_Bh[wj] + 4 * gk * BPS + 16 * RXH * wh + gi;
+                const uint32_t* bl = s_Bl[wj] + 4 * gk * BPS + 16 * RXH * wh + gi;
+#pragma unroll
+                for (int m = 0; m < RXH; ++m) {
+                    const u32x4 ah = {bh[16 * m], bh[BPS + 16 * m], bh[2 * BPS + 16 * m], bh[3 * BPS + 16 * m]};
+                    const u32x4 al = {bl[16 * m], bl[BPS + 16 * m], bl[2 * BPS + 16 * m], bl[3 * BPS + 16 * m]};
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct) {
+                        X[m][ct][0] = mfma_bf(ah, rh[ct], X[m][ct][0]);
+                        X[m][ct][0] = mfma_bf(ah, rl[ct], X[m][ct][0]);
+                        X[m][ct][0] = mfma_bf(al, rh[ct], X[m][ct][0]);
+                        X[m][ct][1] = mfma_bf(ah, ih[ct], X[m][ct][1]);
+                        X[m][ct][1] = mfma_bf(ah, il[ct], X[m][ct][1]);
+                        X[m][ct][1] = mfma_bf(al, ih[ct], X[m][ct][1]);
+                    }
+                }
+            }
+            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end);
+            __syncthreads();
+        }
+        // per-element partials [item][JT][TPG][N] of the wave's bin and element
+        // half; D[row][col]: row = element 16 (RXH wh + m) + 4 gk + v, col =
+        // transmit 16 ct + gi
+        if (wj < nb) {
+            float2* out = A.part + ((int64_t)id * JT + wj) * TPG * A.N;
+#pragma unroll
+            for (int m = 0; m < RXH; ++m)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int e = 16 * (RXH * wh + m) + 4 * gk + v;
+                        if (e < A.N) out[(int64_t)(16 * ct + gi) * A.N + e] = make_float2(X[m][ct][0][v], X[m][ct][1][v]);
+                    }
+        }
+        if (tid == 0) s_item = atomicAdd(A.ticket, 1);
+        __syncthreads();
+        item = s_item;
+    }
+}
+
+template <int NE, int NUV>
+static SynthKernel mw_kernel_nuv(const SynthConfig& c)
+{
+    if (c.has_y) return k_synth_mw<NE, NUV, true, false>;
+    if (c.table) return k_synth_mw<NE, NUV, false, true>;
+    return k_synth_mw<NE, NUV, false, false>;
+}
+
 template <int NE, int NUV>
 static SynthKernel mb_kernel_nuv(const SynthConfig& c)
 {
@@ -940,6 +1199,10 @@ static SynthKernel mq_kernel_nuv(const SynthConfig& c)
 
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
+    if (c.bf && c.wt && c.tt == 32 && c.jt == 4) {
+        if (c.ne == 128) return c.pair ? mw_kernel_nuv<128, 2>(c) : mw_kernel_nuv<128, 1>(c);
+        if (c.ne == 64) return c.pair ? mw_kernel_nuv<64, 2>(c) : mw_kernel_nuv<64, 1>(c);
+    }
     if (c.bf && c.wt && c.tt == 16 && c.jt == 8) {
         if (c.ne == 128) return c.pair ? mb_kernel_nuv<128, 2>(c) : mb_kernel_nuv<128, 1>(c);
         if (c.ne == 64) return c.pair ? mb_kernel_nuv<64, 2>(c) : mb_kernel_nuv<64, 1>(c);
@@ -948,6 +1211,7 @@ SynthKernel synth_mt_kernel(const SynthConfig& c)
         return c.pair ? mq_kernel_nuv<128, MQ_NX, 2>(c) : mq_kernel_nuv<128, MQ_NX, 1>(c);
     if (c.wt && c.ne == 64 && c.tt == 16 && c.jt == 8 && c.nx == MQ_NX64)
         return c.pair ? mq_kernel_nuv<64, MQ_NX64, 2>(c) : mq_kernel_nuv<64, MQ_NX64, 1>(c);
+    if (c.wt) return nullptr;
     if (c.ne == 128 && c.tt == 16) return mt_kernel_shape<128, 1, 4, 3>(c);
     if (c.ne == 128 && c.tt == 32) return mt_kernel_shape<128, 2, 4, 2>(c);
     if (c.ne == 64 && c.tt == 32) return mt_kernel_shape<64, 2, 6, 3>(c);

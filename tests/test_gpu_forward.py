@@ -197,12 +197,14 @@ def test_empty_and_degenerate(S):
 @pytest.mark.parametrize("n_tx,n_el,nu,with_y,no_mfma", [
     (21, 32, 0, False, False), (33, 32, 0, False, False), (6, 32, 0, True, False),
     (12, 64, 1, False, False), (5, 200, 1, False, False), (21, 32, 0, False, True),
-    (11, 100, 0, False, False), (40, 128, 0, False, False), (70, 48, 1, False, False)])
+    (11, 100, 0, False, False), (40, 128, 0, False, False), (70, 48, 1, False, False),
+    (24, 100, 0, True, False)])
 def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
     """Many steered plane waves: the transmit contraction on the matrix cores
     (or, with the flag, on the VALU path) matches the oracle; covers the
-    default eight-bin kernel with 64 and 128 element slots and one to five
-    groups of 16 transmit columns,
+    default kernels with 64 and 128 element slots: eight bins over groups of
+    16 transmit columns up to 16 transmits, four bins over one to three
+    groups of 32 above,
     several transmit groups with a ragged last one, y != 0, nu = 1 and 200
     elements (vector path)."""
     from paper_2102_02738_amd import inputs
@@ -357,7 +359,7 @@ def test_alt_tile_shape(S, orc, n_tx, n_el, nu):
     the four-bin kernel with 32 transmit columns for 100 elements and 21
     transmits, with 16 for 128 elements and 11, the six-bin one with 32
     columns for 48 elements and 11 transmits, with 64 for 48 and 40, instead
-    of the eight-bin kernel; on the vector path pairs instead of single
+    of the default split-bf16 kernels; on the vector path pairs instead of single
     transmits for 5, single instead of pairs for 6) matches the oracle and
     the default shape to rounding order."""
     from paper_2102_02738_amd import inputs
