@@ -403,7 +403,9 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
                 //      gradient for the step's four bins (past the range's
                 //      end they are stepped but not used)
                 if (pend) gradient(pend_j0);
-#pragma unroll 1
+                // the four bins unrolled, so that their table reads can be
+                // issued ahead (5 plane waves, 100k scatterers: 82.0 -> 78.3 ms)
+#pragma unroll
                 for (int jj = 0; jj < JB; ++jj) {
                     const float jf = (float)(A.j_lo + jb0 + jq + jj);
                     const float inv_j = rcp_fast(jf);
