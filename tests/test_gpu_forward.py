@@ -198,7 +198,7 @@ def test_empty_and_degenerate(S):
     (21, 32, 0, False, False), (33, 32, 0, False, False), (6, 32, 0, True, False),
     (12, 64, 1, False, False), (5, 200, 1, False, False), (21, 32, 0, False, True),
     (11, 100, 0, False, False), (40, 128, 0, False, False), (70, 48, 1, False, False),
-    (24, 100, 0, True, False)])
+    (24, 100, 0, True, False), (20, 40, 1, True, False)])
 def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
     """Many steered plane waves: the transmit contraction on the matrix cores
     (or, with the flag, on the VALU path) matches the oracle; covers the

@@ -92,11 +92,14 @@ def test_graph_recaptures_on_new_pointers(S):
     plan.close()
 
 
-def test_batched_uneven_phantoms_graph_vs_oracle(S, orc):
+@pytest.mark.parametrize("n_tx", [7, 20])
+def test_batched_uneven_phantoms_graph_vs_oracle(S, orc, n_tx):
     """One persistent graph launch over 4 uneven phantoms (one empty) with 7
-    diverging waves on the matrix-core path, against per-phantom oracle runs."""
+    diverging waves (the eight-bin kernel) or 20 (the four-bin kernel over a
+    group of 32 columns) on the matrix-core path, against per-phantom oracle
+    runs."""
     import torch
-    w = _convex_uneven(7)
+    w = _convex_uneven(n_tx)
     g, o, (dx, dy, dz, dR), (x, y, z, R, off) = _prep(S, w, S.FLAG_PERSISTENT)
     plan = S.rf_plan(w["probe"], w["medium"], o, w["delays"], w["apod"], offsets=off)
     rf = plan.rf(dx, None, dz, dR, g["n_t"], graph=True).cpu().numpy()
