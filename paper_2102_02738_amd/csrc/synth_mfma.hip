@@ -700,8 +700,13 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
 //   P2  wave w, bin w: a[s][t] = sum_e B[s][e] W[e][t], 8 (NE = 128) or 4
 //       k-steps of 16 elements, 6 MFMAs each; weights from the split table
 //       WT[bin][group][t][e] (uint2: h, l); c = R_s a, split, to LDS;
-//   P3  wave w, bin w ^ 4: X[e][t] += sum_s B[e][s] c[s][t], one k-step per
+//   P3  wave w, bin w: X[e][t] += sum_s B[e][s] c[s][t], one k-step per
 //       element tile (16 scatterers), 6 MFMAs.
+// A wave reads in P3 only the c it wrote in P2, so the two GEMMs need no
+// barrier between them (LDS operations of a wave complete in order), and
+// the next chunk's positions go to the other of two buffers: two barriers
+// per chunk (with three, 16 phantoms at a quarter of their scatterers took
+// 235.9 ms instead of 232.4, results bit-identical).
 // FP32 16x16x4 MFMAs contract 4 real values in 32 cycles, bf16 16x16x32 ones
 // 32 in about 16-20; per complex product this takes 6 x 2 bf16 products
 // instead of 3 (or 4) FP32 ones.
@@ -724,7 +729,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * NSG == SCH, "threads must cover the chunk");
 
-    __shared__ float4 s_sc[SCH];
+    __shared__ float4 s_sc[2][SCH];          // by chunk parity
     __shared__ __align__(16) uint32_t s_Bh[JT][SCH * BPS];
     __shared__ __align__(16) uint32_t s_Bl[JT][SCH * BPS];
     __shared__ __align__(16) uint2 s_c[JT][TPG * CS];
@@ -734,7 +739,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int gi = lane & 15, gk = lane >> 4;      // MFMA lane roles: row/column, k block
-    const int btx = wave, brx = wave ^ 4;          // the wave's transmit and receive bins
+    const int bw = wave;                           // the wave's bin in both GEMMs
     const int n = tid % MS, sh = tid / MS;
     const bool active = n < A.M;
     const SubFrame fr = load_frame(A.sub, active ? n : 0);
@@ -747,12 +752,12 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
         P = *A.dpar;
     }
 
-    auto load_chunk = [&](int s0, int s_end) {
+    auto load_chunk = [&](int s0, int s_end, int par) {
         if (tid < SCH) {
             const int s = s0 + tid;
             float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
             if (s < s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
-            s_sc[tid] = v;
+            s_sc[par][tid] = v;
         }
     };
 
@@ -766,7 +771,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
         const int jb0 = bt * JT;
         const int nb = min(JT, A.n_bins - jb0);
         // this wave's weights: WT[bin][tg][t = gi][e = 16 k + 4 gk .. + 3]
-        const int jbw = min(jb0 + btx, A.n_bins - 1);
+        const int jbw = min(jb0 + bw, A.n_bins - 1);
         const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + gi) * NE + 4 * gk;
 
         // the wave's split weights are the same for every chunk of the item:
@@ -788,9 +793,9 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
 #pragma unroll
         for (int m = 0; m < RXE; ++m) X[m][0] = X[m][1] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-        load_chunk(it.s_begin, it.s_end);
+        load_chunk(it.s_begin, it.s_end, 0);
         __syncthreads();
-        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+        for (int s0 = it.s_begin, par = 0; s0 < it.s_end; s0 += SCH, par ^= 1) {
             // ---- P1: the element sums of the eight bins, split; pair by pair
             //      (set-up, then its eight bins), so that one pair's state is
             //      live at a time and its eight table fetches are in flight
@@ -798,7 +803,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
 #pragma unroll 1
             for (int k = 0; k < PPT; ++k) {
                 const int s = sh * PPT + k;
-                const float4 v = s_sc[s];
+                const float4 v = s_sc[par][s];
                 Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g.E = make_float2(0.f, 0.f);
                 if (TABLE) g.kap *= P.kscale;                 // delta_fetch's argument
@@ -842,11 +847,11 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                 wr[k][1] = q[1];
             }
             __syncthreads();
-            // ---- P2: transmit GEMM of bin btx: rows s = gi, columns t = gi,
+            // ---- P2: transmit GEMM of bin bw: rows s = gi, columns t = gi,
             //      k = (element 16 k + 4 gk + q, Re/Im)
             {
-                const uint32_t* bh = s_Bh[btx] + gi * BPS + 4 * gk;
-                const uint32_t* bl = s_Bl[btx] + gi * BPS + 4 * gk;
+                const uint32_t* bh = s_Bh[bw] + gi * BPS + 4 * gk;
+                const uint32_t* bl = s_Bl[bw] + gi * BPS + 4 * gk;
                 floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
@@ -868,21 +873,24 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                     im = mfma_bf(al, ih, im);
                 }
                 // D[row][col]: row s = 4 gk + v, col t = gi; c = R_s a, split
-                uint2* sc = s_c[btx];
+                uint2* sc = s_c[bw];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int s = 4 * gk + v;
-                    const float R = s_sc[s].w;
+                    const float R = s_sc[par][s].w;
                     const float cx = R * re[v], cy = R * im[v];
                     const uint32_t h = pack_bf16(cx, cy);
                     sc[gi * CS + s] = make_uint2(h, pack_bf16(cx - bf16_lo(h), cy - bf16_hi(h)));
                 }
             }
-            __syncthreads();
-            // ---- P3: receive GEMM of bin brx: rows e, columns t = gi,
+            // P3 reads only the c of the wave's own bin: LDS order within the wave
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // ---- P3: receive GEMM of bin bw: rows e, columns t = gi,
             //      k = (scatterer 4 gk + q, Re/Im); the next chunk's scatterers
             {
-                const uint2* cp = s_c[brx] + gi * CS + 4 * gk;
+                const uint2* cp = s_c[bw] + gi * CS + 4 * gk;
                 const uint4 c01 = *reinterpret_cast<const uint4*>(cp);
                 const uint4 c23 = *reinterpret_cast<const uint4*>(cp + 2);
                 const uint32_t ch[4] = {c01.x, c01.z, c23.x, c23.z};
@@ -891,8 +899,8 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                 const u32x4 rl = {bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
                 const u32x4 ih = {bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
                 const u32x4 il = {bf_swap(cl[0]), bf_swap(cl[1]), bf_swap(cl[2]), bf_swap(cl[3])};
-                const uint32_t* bh = s_Bh[brx] + 4 * gk * BPS + gi;
-                const uint32_t* bl = s_Bl[brx] + 4 * gk * BPS + gi;
+                const uint32_t* bh = s_Bh[bw] + 4 * gk * BPS + gi;
+                const uint32_t* bl = s_Bl[bw] + 4 * gk * BPS + gi;
 #pragma unroll
                 for (int m = 0; m < RXE; ++m) {
                     const u32x4 ah = {bh[16 * m], bh[BPS + 16 * m], bh[2 * BPS + 16 * m], bh[3 * BPS + 16 * m]};
@@ -905,13 +913,13 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                     X[m][1] = mfma_bf(al, ih, X[m][1]);
                 }
             }
-            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end);
+            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end, par ^ 1);
             __syncthreads();
         }
         // per-element partials [item][JT][TPG][N] of the wave's receive bin;
         // D[row][col]: row = element 16 m + 4 gk + v, col = transmit gi
-        if (brx < nb) {
-            float2* out = A.part + ((int64_t)id * JT + brx) * TPG * A.N;
+        if (bw < nb) {
+            float2* out = A.part + ((int64_t)id * JT + bw) * TPG * A.N;
 #pragma unroll
             for (int m = 0; m < RXE; ++m)
 #pragma unroll
