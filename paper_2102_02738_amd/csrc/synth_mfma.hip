@@ -699,14 +699,17 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
 //       pairs), element sums, split, into two LDS planes per bin (h and l);
 //   P2  wave w, bin w: a[s][t] = sum_e B[s][e] W[e][t], 8 (NE = 128) or 4
 //       k-steps of 16 elements, 6 MFMAs each; weights from the split table
-//       WT[bin][group][t][e] (uint2: h, l); c = R_s a, split, to LDS;
+//       WT[bin][group][t][e] (uint2: h, l); c = R_s a, split;
 //   P3  wave w, bin w: X[e][t] += sum_s B[e][s] c[s][t], one k-step per
 //       element tile (16 scatterers), 6 MFMAs.
-// A wave reads in P3 only the c it wrote in P2, so the two GEMMs need no
-// barrier between them (LDS operations of a wave complete in order), and
-// the next chunk's positions go to the other of two buffers: two barriers
-// per chunk (with three, 16 phantoms at a quarter of their scatterers took
-// 235.9 ms instead of 232.4, results bit-identical).
+// The transmit GEMM leaves c[s = 4 (lane / 16) + v][t = lane % 16] in the
+// lane that takes it as the receive GEMM's B operand (k = scatterers 4
+// (lane / 16) .. + 3, column lane % 16): with both GEMMs of a wave on one
+// bin, c never leaves the registers, the two GEMMs need no barrier between
+// them, and the next chunk's positions go to the other of two buffers: two
+// barriers per chunk.  16 phantoms at a quarter of their scatterers: 235.9
+// ms with c through LDS and three barriers, 232.4 with two, 230.0 with c in
+// registers (results bit-identical).
 // FP32 16x16x4 MFMAs contract 4 real values in 32 cycles, bf16 16x16x32 ones
 // 32 in about 16-20; per complex product this takes 6 x 2 bf16 products
 // instead of 3 (or 4) FP32 ones.
@@ -722,7 +725,6 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     constexpr int JT = 8;                   // bins per item: two per SIMD
     constexpr int TPG = 16;                 // transmit columns
     constexpr int BPS = NE + 4;             // row stride (words) of the element-sum planes
-    constexpr int CS = SCH + 2;             // row stride (uint2) of c[t][s]
     constexpr int KS = NE / 16;             // transmit-GEMM k-steps (16 elements each)
     constexpr int RXE = NE / 16;            // receive element tiles
     static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
@@ -732,7 +734,6 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     __shared__ float4 s_sc[2][SCH];          // by chunk parity
     __shared__ __align__(16) uint32_t s_Bh[JT][SCH * BPS];
     __shared__ __align__(16) uint32_t s_Bl[JT][SCH * BPS];
-    __shared__ __align__(16) uint2 s_c[JT][TPG * CS];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
     __shared__ int s_item;
 
@@ -849,6 +850,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
             __syncthreads();
             // ---- P2: transmit GEMM of bin bw: rows s = gi, columns t = gi,
             //      k = (element 16 k + 4 gk + q, Re/Im)
+            uint32_t ch[4], cl[4];
             {
                 const uint32_t* bh = s_Bh[bw] + gi * BPS + 4 * gk;
                 const uint32_t* bl = s_Bl[bw] + gi * BPS + 4 * gk;
@@ -872,29 +874,20 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                     im = mfma_bf(ah, il, im);
                     im = mfma_bf(al, ih, im);
                 }
-                // D[row][col]: row s = 4 gk + v, col t = gi; c = R_s a, split
-                uint2* sc = s_c[bw];
+                // D[row][col]: row s = 4 gk + v, col t = gi; c = R_s a, split.
+                // The receive GEMM's B operand takes k = (scatterer 4 gk + q,
+                // Re/Im) and column gi in the same lane: c stays in registers
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int s = 4 * gk + v;
-                    const float R = s_sc[par][s].w;
+                    const float R = s_sc[par][4 * gk + v].w;
                     const float cx = R * re[v], cy = R * im[v];
-                    const uint32_t h = pack_bf16(cx, cy);
-                    sc[gi * CS + s] = make_uint2(h, pack_bf16(cx - bf16_lo(h), cy - bf16_hi(h)));
+                    ch[v] = pack_bf16(cx, cy);
+                    cl[v] = pack_bf16(cx - bf16_lo(ch[v]), cy - bf16_hi(ch[v]));
                 }
             }
-            // P3 reads only the c of the wave's own bin: LDS order within the wave
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // ---- P3: receive GEMM of bin bw: rows e, columns t = gi,
             //      k = (scatterer 4 gk + q, Re/Im); the next chunk's scatterers
             {
-                const uint2* cp = s_c[bw] + gi * CS + 4 * gk;
-                const uint4 c01 = *reinterpret_cast<const uint4*>(cp);
-                const uint4 c23 = *reinterpret_cast<const uint4*>(cp + 2);
-                const uint32_t ch[4] = {c01.x, c01.z, c23.x, c23.z};
-                const uint32_t cl[4] = {c01.y, c01.w, c23.y, c23.w};
                 const u32x4 rh = {bf_conj(ch[0]), bf_conj(ch[1]), bf_conj(ch[2]), bf_conj(ch[3])};
                 const u32x4 rl = {bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
                 const u32x4 ih = {bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
@@ -938,11 +931,15 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
 // split-bf16 products as in k_synth_mb.  The Green's terms of a pair are
 // synthesised once per 32 transmits (twice over two groups of 16 in
 // k_synth_mb), at the price of a set-up every four bins.  Wave w = (bin
-// w / 2, half w % 2):
+// w / 2, column tile w % 2):
 //   P1  every thread: set-up and the element sums of the four bins, split;
-//   P2  the transmit GEMM of its bin for column tile w % 2 (16 transmits);
-//   P3  the receive GEMM of its bin for element half w % 2, both column
-//       tiles, into its registers.
+//   P2  the transmit GEMM of its bin and column tile (16 transmits);
+//   P3  the receive GEMM of its bin and column tile over all elements, into
+//       its registers, from the c of P2 kept in registers as in k_synth_mb
+//       (two barriers per chunk).  With the receive GEMM over element halves
+//       and both column tiles, c went through LDS with a barrier between the
+//       GEMMs: 128 focused transmits on 64 elements 18.8 -> 17.3 ms, 21
+//       plane waves 101.0 -> 100.2 ms (results bit-identical).
 template <int NE, int NUV, bool HASY, bool TABLE>
 __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
 {
@@ -954,17 +951,15 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
     constexpr int JT = 4;                   // bins per item: two waves per bin
     constexpr int TPG = 32;                 // transmit columns: two tiles of 16
     constexpr int BPS = NE + 4;             // row stride (words) of the element-sum planes
-    constexpr int CS = SCH + 2;             // row stride (uint2) of c[t][s]
     constexpr int KS = NE / 16;             // transmit-GEMM k-steps (16 elements each)
-    constexpr int RXH = NE / 32;            // receive element tiles per wave (half of them)
+    constexpr int RXE = NE / 16;            // receive element tiles
     static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * NSG == SCH, "threads must cover the chunk");
 
-    __shared__ float4 s_sc[SCH];
+    __shared__ float4 s_sc[2][SCH];          // by chunk parity
     __shared__ __align__(16) uint32_t s_Bh[JT][SCH * BPS];
     __shared__ __align__(16) uint32_t s_Bl[JT][SCH * BPS];
-    __shared__ __align__(16) uint2 s_c[JT][TPG * CS];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
     __shared__ int s_item;
 
@@ -984,12 +979,12 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
         P = *A.dpar;
     }
 
-    auto load_chunk = [&](int s0, int s_end) {
+    auto load_chunk = [&](int s0, int s_end, int par) {
         if (tid < SCH) {
             const int s = s0 + tid;
             float4 v = make_float4(0.f, 0.f, 1.f, 0.f);     // padding: R = 0
             if (s < s_end) v = make_float4(A.x[s], HASY ? A.y[s] : 0.f, A.z[s], A.refl[s]);
-            s_sc[tid] = v;
+            s_sc[par][tid] = v;
         }
     };
 
@@ -1016,23 +1011,20 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
             wr[k][0] = q[0];
             wr[k][1] = q[1];
         }
-        // receive sums of the wave's bin, element half wh: tiles x column
-        // tiles x (Re, Im)
-        floatx4 X[RXH][2][2];
+        // receive sums of the wave's bin and column tile: element tiles x (Re, Im)
+        floatx4 X[RXE][2];
 #pragma unroll
-        for (int m = 0; m < RXH; ++m)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) X[m][ct][0] = X[m][ct][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < RXE; ++m) X[m][0] = X[m][1] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-        load_chunk(it.s_begin, it.s_end);
+        load_chunk(it.s_begin, it.s_end, 0);
         __syncthreads();
-        for (int s0 = it.s_begin; s0 < it.s_end; s0 += SCH) {
+        for (int s0 = it.s_begin, par = 0; s0 < it.s_end; s0 += SCH, par ^= 1) {
             // ---- P1: the element sums of the four bins, split; pair by pair
             //      (set-up, then its four bins)
 #pragma unroll 1
             for (int k = 0; k < PPT; ++k) {
                 const int s = sh * PPT + k;
-                const float4 v = s_sc[s];
+                const float4 v = s_sc[par][s];
                 Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
                 if (!active) g.E = make_float2(0.f, 0.f);
                 if (TABLE) g.kap *= P.kscale;                 // delta_fetch's argument
@@ -1075,6 +1067,7 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                 wr[k][1] = q[1];
             }
             __syncthreads();
+            uint32_t ch[4], cl[4];
             // ---- P2: transmit GEMM of bin wj, column tile wh: rows s = gi,
             //      columns t = 16 wh + gi, k = (element 16 k + 4 gk + q, Re/Im)
             {
@@ -1099,69 +1092,55 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                     im = mfma_bf(ah, il, im);
                     im = mfma_bf(al, ih, im);
                 }
-                // D[row][col]: row s = 4 gk + v, col t = 16 wh + gi; c = R_s a, split
-                uint2* sc = s_c[wj] + (16 * wh + gi) * CS;
+                // D[row][col]: row s = 4 gk + v, col t = 16 wh + gi; c = R_s a,
+                // split.  The receive GEMM's B operand takes k = (scatterer
+                // 4 gk + q, Re/Im) and column gi in the same lane: c stays in
+                // registers
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int s = 4 * gk + v;
-                    const float R = s_sc[s].w;
+                    const float R = s_sc[par][4 * gk + v].w;
                     const float cx = R * re[v], cy = R * im[v];
-                    const uint32_t h = pack_bf16(cx, cy);
-                    sc[s] = make_uint2(h, pack_bf16(cx - bf16_lo(h), cy - bf16_hi(h)));
+                    ch[v] = pack_bf16(cx, cy);
+                    cl[v] = pack_bf16(cx - bf16_lo(ch[v]), cy - bf16_hi(ch[v]));
                 }
             }
-            __syncthreads();
-            // ---- P3: receive GEMM of bin wj, element tiles wh RXH .. + RXH - 1,
-            //      both column tiles, k = (scatterer 4 gk + q, Re/Im); the next
-            //      chunk's scatterers
+            // ---- P3: receive GEMM of bin wj, column tile wh, all element
+            //      tiles, k = (scatterer 4 gk + q, Re/Im); the next chunk's
+            //      scatterers
             {
-                u32x4 rh[2], rl[2], ih[2], il[2];
+                const u32x4 rh = {bf_conj(ch[0]), bf_conj(ch[1]), bf_conj(ch[2]), bf_conj(ch[3])};
+                const u32x4 rl = {bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
+                const u32x4 ih = {bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
+                const u32x4 il = {bf_swap(cl[0]), bf_swap(cl[1]), bf_swap(cl[2]), bf_swap(cl[3])};
+                const uint32_t* bh = s_Bh[wj] + 4 * gk * BPS + gi;
+                const uint32_t* bl = s_Bl[wj] + 4 * gk * BPS + gi;
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct) {
-                    const uint2* cp = s_c[wj] + (16 * ct + gi) * CS + 4 * gk;
-                    const uint4 c01 = *reinterpret_cast<const uint4*>(cp);
-                    const uint4 c23 = *reinterpret_cast<const uint4*>(cp + 2);
-                    const uint32_t ch[4] = {c01.x, c01.z, c23.x, c23.z};
-                    const uint32_t cl[4] = {c01.y, c01.w, c23.y, c23.w};
-                    rh[ct] = u32x4{bf_conj(ch[0]), bf_conj(ch[1]), bf_conj(ch[2]), bf_conj(ch[3])};
-                    rl[ct] = u32x4{bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
-                    ih[ct] = u32x4{bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
-                    il[ct] = u32x4{bf_swap(cl[0]), bf_swap(cl[1]), bf_swap(cl[2]), bf_swap(cl[3])};
-                }
-                const uint32_t* bh = s_Bh[wj] + 4 * gk * BPS + 16 * RXH * wh + gi;
-                const uint32_t* bl = s_Bl[wj] + 4 * gk * BPS + 16 * RXH * wh + gi;
-#pragma unroll
-                for (int m = 0; m < RXH; ++m) {
+                for (int m = 0; m < RXE; ++m) {
                     const u32x4 ah = {bh[16 * m], bh[BPS + 16 * m], bh[2 * BPS + 16 * m], bh[3 * BPS + 16 * m]};
                     const u32x4 al = {bl[16 * m], bl[BPS + 16 * m], bl[2 * BPS + 16 * m], bl[3 * BPS + 16 * m]};
-#pragma unroll
-                    for (int ct = 0; ct < 2; ++ct) {
-                        X[m][ct][0] = mfma_bf(ah, rh[ct], X[m][ct][0]);
-                        X[m][ct][0] = mfma_bf(ah, rl[ct], X[m][ct][0]);
-                        X[m][ct][0] = mfma_bf(al, rh[ct], X[m][ct][0]);
-                        X[m][ct][1] = mfma_bf(ah, ih[ct], X[m][ct][1]);
-                        X[m][ct][1] = mfma_bf(ah, il[ct], X[m][ct][1]);
-                        X[m][ct][1] = mfma_bf(al, ih[ct], X[m][ct][1]);
-                    }
+                    X[m][0] = mfma_bf(ah, rh, X[m][0]);
+                    X[m][0] = mfma_bf(ah, rl, X[m][0]);
+                    X[m][0] = mfma_bf(al, rh, X[m][0]);
+                    X[m][1] = mfma_bf(ah, ih, X[m][1]);
+                    X[m][1] = mfma_bf(ah, il, X[m][1]);
+                    X[m][1] = mfma_bf(al, ih, X[m][1]);
                 }
             }
-            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end);
+            if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end, par ^ 1);
             __syncthreads();
         }
-        // per-element partials [item][JT][TPG][N] of the wave's bin and element
-        // half; D[row][col]: row = element 16 (RXH wh + m) + 4 gk + v, col =
-        // transmit 16 ct + gi
+        // per-element partials [item][JT][TPG][N] of the wave's bin and column
+        // tile; D[row][col]: row = element 16 m + 4 gk + v, col = transmit
+        // 16 wh + gi
         if (wj < nb) {
             float2* out = A.part + ((int64_t)id * JT + wj) * TPG * A.N;
 #pragma unroll
-            for (int m = 0; m < RXH; ++m)
+            for (int m = 0; m < RXE; ++m)
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int e = 16 * (RXH * wh + m) + 4 * gk + v;
-                        if (e < A.N) out[(int64_t)(16 * ct + gi) * A.N + e] = make_float2(X[m][ct][0][v], X[m][ct][1][v]);
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const int e = 16 * m + 4 * gk + v;
+                    if (e < A.N) out[(int64_t)(16 * wh + gi) * A.N + e] = make_float2(X[m][0][v], X[m][1][v]);
+                }
         }
         if (tid == 0) s_item = atomicAdd(A.ticket, 1);
         __syncthreads();
