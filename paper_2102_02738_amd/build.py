@@ -31,7 +31,8 @@ def _compile(src: str, device: bool) -> str:
     if device:
         cmd[1:1] = ["-x", "hip", *DEVICE]
     else:
-        cmd[1:1] = ["-D__HIP_PLATFORM_AMD__"]
+        # host code only (hipcc would otherwise add a device pass for its default target)
+        cmd[1:1] = ["-D__HIP_PLATFORM_AMD__", "--offload-host-only"]
     subprocess.check_call(cmd)
     return obj
 

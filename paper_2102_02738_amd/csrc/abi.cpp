@@ -1162,6 +1162,7 @@ int simus_rf_plan_graph_launch(simus_rf_plan plan, const float* x, const float* 
 
 // ---- the autotuner's file cache: one text line per problem class,
 // "<key> <shape flags> <scatterers per item / default x 1000> <ms>"
+extern "C++" {
 namespace {
 std::mutex g_tune_mu;
 std::string g_tune_path;
@@ -1223,6 +1224,7 @@ void tune_store(const std::string& key, int32_t shape_flags, int32_t mult_permil
     if (std::fclose(f) != 0 || !ok) throw Error{SIMUS_EINVAL, "cannot append to the autotuner cache " + g_tune_path};
 }
 }  // namespace
+}  // extern "C++"
 
 int simus_tune_cache(const char* path)
 {

@@ -773,7 +773,10 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
         const int nb = min(JT, A.n_bins - jb0);
         // this wave's weights: WT[bin][tg][t = gi][e = 16 k + 4 gk .. + 3]
         const int jbw = min(jb0 + bw, A.n_bins - 1);
-        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + gi) * NE + 4 * gk;
+        // columns past the transmit count are zero in the table: their lanes
+        // all read the first of them (one cache line per load)
+        const int wc = min(gi, A.n_tx - tg * TPG);
+        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + wc) * NE + 4 * gk;
 
         // the wave's split weights are the same for every chunk of the item:
         // those of the first KH k-steps stay in registers (all of them for 64
@@ -999,7 +1002,10 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
         const int nb = min(JT, A.n_bins - jb0);
         // this wave's weights: WT[bin][tg][t = 16 wh + gi][e = 16 k + 4 gk .. + 3]
         const int jbw = min(jb0 + wj, A.n_bins - 1);
-        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + 16 * wh + gi) * NE + 4 * gk;
+        // columns past the transmit count are zero in the table: their lanes
+        // all read the first of them (one cache line per load)
+        const int wc = min(16 * wh + gi, A.n_tx - tg * TPG);
+        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + wc) * NE + 4 * gk;
         // the weights of the first KH k-steps stay in registers for the item
         // (all of them for 64 element slots, half for 128 without y: 21 plane
         // waves, 200k scatterers 112.6 -> 101.1 ms)
