@@ -300,10 +300,13 @@ __global__ __launch_bounds__(512) void k_adjoint_mt(AdjArgs A)
 //       products: wave w, bin w / 2, row tile w % 2.
 // BF: the GEMM's products as three products of bf16 high and low parts
 // (v_mfma_f32_16x16x32_bf16, FP32 accumulation, about 2^-16 of each
-// product, as in k_synth_mb): the element sums are split into two LDS planes
-// of packed (re, im) words and the table holds WL[p][bin][col][e] as (h, l)
-// words; otherwise FP32 16x16x4 MFMAs with three products per complex
-// product and WL[p][bin][e][col] as float2.
+// product, as in k_synth_mb): the element sums go to LDS in FP32 and the
+// GEMM wave splits each once as it reads it (splitting in the synthesis,
+// where both lanes of a sub-element pair split the same sum, took 72.8 ms
+// instead of 69.6 on 5 plane waves, 100k scatterers, results
+// bit-identical); the table holds WL[p][bin][col][e] as (h, l) words.
+// Otherwise FP32 16x16x4 MFMAs with three products per complex product and
+// WL[p][bin][e][col] as float2.
 // Lanes of a scatterer are summed once per chunk (transmits and bins, in a
 // fixed order).
 template <int NUV, bool HASY, bool TABLE, bool BF>
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
     constexpr int SCH = adj_mt_chunk(NUV, HASY);   // scatterers per chunk
     constexpr int NL = SCH == 10 ? 3 : 4;   // rows per scatterer: B, dB/dx, dB/dz(, dB/dy)
     constexpr int ROWS = 32;                // SCH NL rows, the rest zero
-    constexpr int LST = BF ? NE + 4 : NE + 2;   // row stride of the element sums (words / float2)
+    constexpr int LST = BF ? NE + 4 : NE + 2;   // row stride (float2) of the element sums
     constexpr int TG = 8;                   // transmits
     constexpr int NC = 2 * TG;              // columns: W, then Lam
     constexpr int VST = NC + 2;             // row stride of V
@@ -334,7 +337,8 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
     static_assert(TG * JB == 32, "a scatterer's gradient lanes are 32 consecutive lanes");
 
     __shared__ float4 s_sc[SCH];
-    // BF: planes [h, l] of packed words; else one plane of float2 (two words each)
+    // the element sums: one plane of float2 [row][LST] (BF: over both halves of
+    // the array, LST = 132; else LST = 130)
     __shared__ __align__(16) uint32_t s_L[JB][NPL][ROWS * LST * (BF ? 1 : 2)];
     __shared__ float2 s_V[JB][ROWS * VST];
     __shared__ float4 s_tab[TABLE ? 2 * DELTA_NT : 1];
@@ -433,15 +437,13 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
                             const int e = NUV == 2 ? (n >> 1) : n;
                             const int at = (s * NL + L) * LST + e;
                             if constexpr (BF) {
-                                const uint32_t h = pack_bf16(b.x, b.y);
-                                const uint32_t l = pack_bf16(b.x - bf16_lo(h), b.y - bf16_hi(h));
-                                if (NUV == 2) {
-                                    // the pair's even lane stores the high part, the odd one the low part
-                                    s_L[jj][n & 1][at] = (n & 1) ? l : h;
-                                } else {
-                                    s_L[jj][0][at] = h;
-                                    s_L[jj][1][at] = l;
-                                }
+                                // FP32 element sums, float2 [row][LST]; the GEMM
+                                // wave splits them.  nu = 2: the pair's even
+                                // lane stores Re, the odd one Im
+                                if (NUV == 2)
+                                    reinterpret_cast<float*>(s_L[jj][0])[2 * at + (n & 1)] = (n & 1) ? b.y : b.x;
+                                else
+                                    reinterpret_cast<float2*>(s_L[jj][0])[at] = b;
                             } else {
                                 reinterpret_cast<float2*>(s_L[jj][0])[at] = b;
                             }
@@ -482,10 +484,18 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
                             const u32x4 il = {bf_swap(wlo[0]), bf_swap(wlo[1]), bf_swap(wlo[2]), bf_swap(wlo[3])};
 #pragma unroll
                             for (int r = 0; r < 2; ++r) {
-                                const int o = (r * 16 + gi) * LST + 16 * k + 4 * gk;
-                                const uint4 ah4 = *reinterpret_cast<const uint4*>(s_L[bj][0] + o);
-                                const uint4 al4 = *reinterpret_cast<const uint4*>(s_L[bj][1] + o);
-                                const u32x4 ah = {ah4.x, ah4.y, ah4.z, ah4.w}, al = {al4.x, al4.y, al4.z, al4.w};
+                                // elements 16 k + 4 gk .. + 3 of row 16 r + gi, split
+                                const float2* pf = reinterpret_cast<const float2*>(s_L[bj][0]) + (r * 16 + gi) * LST + 16 * k + 4 * gk;
+                                const float4 f01 = *reinterpret_cast<const float4*>(pf);
+                                const float4 f23 = *reinterpret_cast<const float4*>(pf + 2);
+                                const float fx[4] = {f01.x, f01.z, f23.x, f23.z}, fy[4] = {f01.y, f01.w, f23.y, f23.w};
+                                u32x4 ah, al;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const uint32_t h = pack_bf16(fx[q], fy[q]);
+                                    ah[q] = h;
+                                    al[q] = pack_bf16(fx[q] - bf16_lo(h), fy[q] - bf16_hi(h));
+                                }
                                 re[r] = mfma_bf(ah, rh, re[r]);
                                 re[r] = mfma_bf(ah, rl, re[r]);
                                 re[r] = mfma_bf(al, rh, re[r]);
