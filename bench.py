@@ -401,7 +401,7 @@ def _pfield_case(workload: str, probe: dict, dl, X, Z, steps: int) -> dict:
                 kernel_ms=k_ms,
                 roofline=dict(bound="alu", achieved=alg / (k_ms * 1e-3) / 1e12, peak=VALU_PEAK / 1e12,
                               unit="TOP/s", frac=alg / (k_ms * 1e-3) / VALU_PEAK, traffic=None,
-                              kernel="k_pfield<16, false, true>",
+                              kernel="k_pfield<24, false, true>",
                               work_per_unit=dict(term=PF_TERM_SLOTS, point_bin=PF_POINT_BIN_SLOTS)),
                 finite=bool(torch.isfinite(out["p"]).all()))
 

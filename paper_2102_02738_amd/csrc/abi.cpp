@@ -839,10 +839,13 @@ void pfield(const simus_probe* probe, const simus_medium* medium, const simus_op
     C.ph.total = n_pts;
     // frequency ranges of nearly equal size, each split into tiles of at
     // most PFIELD_JT bins: as many ranges as tiles, up to about 6 rounds of
-    // resident blocks (5 per CU) over the point blocks
+    // resident blocks (5 per CU) over the point blocks; past that, ranges of
+    // a whole number of tiles each, so that the tiles stay nearly full
     const int64_t n_pb = (n_pts + 255) / 256;
-    const int64_t n_tl = (n_f + PFIELD_JT - 1) / PFIELD_JT;
-    const int n_ranges = (int)std::max<int64_t>(1, std::min<int64_t>(n_tl, (6 * 1280 + n_pb - 1) / n_pb));
+    const int64_t n_tl = std::max<int64_t>(1, (n_f + PFIELD_JT - 1) / PFIELD_JT);
+    const int64_t cap = std::max<int64_t>(1, (6 * 1280 + n_pb - 1) / n_pb);
+    const int64_t tiles_per_range = (n_tl + cap - 1) / cap;
+    const int n_ranges = (int)((n_tl + tiles_per_range - 1) / tiles_per_range);
     if (n_pb > 0x7fffffff || n_ranges > 65535) throw Error{SIMUS_EINVAL, "too many field points"};
 
     Layout up;

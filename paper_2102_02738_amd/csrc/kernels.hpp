@@ -193,7 +193,10 @@ struct FieldArgs {
 // on the 64-element, 256 x 256-point, 402-frequency field: 8 -> 1.74 ms,
 // 16 -> 1.58 ms, 32 -> 1.66 ms (registers halve the occupancy); with the
 // balanced ranges and tiles, 16 -> 1.48 ms, 24 -> 1.49 ms, 32 -> 1.70 ms.
-constexpr int PFIELD_JT = 16;
+// On the 128-element, 705-frequency field, whose 30 ranges of 23-24 bins
+// took two tiles each at 16: 16 -> 9.57 ms, 20 -> 9.86, 24 -> 8.66 (107
+// registers, four waves per SIMD), 28 -> 8.72.
+constexpr int PFIELD_JT = 24;
 hipError_t launch_pfield(const FieldArgs& a, bool has_y, bool table, int n_ranges, hipStream_t st);
 hipError_t launch_pfield_reduce(const float* part, int n_ranges, int64_t n_pts, float dw, float* out,
                                 hipStream_t st);
