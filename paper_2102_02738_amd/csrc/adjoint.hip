@@ -207,11 +207,12 @@ hipError_t launch_dft_t(float2* lam, const float* rho, int64_t n_chan, int n_bin
 }
 
 // Bins per tile of the vector adjoint for tt transmits per group, measured
-// (100k scatterers): one transmit 4 bins (126 VGPRs, four waves per SIMD;
-// 64.0 ms against 70.5 with 8), two transmits 4 (88.5 ms; 2 bins 96.7),
+// (100k scatterers): one transmit 6 bins (158 VGPRs, three waves per SIMD;
+// 53.9 ms against 55.1 with 5 and 60.4 with 4 at four waves per SIMD, and
+// 70.5 with 8 at two on an earlier build), two transmits 4 (88.5 ms; 2 bins 96.7),
 // four transmits 1 (64 elements: 65.2 ms; 2 bins 67.1); with y != 0 two
 // transmits take 2 bins (4 would need 239 VGPRs).
-constexpr int adj_jt(int tt, bool has_y) { return tt == 1 ? 4 : tt == 2 ? (has_y ? 2 : 4) : 1; }
+constexpr int adj_jt(int tt, bool has_y) { return tt == 1 ? 6 : tt == 2 ? (has_y ? 2 : 4) : 1; }
 
 AdjConfig adjoint_config(int n_tx, bool has_y)
 {
@@ -243,7 +244,7 @@ hipError_t launch_adjoint(const AdjConfig& c, const AdjArgs& a, int n_items, hip
     // the kernel's tile must be the one the item ranges were cut for
     if (c.jt != adj_jt(c.tt, c.has_y)) return hipErrorInvalidValue;
     switch (c.tt) {
-    case 1: return launch_adj_jt<4, 1>(c, a, n_items, st);
+    case 1: return launch_adj_jt<6, 1>(c, a, n_items, st);
     case 2: return c.has_y ? launch_adj_jt<2, 2>(c, a, n_items, st) : launch_adj_jt<4, 2>(c, a, n_items, st);
     case 4: return launch_adj_jt<1, 4>(c, a, n_items, st);
     case 8: return c.has_y ? hipErrorInvalidValue : launch_adj_jt<1, 8>(c, a, n_items, st);
