@@ -625,6 +625,10 @@ static MtShape mt_shape(int N, int n_tx, bool alt, bool fp32)
     // plane waves, 200k scatterers 112 vs 158 ms over two groups of 16; 128
     // focused transmits on 64 elements 19.8 vs 26.1 ms; 40 plane waves, 100k
     // scatterers 119 vs 122 ms.
+    // More than 32 transmits on 64 element slots: groups of 64 columns, two
+    // column tiles per wave (128 focused transmits on 64 elements 17.2 vs
+    // 14.1 ms with groups of 32).
+    if (!alt && n_tx > 32 && !fp32 && N <= 64) return {64, 4, 4, 2};
     if (!alt && n_tx > 16 && !fp32) return {N <= 64 ? 64 : 128, 2, 4, 2};
     if (!alt) return {N <= 64 ? 64 : 128, 1, 8, N <= 64 ? MQ_NX64 : MQ_NX};
     // the alternative, k_synth_mt: 64 element slots, 6 bins per item, groups
@@ -930,20 +934,21 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     }
 }
 
-// More than 16 transmits: groups of 32 transmit columns, four bins per item,
+// More than 16 transmits: groups of 32 transmit columns (64 with CPW = 2,
+// for 64 element slots and more than 32 transmits), four bins per item,
 // split-bf16 products as in k_synth_mb.  The Green's terms of a pair are
-// synthesised once per 32 transmits (twice over two groups of 16 in
-// k_synth_mb), at the price of a set-up every four bins.  Wave w = (bin
-// w / 2, column tile w % 2):
+// synthesised once per group (twice over two groups of 16 in k_synth_mb),
+// at the price of a set-up every four bins.  Wave w = (bin w / 2, CPW
+// column tiles from CPW (w % 2)):
 //   P1  every thread: set-up and the element sums of the four bins, split;
-//   P2  the transmit GEMM of its bin and column tile (16 transmits);
-//   P3  the receive GEMM of its bin and column tile over all elements, into
+//   P2  the transmit GEMM of its bin and column tiles (16 CPW transmits);
+//   P3  the receive GEMM of its bin and column tiles over all elements, into
 //       its registers, from the c of P2 kept in registers as in k_synth_mb
 //       (two barriers per chunk).  With the receive GEMM over element halves
 //       and both column tiles, c went through LDS with a barrier between the
 //       GEMMs: 128 focused transmits on 64 elements 18.8 -> 17.3 ms, 21
 //       plane waves 101.0 -> 100.2 ms (results bit-identical).
-template <int NE, int NUV, bool HASY, bool TABLE>
+template <int NE, int NUV, bool HASY, bool TABLE, int CPW>
 __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
 {
     constexpr int NB = 512;
@@ -952,13 +957,14 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
     constexpr int PPT = SCH * MS / NB;      // pairs per synthesis thread
     constexpr int NSG = NB / MS;            // scatterer groups
     constexpr int JT = 4;                   // bins per item: two waves per bin
-    constexpr int TPG = 32;                 // transmit columns: two tiles of 16
+    constexpr int TPG = 32 * CPW;           // transmit columns: two halves of CPW tiles of 16
     constexpr int BPS = NE + 4;             // row stride (words) of the element-sum planes
     constexpr int KS = NE / 16;             // transmit-GEMM k-steps (16 elements each)
     constexpr int RXE = NE / 16;            // receive element tiles
     static_assert(NE == 64 || NE == 128, "64 or 128 element slots");
     static_assert(NUV == 1 || NUV == 2, "nu must be 1 or 2");
     static_assert(PPT * NSG == SCH, "threads must cover the chunk");
+    static_assert(CPW == 1 || (CPW == 2 && NE == 64), "two column tiles per wave for 64 slots only");
 
     __shared__ float4 s_sc[2][SCH];          // by chunk parity
     __shared__ __align__(16) uint32_t s_Bh[JT][SCH * BPS];
@@ -1000,27 +1006,38 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
         const int bt = it.tile & 0xffff, tg = it.tile >> 16;
         const int jb0 = bt * JT;
         const int nb = min(JT, A.n_bins - jb0);
-        // this wave's weights: WT[bin][tg][t = 16 wh + gi][e = 16 k + 4 gk .. + 3]
+        // this wave's weights: WT[bin][tg][t = 16 (CPW wh + ct) + gi][e = 16 k + 4 gk .. + 3]
         const int jbw = min(jb0 + wj, A.n_bins - 1);
         // columns past the transmit count are zero in the table: their lanes
         // all read the first of them (one cache line per load)
-        const int wc = min(16 * wh + gi, A.n_tx - tg * TPG);
-        const uint2* wg = WTb + (((int64_t)jbw * n_tg + tg) * TPG + wc) * NE + 4 * gk;
+        const uint2* wg[CPW];
+#pragma unroll
+        for (int ct = 0; ct < CPW; ++ct) {
+            const int wc = min(16 * (CPW * wh + ct) + gi, A.n_tx - tg * TPG);
+            wg[ct] = WTb + (((int64_t)jbw * n_tg + tg) * TPG + wc) * NE + 4 * gk;
+        }
         // the weights of the first KH k-steps stay in registers for the item
         // (all of them for 64 element slots, half for 128 without y: 21 plane
-        // waves, 200k scatterers 112.6 -> 101.1 ms)
-        constexpr int KH = NE == 64 ? KS : HASY ? 0 : KS / 2;
-        uint4 wr[KS][2];
+        // waves, 200k scatterers 112.6 -> 101.1 ms; half with two column tiles
+        // per wave, where all spill 26 dwords: 128 focused transmits on 64
+        // elements 14.1 ms, 15.6 with three of four k-steps, 19.7 with none)
+        constexpr int KH = CPW == 2 ? (HASY ? 0 : KS / 2) : NE == 64 ? KS : HASY ? 0 : KS / 2;
+        uint4 wr[CPW][KS][2];
 #pragma unroll
-        for (int k = 0; k < KH; ++k) {
-            const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
-            wr[k][0] = q[0];
-            wr[k][1] = q[1];
-        }
-        // receive sums of the wave's bin and column tile: element tiles x (Re, Im)
-        floatx4 X[RXE][2];
+        for (int ct = 0; ct < CPW; ++ct)
 #pragma unroll
-        for (int m = 0; m < RXE; ++m) X[m][0] = X[m][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < KH; ++k) {
+                const uint4* q = reinterpret_cast<const uint4*>(wg[ct] + 16 * k);
+                wr[ct][k][0] = q[0];
+                wr[ct][k][1] = q[1];
+            }
+        // receive sums of the wave's bin and column tiles: element tiles x
+        // column tiles x (Re, Im)
+        floatx4 X[RXE][CPW][2];
+#pragma unroll
+        for (int m = 0; m < RXE; ++m)
+#pragma unroll
+            for (int ct = 0; ct < CPW; ++ct) X[m][ct][0] = X[m][ct][1] = floatx4{0.f, 0.f, 0.f, 0.f};
 
         load_chunk(it.s_begin, it.s_end, 0);
         __syncthreads();
@@ -1067,16 +1084,20 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
             }
             // the rest of the wave's split weights, per chunk
 #pragma unroll
-            for (int k = KH; k < KS; ++k) {
-                const uint4* q = reinterpret_cast<const uint4*>(wg + 16 * k);
-                wr[k][0] = q[0];
-                wr[k][1] = q[1];
-            }
+            for (int ct = 0; ct < CPW; ++ct)
+#pragma unroll
+                for (int k = KH; k < KS; ++k) {
+                    const uint4* q = reinterpret_cast<const uint4*>(wg[ct] + 16 * k);
+                    wr[ct][k][0] = q[0];
+                    wr[ct][k][1] = q[1];
+                }
             __syncthreads();
-            uint32_t ch[4], cl[4];
-            // ---- P2: transmit GEMM of bin wj, column tile wh: rows s = gi,
-            //      columns t = 16 wh + gi, k = (element 16 k + 4 gk + q, Re/Im)
-            {
+            uint32_t ch[CPW][4], cl[CPW][4];
+            // ---- P2: transmit GEMM of bin wj, column tiles CPW wh .. + CPW - 1:
+            //      rows s = gi, columns t = 16 (CPW wh + ct) + gi, k = (element
+            //      16 k + 4 gk + q, Re/Im)
+#pragma unroll
+            for (int ct = 0; ct < CPW; ++ct) {
                 const uint32_t* bh = s_Bh[wj] + gi * BPS + 4 * gk;
                 const uint32_t* bl = s_Bl[wj] + gi * BPS + 4 * gk;
                 floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = re;
@@ -1085,8 +1106,8 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                     const uint4 ah4 = *reinterpret_cast<const uint4*>(bh + 16 * k);
                     const uint4 al4 = *reinterpret_cast<const uint4*>(bl + 16 * k);
                     const u32x4 ah = {ah4.x, ah4.y, ah4.z, ah4.w}, al = {al4.x, al4.y, al4.z, al4.w};
-                    const uint32_t wh4[4] = {wr[k][0].x, wr[k][0].z, wr[k][1].x, wr[k][1].z};
-                    const uint32_t wl4[4] = {wr[k][0].y, wr[k][0].w, wr[k][1].y, wr[k][1].w};
+                    const uint32_t wh4[4] = {wr[ct][k][0].x, wr[ct][k][0].z, wr[ct][k][1].x, wr[ct][k][1].z};
+                    const uint32_t wl4[4] = {wr[ct][k][0].y, wr[ct][k][0].w, wr[ct][k][1].y, wr[ct][k][1].w};
                     const u32x4 rh = {bf_conj(wh4[0]), bf_conj(wh4[1]), bf_conj(wh4[2]), bf_conj(wh4[3])};
                     const u32x4 rl = {bf_conj(wl4[0]), bf_conj(wl4[1]), bf_conj(wl4[2]), bf_conj(wl4[3])};
                     const u32x4 ih = {bf_swap(wh4[0]), bf_swap(wh4[1]), bf_swap(wh4[2]), bf_swap(wh4[3])};
@@ -1098,55 +1119,65 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                     im = mfma_bf(ah, il, im);
                     im = mfma_bf(al, ih, im);
                 }
-                // D[row][col]: row s = 4 gk + v, col t = 16 wh + gi; c = R_s a,
-                // split.  The receive GEMM's B operand takes k = (scatterer
-                // 4 gk + q, Re/Im) and column gi in the same lane: c stays in
-                // registers
+                // D[row][col]: row s = 4 gk + v, col t = 16 (CPW wh + ct) + gi;
+                // c = R_s a, split.  The receive GEMM's B operand takes k =
+                // (scatterer 4 gk + q, Re/Im) and column gi in the same lane: c
+                // stays in registers
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const float R = s_sc[par][4 * gk + v].w;
                     const float cx = R * re[v], cy = R * im[v];
-                    ch[v] = pack_bf16(cx, cy);
-                    cl[v] = pack_bf16(cx - bf16_lo(ch[v]), cy - bf16_hi(ch[v]));
+                    ch[ct][v] = pack_bf16(cx, cy);
+                    cl[ct][v] = pack_bf16(cx - bf16_lo(ch[ct][v]), cy - bf16_hi(ch[ct][v]));
                 }
             }
-            // ---- P3: receive GEMM of bin wj, column tile wh, all element
-            //      tiles, k = (scatterer 4 gk + q, Re/Im); the next chunk's
-            //      scatterers
+            // ---- P3: receive GEMM of bin wj, the wave's column tiles, all
+            //      element tiles, k = (scatterer 4 gk + q, Re/Im); the next
+            //      chunk's scatterers
             {
-                const u32x4 rh = {bf_conj(ch[0]), bf_conj(ch[1]), bf_conj(ch[2]), bf_conj(ch[3])};
-                const u32x4 rl = {bf_conj(cl[0]), bf_conj(cl[1]), bf_conj(cl[2]), bf_conj(cl[3])};
-                const u32x4 ih = {bf_swap(ch[0]), bf_swap(ch[1]), bf_swap(ch[2]), bf_swap(ch[3])};
-                const u32x4 il = {bf_swap(cl[0]), bf_swap(cl[1]), bf_swap(cl[2]), bf_swap(cl[3])};
+                u32x4 rh[CPW], rl[CPW], ih[CPW], il[CPW];
+#pragma unroll
+                for (int ct = 0; ct < CPW; ++ct) {
+                    rh[ct] = u32x4{bf_conj(ch[ct][0]), bf_conj(ch[ct][1]), bf_conj(ch[ct][2]), bf_conj(ch[ct][3])};
+                    rl[ct] = u32x4{bf_conj(cl[ct][0]), bf_conj(cl[ct][1]), bf_conj(cl[ct][2]), bf_conj(cl[ct][3])};
+                    ih[ct] = u32x4{bf_swap(ch[ct][0]), bf_swap(ch[ct][1]), bf_swap(ch[ct][2]), bf_swap(ch[ct][3])};
+                    il[ct] = u32x4{bf_swap(cl[ct][0]), bf_swap(cl[ct][1]), bf_swap(cl[ct][2]), bf_swap(cl[ct][3])};
+                }
                 const uint32_t* bh = s_Bh[wj] + 4 * gk * BPS + gi;
                 const uint32_t* bl = s_Bl[wj] + 4 * gk * BPS + gi;
 #pragma unroll
                 for (int m = 0; m < RXE; ++m) {
                     const u32x4 ah = {bh[16 * m], bh[BPS + 16 * m], bh[2 * BPS + 16 * m], bh[3 * BPS + 16 * m]};
                     const u32x4 al = {bl[16 * m], bl[BPS + 16 * m], bl[2 * BPS + 16 * m], bl[3 * BPS + 16 * m]};
-                    X[m][0] = mfma_bf(ah, rh, X[m][0]);
-                    X[m][0] = mfma_bf(ah, rl, X[m][0]);
-                    X[m][0] = mfma_bf(al, rh, X[m][0]);
-                    X[m][1] = mfma_bf(ah, ih, X[m][1]);
-                    X[m][1] = mfma_bf(ah, il, X[m][1]);
-                    X[m][1] = mfma_bf(al, ih, X[m][1]);
+#pragma unroll
+                    for (int ct = 0; ct < CPW; ++ct) {
+                        X[m][ct][0] = mfma_bf(ah, rh[ct], X[m][ct][0]);
+                        X[m][ct][0] = mfma_bf(ah, rl[ct], X[m][ct][0]);
+                        X[m][ct][0] = mfma_bf(al, rh[ct], X[m][ct][0]);
+                        X[m][ct][1] = mfma_bf(ah, ih[ct], X[m][ct][1]);
+                        X[m][ct][1] = mfma_bf(ah, il[ct], X[m][ct][1]);
+                        X[m][ct][1] = mfma_bf(al, ih[ct], X[m][ct][1]);
+                    }
                 }
             }
             if (s0 + SCH < it.s_end) load_chunk(s0 + SCH, it.s_end, par ^ 1);
             __syncthreads();
         }
         // per-element partials [item][JT][TPG][N] of the wave's bin and column
-        // tile; D[row][col]: row = element 16 m + 4 gk + v, col = transmit
-        // 16 wh + gi
+        // tiles; D[row][col]: row = element 16 m + 4 gk + v, col = transmit
+        // 16 (CPW wh + ct) + gi
         if (wj < nb) {
             float2* out = A.part + ((int64_t)id * JT + wj) * TPG * A.N;
 #pragma unroll
             for (int m = 0; m < RXE; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int e = 16 * m + 4 * gk + v;
-                    if (e < A.N) out[(int64_t)(16 * wh + gi) * A.N + e] = make_float2(X[m][0][v], X[m][1][v]);
-                }
+                for (int ct = 0; ct < CPW; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int e = 16 * m + 4 * gk + v;
+                        if (e < A.N)
+                            out[(int64_t)(16 * (CPW * wh + ct) + gi) * A.N + e] = make_float2(X[m][ct][0][v], X[m][ct][1][v]);
+                    }
         }
         if (tid == 0) s_item = atomicAdd(A.ticket, 1);
         __syncthreads();
@@ -1154,12 +1185,12 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
     }
 }
 
-template <int NE, int NUV>
+template <int NE, int NUV, int CPW = 1>
 static SynthKernel mw_kernel_nuv(const SynthConfig& c)
 {
-    if (c.has_y) return k_synth_mw<NE, NUV, true, false>;
-    if (c.table) return k_synth_mw<NE, NUV, false, true>;
-    return k_synth_mw<NE, NUV, false, false>;
+    if (c.has_y) return k_synth_mw<NE, NUV, true, false, CPW>;
+    if (c.table) return k_synth_mw<NE, NUV, false, true, CPW>;
+    return k_synth_mw<NE, NUV, false, false, CPW>;
 }
 
 template <int NE, int NUV>
@@ -1180,6 +1211,8 @@ static SynthKernel mq_kernel_nuv(const SynthConfig& c)
 
 SynthKernel synth_mt_kernel(const SynthConfig& c)
 {
+    if (c.bf && c.wt && c.tt == 64 && c.jt == 4 && c.ne == 64)
+        return c.pair ? mw_kernel_nuv<64, 2, 2>(c) : mw_kernel_nuv<64, 1, 2>(c);
     if (c.bf && c.wt && c.tt == 32 && c.jt == 4) {
         if (c.ne == 128) return c.pair ? mw_kernel_nuv<128, 2>(c) : mw_kernel_nuv<128, 1>(c);
         if (c.ne == 64) return c.pair ? mw_kernel_nuv<64, 2>(c) : mw_kernel_nuv<64, 1>(c);

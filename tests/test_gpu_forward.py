@@ -198,13 +198,15 @@ def test_empty_and_degenerate(S):
     (21, 32, 0, False, False), (33, 32, 0, False, False), (6, 32, 0, True, False),
     (12, 64, 1, False, False), (5, 200, 1, False, False), (21, 32, 0, False, True),
     (11, 100, 0, False, False), (40, 128, 0, False, False), (70, 48, 1, False, False),
-    (24, 100, 0, True, False), (20, 40, 1, True, False)])
+    (24, 100, 0, True, False), (20, 40, 1, True, False), (36, 40, 1, True, False),
+    (45, 20, 2, False, False)])
 def test_many_transmits(S, orc, n_tx, n_el, nu, with_y, no_mfma):
     """Many steered plane waves: the transmit contraction on the matrix cores
     (or, with the flag, on the VALU path) matches the oracle; covers the
     default kernels with 64 and 128 element slots: eight bins over groups of
     16 transmit columns up to 16 transmits, four bins over one to three
-    groups of 32 above,
+    groups of 32 above (of 64, two column tiles per wave, above 32 transmits
+    on 64 slots: nu = 1 and 2, y != 0),
     several transmit groups with a ragged last one, y != 0, nu = 1 and 200
     elements (vector path)."""
     from paper_2102_02738_amd import inputs
