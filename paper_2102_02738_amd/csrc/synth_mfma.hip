@@ -701,6 +701,7 @@ SynthConfig mt_config(int M, int N, int n_tx, bool has_y, bool alt, bool fp32)
 //   P1  pair by pair (its set-up, then its eight bins with their table
 //       fetches in flight together: 6 % faster than bin by bin over all
 //       pairs), element sums, split, into two LDS planes per bin (h and l);
+//       for nu = 2 a thread takes both sub-elements of an element;
 //   P2  wave w, bin w: a[s][t] = sum_e B[s][e] W[e][t], 8 (NE = 128) or 4
 //       k-steps of 16 elements, 6 MFMAs each; weights from the split table
 //       WT[bin][group][t][e] (uint2: h, l); c = R_s a, split;
@@ -745,9 +746,13 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
     const int wave = tid >> 6, lane = tid & 63;
     const int gi = lane & 15, gk = lane >> 4;      // MFMA lane roles: row/column, k block
     const int bw = wave;                           // the wave's bin in both GEMMs
+    // synthesis role: nu = 1, thread = (sub-element n, scatterer group sh);
+    // nu = 2, thread = (element ne, scatterer group sge), both sub-elements
     const int n = tid % MS, sh = tid / MS;
-    const bool active = n < A.M;
-    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    const int ne = tid % NE, sge = tid / NE;
+    const bool active = NUV == 2 ? 2 * ne < A.M : n < A.M;
+    const SubFrame fr = load_frame(A.sub, NUV == 2 ? (active ? 2 * ne : 0) : (active ? n : 0));
+    const SubFrame fr1 = load_frame(A.sub, NUV == 2 && active ? 2 * ne + 1 : 0);
     const int n_tg = (A.n_tx + TPG - 1) / TPG;
     const uint2* WTb = reinterpret_cast<const uint2*>(A.WT);
 
@@ -785,10 +790,11 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
         // the wave's split weights are the same for every chunk of the item:
         // those of the first KH k-steps stay in registers (all of them for 64
         // element slots; the first half for 128, where all would spill 72
-        // dwords; none with y, which then spills 19): 128 focused transmits
-        // on a 64-element array 30.7 -> 26.3 ms, a quarter of the uneven
-        // 16-phantom batch 255.7 -> 251.2 ms
-        constexpr int KH = NE == 64 ? KS : HASY ? 0 : KS / 2;
+        // dwords, three of eight for nu = 2, whose synthesis holds both
+        // sub-elements' sums; none with y, which then spills 19): 128 focused
+        // transmits on a 64-element array 30.7 -> 26.3 ms, a quarter of the
+        // uneven 16-phantom batch 255.7 -> 251.2 ms
+        constexpr int KH = NE == 64 ? KS : HASY ? 0 : NUV == 2 ? 3 : KS / 2;
         uint4 wr[KS][2];
 #pragma unroll
         for (int k = 0; k < KH; ++k) {
@@ -808,6 +814,46 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
             //      (set-up, then its eight bins), so that one pair's state is
             //      live at a time and its eight table fetches are in flight
             //      together
+            if constexpr (NUV == 2) {
+                // both sub-elements of element ne in one thread: their sum
+                // is split once (a lane per sub-element, summed by a DPP
+                // exchange and split by both lanes: a quarter of the uneven
+                // 16-phantom batch 227.5 -> 202.7 ms, results bit-identical)
+                constexpr int PPS = SCH * NE / NB;   // scatterers per thread
+#pragma unroll 1
+                for (int k = 0; k < PPS; ++k) {
+                    const int s = sge * PPS + k;
+                    const float4 v = s_sc[par][s];
+                    float2 B[JT];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        Geo g = make_geo<HASY, true>(A.K, u ? fr1 : fr, v.x, v.y, v.z, A.j_lo + jb0);
+                        if (!active) g.E = make_float2(0.f, 0.f);
+                        if (TABLE) g.kap *= P.kscale;             // delta_fetch's argument
+                        float2 G[JT];
+                        if constexpr (TABLE) {
+                            DeltaFetch fch[JT];
+#pragma unroll
+                            for (int jj = 0; jj < JT; ++jj) fch[jj] = delta_fetch(s_tab, P, (float)(A.j_lo + jb0 + jj) * g.kap);
+#pragma unroll
+                            for (int jj = 0; jj < JT; ++jj) G[jj] = green_next_fetched(g, fch[jj]);
+                        } else {
+#pragma unroll
+                            for (int jj = 0; jj < JT; ++jj)
+                                G[jj] = green_next<HASY, TABLE>(A.K, g, (float)(A.j_lo + jb0 + jj), 1.f, s_tab, P);
+                        }
+#pragma unroll
+                        for (int jj = 0; jj < JT; ++jj)
+                            B[jj] = u ? make_float2(B[jj].x + G[jj].x, B[jj].y + G[jj].y) : G[jj];
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < JT; ++jj) {
+                        const uint32_t h = pack_bf16(B[jj].x, B[jj].y);
+                        s_Bh[jj][s * BPS + ne] = h;
+                        s_Bl[jj][s * BPS + ne] = pack_bf16(B[jj].x - bf16_lo(h), B[jj].y - bf16_hi(h));
+                    }
+                }
+            } else {
 #pragma unroll 1
             for (int k = 0; k < PPT; ++k) {
                 const int s = sh * PPT + k;
@@ -846,6 +892,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                         s_Bl[jj][s * BPS + e] = l;
                     }
                 }
+            }
             }
             // the rest of the wave's split weights, per chunk
 #pragma unroll
@@ -976,9 +1023,13 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
     const int wave = tid >> 6, lane = tid & 63;
     const int gi = lane & 15, gk = lane >> 4;      // MFMA lane roles: row/column, k block
     const int wj = wave >> 1, wh = wave & 1;       // the wave's bin and half
+    // synthesis role: nu = 1, thread = (sub-element n, scatterer group sh);
+    // nu = 2, thread = (element ne, scatterer group sge), both sub-elements
     const int n = tid % MS, sh = tid / MS;
-    const bool active = n < A.M;
-    const SubFrame fr = load_frame(A.sub, active ? n : 0);
+    const int ne = tid % NE, sge = tid / NE;
+    const bool active = NUV == 2 ? 2 * ne < A.M : n < A.M;
+    const SubFrame fr = load_frame(A.sub, NUV == 2 ? (active ? 2 * ne : 0) : (active ? n : 0));
+    const SubFrame fr1 = load_frame(A.sub, NUV == 2 && active ? 2 * ne + 1 : 0);
     const int n_tg = (A.n_tx + TPG - 1) / TPG;
     const uint2* WTb = reinterpret_cast<const uint2*>(A.WT);
 
@@ -1020,8 +1071,9 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
         // (all of them for 64 element slots, half for 128 without y: 21 plane
         // waves, 200k scatterers 112.6 -> 101.1 ms; half with two column tiles
         // per wave, where all spill 26 dwords: 128 focused transmits on 64
-        // elements 14.1 ms, 15.6 with three of four k-steps, 19.7 with none)
-        constexpr int KH = CPW == 2 ? (HASY ? 0 : KS / 2) : NE == 64 ? KS : HASY ? 0 : KS / 2;
+        // elements 14.1 ms, 15.6 with three of four k-steps, 19.7 with none;
+        // one for nu = 2, whose synthesis holds both sub-elements' sums)
+        constexpr int KH = CPW == 2 ? (HASY ? 0 : NUV == 2 ? 1 : KS / 2) : NE == 64 ? KS : HASY ? 0 : KS / 2;
         uint4 wr[CPW][KS][2];
 #pragma unroll
         for (int ct = 0; ct < CPW; ++ct)
@@ -1044,6 +1096,45 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
         for (int s0 = it.s_begin, par = 0; s0 < it.s_end; s0 += SCH, par ^= 1) {
             // ---- P1: the element sums of the four bins, split; pair by pair
             //      (set-up, then its four bins)
+            if constexpr (NUV == 2) {
+                // both sub-elements of element ne in one thread: their sum
+                // is split once (21 plane waves, 200k scatterers 99.5 -> 88.9
+                // ms, results bit-identical)
+                constexpr int PPS = SCH * NE / NB;   // scatterers per thread
+#pragma unroll 1
+                for (int k = 0; k < PPS; ++k) {
+                    const int s = sge * PPS + k;
+                    const float4 v = s_sc[par][s];
+                    float2 B[JT];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        Geo g = make_geo<HASY, true>(A.K, u ? fr1 : fr, v.x, v.y, v.z, A.j_lo + jb0);
+                        if (!active) g.E = make_float2(0.f, 0.f);
+                        if (TABLE) g.kap *= P.kscale;             // delta_fetch's argument
+                        float2 G[JT];
+                        if constexpr (TABLE) {
+                            DeltaFetch fch[JT];
+#pragma unroll
+                            for (int jj = 0; jj < JT; ++jj) fch[jj] = delta_fetch(s_tab, P, (float)(A.j_lo + jb0 + jj) * g.kap);
+#pragma unroll
+                            for (int jj = 0; jj < JT; ++jj) G[jj] = green_next_fetched(g, fch[jj]);
+                        } else {
+#pragma unroll
+                            for (int jj = 0; jj < JT; ++jj)
+                                G[jj] = green_next<HASY, TABLE>(A.K, g, (float)(A.j_lo + jb0 + jj), 1.f, s_tab, P);
+                        }
+#pragma unroll
+                        for (int jj = 0; jj < JT; ++jj)
+                            B[jj] = u ? make_float2(B[jj].x + G[jj].x, B[jj].y + G[jj].y) : G[jj];
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < JT; ++jj) {
+                        const uint32_t h = pack_bf16(B[jj].x, B[jj].y);
+                        s_Bh[jj][s * BPS + ne] = h;
+                        s_Bl[jj][s * BPS + ne] = pack_bf16(B[jj].x - bf16_lo(h), B[jj].y - bf16_hi(h));
+                    }
+                }
+            } else {
 #pragma unroll 1
             for (int k = 0; k < PPT; ++k) {
                 const int s = sh * PPT + k;
@@ -1081,6 +1172,7 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                         s_Bl[jj][s * BPS + e] = l;
                     }
                 }
+            }
             }
             // the rest of the wave's split weights, per chunk
 #pragma unroll
