@@ -855,44 +855,33 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                 }
             } else {
 #pragma unroll 1
-            for (int k = 0; k < PPT; ++k) {
-                const int s = sh * PPT + k;
-                const float4 v = s_sc[par][s];
-                Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
-                if (!active) g.E = make_float2(0.f, 0.f);
-                if (TABLE) g.kap *= P.kscale;                 // delta_fetch's argument
-                float2 G[JT];
-                if constexpr (TABLE) {
-                    DeltaFetch fch[JT];
+                for (int k = 0; k < PPT; ++k) {
+                    const int s = sh * PPT + k;
+                    const float4 v = s_sc[par][s];
+                    Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+                    if (!active) g.E = make_float2(0.f, 0.f);
+                    if (TABLE) g.kap *= P.kscale;                 // delta_fetch's argument
+                    float2 G[JT];
+                    if constexpr (TABLE) {
+                        DeltaFetch fch[JT];
 #pragma unroll
-                    for (int jj = 0; jj < JT; ++jj) fch[jj] = delta_fetch(s_tab, P, (float)(A.j_lo + jb0 + jj) * g.kap);
+                        for (int jj = 0; jj < JT; ++jj) fch[jj] = delta_fetch(s_tab, P, (float)(A.j_lo + jb0 + jj) * g.kap);
 #pragma unroll
-                    for (int jj = 0; jj < JT; ++jj) G[jj] = green_next_fetched(g, fch[jj]);
-                } else {
-#pragma unroll
-                    for (int jj = 0; jj < JT; ++jj)
-                        G[jj] = green_next<HASY, TABLE>(A.K, g, (float)(A.j_lo + jb0 + jj), 1.f, s_tab, P);
-                }
-                const int e = NUV == 2 ? (n >> 1) : n;
-#pragma unroll
-                for (int jj = 0; jj < JT; ++jj) {
-                    float bx = G[jj].x, by = G[jj].y;
-                    if (NUV == 2) {
-                        bx += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bx), 0xB1, 0xF, 0xF, true));
-                        by += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(by), 0xB1, 0xF, 0xF, true));
-                    }
-                    const uint32_t h = pack_bf16(bx, by);
-                    const uint32_t l = pack_bf16(bx - bf16_lo(h), by - bf16_hi(h));
-                    if (NUV == 2) {
-                        // the pair's even lane stores the high part, the odd one the low part
-                        uint32_t* plane = (n & 1) ? s_Bl[jj] : s_Bh[jj];
-                        plane[s * BPS + e] = (n & 1) ? l : h;
+                        for (int jj = 0; jj < JT; ++jj) G[jj] = green_next_fetched(g, fch[jj]);
                     } else {
+#pragma unroll
+                        for (int jj = 0; jj < JT; ++jj)
+                            G[jj] = green_next<HASY, TABLE>(A.K, g, (float)(A.j_lo + jb0 + jj), 1.f, s_tab, P);
+                    }
+                    const int e = n;
+#pragma unroll
+                    for (int jj = 0; jj < JT; ++jj) {
+                        const float bx = G[jj].x, by = G[jj].y;
+                        const uint32_t h = pack_bf16(bx, by);
                         s_Bh[jj][s * BPS + e] = h;
-                        s_Bl[jj][s * BPS + e] = l;
+                        s_Bl[jj][s * BPS + e] = pack_bf16(bx - bf16_lo(h), by - bf16_hi(h));
                     }
                 }
-            }
             }
             // the rest of the wave's split weights, per chunk
 #pragma unroll
@@ -1136,43 +1125,33 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                 }
             } else {
 #pragma unroll 1
-            for (int k = 0; k < PPT; ++k) {
-                const int s = sh * PPT + k;
-                const float4 v = s_sc[par][s];
-                Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
-                if (!active) g.E = make_float2(0.f, 0.f);
-                if (TABLE) g.kap *= P.kscale;                 // delta_fetch's argument
-                float2 G[JT];
-                if constexpr (TABLE) {
-                    DeltaFetch fch[JT];
+                for (int k = 0; k < PPT; ++k) {
+                    const int s = sh * PPT + k;
+                    const float4 v = s_sc[par][s];
+                    Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
+                    if (!active) g.E = make_float2(0.f, 0.f);
+                    if (TABLE) g.kap *= P.kscale;                 // delta_fetch's argument
+                    float2 G[JT];
+                    if constexpr (TABLE) {
+                        DeltaFetch fch[JT];
 #pragma unroll
-                    for (int jj = 0; jj < JT; ++jj) fch[jj] = delta_fetch(s_tab, P, (float)(A.j_lo + jb0 + jj) * g.kap);
+                        for (int jj = 0; jj < JT; ++jj) fch[jj] = delta_fetch(s_tab, P, (float)(A.j_lo + jb0 + jj) * g.kap);
 #pragma unroll
-                    for (int jj = 0; jj < JT; ++jj) G[jj] = green_next_fetched(g, fch[jj]);
-                } else {
-#pragma unroll
-                    for (int jj = 0; jj < JT; ++jj)
-                        G[jj] = green_next<HASY, TABLE>(A.K, g, (float)(A.j_lo + jb0 + jj), 1.f, s_tab, P);
-                }
-                const int e = NUV == 2 ? (n >> 1) : n;
-#pragma unroll
-                for (int jj = 0; jj < JT; ++jj) {
-                    float bx = G[jj].x, by = G[jj].y;
-                    if (NUV == 2) {
-                        bx += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bx), 0xB1, 0xF, 0xF, true));
-                        by += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(by), 0xB1, 0xF, 0xF, true));
-                    }
-                    const uint32_t h = pack_bf16(bx, by);
-                    const uint32_t l = pack_bf16(bx - bf16_lo(h), by - bf16_hi(h));
-                    if (NUV == 2) {
-                        uint32_t* plane = (n & 1) ? s_Bl[jj] : s_Bh[jj];
-                        plane[s * BPS + e] = (n & 1) ? l : h;
+                        for (int jj = 0; jj < JT; ++jj) G[jj] = green_next_fetched(g, fch[jj]);
                     } else {
+#pragma unroll
+                        for (int jj = 0; jj < JT; ++jj)
+                            G[jj] = green_next<HASY, TABLE>(A.K, g, (float)(A.j_lo + jb0 + jj), 1.f, s_tab, P);
+                    }
+                    const int e = n;
+#pragma unroll
+                    for (int jj = 0; jj < JT; ++jj) {
+                        const float bx = G[jj].x, by = G[jj].y;
+                        const uint32_t h = pack_bf16(bx, by);
                         s_Bh[jj][s * BPS + e] = h;
-                        s_Bl[jj][s * BPS + e] = l;
+                        s_Bl[jj][s * BPS + e] = pack_bf16(bx - bf16_lo(h), by - bf16_hi(h));
                     }
                 }
-            }
             }
             // the rest of the wave's split weights, per chunk
 #pragma unroll
