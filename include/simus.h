@@ -150,11 +150,13 @@ typedef struct {
                                         32 transmits where they pad no more) instead of the
                                         default split-bf16 ones (every eight bins over groups
                                         of 16 up to 16 transmits, every four bins over groups
-                                        of 32 above).  Vector path: single transmits instead
-                                        of pairs, or pairs instead of single transmits.  The
-                                        autotuner tries it.  simus_rf_backward: the other of
-                                        its two kernels (matrix-core or vector) where both
-                                        apply.  The results agree to rounding order */
+                                        of 32 above, or of 64 for 64 or fewer elements and
+                                        more than 32 transmits).  Vector path: single
+                                        transmits instead of pairs, or pairs instead of
+                                        single transmits.  The autotuner tries it.
+                                        simus_rf_backward: the other of its two kernels
+                                        (matrix-core or vector) where both apply.  The
+                                        results agree to rounding order */
 #define SIMUS_FLAG_FP32_PRODUCTS 64  /* matrix-core path, default shape: the two
                                         contractions with FP32 matrix-core products (eight
                                         bins per set-up over groups of 16 transmit columns)
