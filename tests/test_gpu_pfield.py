@@ -91,3 +91,21 @@ def test_pfield_empty_and_single_point(S, orc):
     e1 = rel_l2(got.cpu().numpy(), ref)
     print("single point rel L2", e1)
     assert e1 <= TOL
+
+
+@pytest.mark.parametrize("nf", [20, 47, 100])
+def test_pfield_tile_shapes(S, orc, nf):
+    """Frequency counts whose tiles are shorter than the unrolled ones (20,
+    100: tiles of 20 bins) or exactly 23 and 24 bins long (47), on the
+    table path: the same sum as the FP64 oracle (Eqs. 41-42)."""
+    import torch
+    w, dl, X, Y, Z = _case("linear_pw10")
+    apod = np.ones(w["probe"]["n_elements"], np.float32)
+    su = oracle_setup(orc, w)
+    dX, dZ = to_dev(X, Z)
+    got = S.pfield(w["probe"], w["medium"], w["options"], nf, dl, apod, dX, None, dZ)
+    torch.cuda.synchronize()
+    ref = orc.pfield(su, dl, apod, nf, X, np.zeros_like(X), Z)
+    e = rel_l2(got.cpu().numpy(), ref)
+    print("nf", nf, "rel L2", e)
+    assert e <= TOL
