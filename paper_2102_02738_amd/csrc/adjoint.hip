@@ -63,7 +63,48 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs A)
 #pragma unroll
                     for (int i = 0; i < NX; ++i) da[jj][t][i] = db[jj][t][i] = make_float2(0.f, 0.f);
                 }
-            for (int n = 0; n < A.M; ++n) {
+            // With the table (y = 0), a full tile (JT bins, TT transmits) runs
+            // as one straight-line bin loop, with no branch per bin and
+            // transmit: the compiler can then issue later bins' table reads
+            // and weight loads early (one transmit, 5 plane waves' scatterers:
+            // 54.3 -> 52.9 ms).  Without the table it would take 22 more
+            // registers and a wave less per SIMD.  The loop below serves the
+            // rest.
+            auto tile_full = [&](auto) {
+                for (int n = 0; n < A.M; ++n) {
+                    const SubFrame fr = load_frame(A.sub, n);
+                    const int e = n / A.nu;
+                    GeoD D;
+                    Geo g = make_geo<HASY>(A.K, fr, px, py, pz, A.j_lo + jb0, &D);
+                    if (!live) g.E = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int jj = 0; jj < JT; ++jj) {
+                        const int jb = jb0 + jj;
+                        const float jf = (float)(A.j_lo + jb);
+                        float2 dG[NX];
+                        const float2 G = green_grad_next<HASY, TABLE, NX>(A.K, g, D, jf, rcp_fast(jf),
+                                                                          s_tab, P, dG);
+#pragma unroll
+                        for (int t = 0; t < TT; ++t) {
+                            const float2 W = A.W[((int64_t)jb * A.n_tx + t0 + t) * A.N + e];
+                            const float2 L =
+                                A.lam[(((int64_t)p * A.n_bins + jb) * A.n_tx + t0 + t) * A.N + e];
+                            a[jj][t] = cfma(W, G, a[jj][t]);
+                            b[jj][t] = cfma(L, G, b[jj][t]);
+#pragma unroll
+                            for (int i = 0; i < NX; ++i) {
+                                da[jj][t][i] = cfma(W, dG[i], da[jj][t][i]);
+                                db[jj][t][i] = cfma(L, dG[i], db[jj][t][i]);
+                            }
+                        }
+                    }
+                }
+            };
+            const bool full = TABLE && !HASY && jb0 + JT <= b_end && t0 + TT <= A.n_tx;
+            if constexpr (TABLE && !HASY) {
+                if (full) tile_full(0);
+            }
+            for (int n = 0; !full && n < A.M; ++n) {
                 const SubFrame fr = load_frame(A.sub, n);
                 const int e = n / A.nu;
                 GeoD D;
