@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs A)
             // and weight loads early (one transmit, 5 plane waves' scatterers:
             // 54.3 -> 52.9 ms).  Without the table it would take 22 more
             // registers and a wave less per SIMD.  The loop below serves the
-            // rest.
+            // rest.  (A generic lambda: its body is compiled only where the
+            // table branch calls it.)
             auto tile_full = [&](auto) {
                 for (int n = 0; n < A.M; ++n) {
                     const SubFrame fr = load_frame(A.sub, n);
