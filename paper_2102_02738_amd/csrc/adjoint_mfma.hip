@@ -417,6 +417,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mq(AdjArgs A)
                 // issued ahead (5 plane waves, 100k scatterers: 82.0 -> 78.3 ms)
 #pragma unroll
                 for (int jj = 0; jj < JB; ++jj) {
+                    prio_by_progress(jj, JB);
                     const float jf = (float)(A.j_lo + jb0 + jq + jj);
                     const float inv_j = rcp_fast(jf);
 #pragma unroll

@@ -481,6 +481,7 @@ __global__ __launch_bounds__(512) void k_synth_mq(SynthArgs A)
                 }
 #pragma unroll 1
                 for (int jj = 0; jj < JT; ++jj) {
+                    prio_by_progress(jj, JT);
                     const float jf = (float)(A.j_lo + jb0 + jj);
                     float2 G[PPT];
                     if constexpr (TABLE) {
@@ -513,6 +514,7 @@ __global__ __launch_bounds__(512) void k_synth_mq(SynthArgs A)
                     }
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             // the first batch of weights, in flight across the barrier
             float2 wa[2][KB];
 #pragma unroll
@@ -822,6 +824,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                 constexpr int PPS = SCH * NE / NB;   // scatterers per thread
 #pragma unroll 1
                 for (int k = 0; k < PPS; ++k) {
+                    prio_by_progress(k, PPS);
                     const int s = sge * PPS + k;
                     const float4 v = s_sc[par][s];
                     float2 B[JT];
@@ -856,6 +859,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
             } else {
 #pragma unroll 1
                 for (int k = 0; k < PPT; ++k) {
+                    prio_by_progress(k, PPT);
                     const int s = sh * PPT + k;
                     const float4 v = s_sc[par][s];
                     Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
@@ -883,6 +887,9 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                     }
                 }
             }
+            // the GEMM phase: a wave in the transmit GEMM issues before one
+            // already in the receive GEMM
+            __builtin_amdgcn_s_setprio(3);
             // the rest of the wave's split weights, per chunk
 #pragma unroll
             for (int k = KH; k < KS; ++k) {
@@ -928,6 +935,7 @@ __global__ __launch_bounds__(512) void k_synth_mb(SynthArgs A)
                     cl[v] = pack_bf16(cx - bf16_lo(ch[v]), cy - bf16_hi(ch[v]));
                 }
             }
+            __builtin_amdgcn_s_setprio(2);
             // ---- P3: receive GEMM of bin bw: rows e, columns t = gi,
             //      k = (scatterer 4 gk + q, Re/Im); the next chunk's scatterers
             {
@@ -1092,6 +1100,7 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                 constexpr int PPS = SCH * NE / NB;   // scatterers per thread
 #pragma unroll 1
                 for (int k = 0; k < PPS; ++k) {
+                    prio_by_progress(k, PPS);
                     const int s = sge * PPS + k;
                     const float4 v = s_sc[par][s];
                     float2 B[JT];
@@ -1126,6 +1135,7 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
             } else {
 #pragma unroll 1
                 for (int k = 0; k < PPT; ++k) {
+                    prio_by_progress(k, PPT);
                     const int s = sh * PPT + k;
                     const float4 v = s_sc[par][s];
                     Geo g = make_geo<HASY, true>(A.K, fr, v.x, v.y, v.z, A.j_lo + jb0);
@@ -1153,6 +1163,9 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                     }
                 }
             }
+            // the GEMM phase: a wave in the transmit GEMM issues before one
+            // already in the receive GEMM
+            __builtin_amdgcn_s_setprio(3);
             // the rest of the wave's split weights, per chunk
 #pragma unroll
             for (int ct = 0; ct < CPW; ++ct)
@@ -1202,6 +1215,7 @@ __global__ __launch_bounds__(512) void k_synth_mw(SynthArgs A)
                     cl[ct][v] = pack_bf16(cx - bf16_lo(ch[ct][v]), cy - bf16_hi(ch[ct][v]));
                 }
             }
+            __builtin_amdgcn_s_setprio(2);
             // ---- P3: receive GEMM of bin wj, the wave's column tiles, all
             //      element tiles, k = (scatterer 4 gk + q, Re/Im); the next
             //      chunk's scatterers
